@@ -1,0 +1,251 @@
+/*
+ * hinqs.h -- C ABI of the MI355X (gfx950) selected-CI subspace solver.
+ *
+ * The library builds the second-quantized Hamiltonian
+ *     H = E_core + sum_pq h_pq a+_p a_q + 1/2 sum_pqrs g_pqrs a+_p a+_q a_s a_r
+ * (paper Sec. 2.2, the Hamiltonian stated before Step 1; E_core is the
+ * constant the paper calls E_nuc) restricted to a sampled determinant set B,
+ * [H_B]_ij = <x_i|H|x_j> (Sec. 2.2, Step 3), applies it to blocks of vectors
+ * and finds its lowest eigenpair with a Davidson eigensolver (Step 3), which
+ * yields E_0 and Psi_0 as a linear combination of the determinants of B.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - A determinant is a pair of occupation strings (alpha, beta), each a
+ *   uint64 whose bit p is set when spatial orbital p is occupied with that
+ *   spin (Sec. 2.1: x = (sigma_alpha, sigma_beta)).  norb <= 32.
+ * - Fermionic sign gauge: |x> = prod_{P occupied, ascending} a+_P |vac>, with
+ *   the alpha spin-orbitals 0..norb-1 ordered before the beta ones.
+ * - Two-electron integrals are passed in chemists' notation (pq|rs), i.e.
+ *   g_pqrs of the Hamiltonian above equals (pr|qs).
+ * - Vectors indexed by determinant follow the caller's order of
+ *   hinqs_set_determinants unless HINQS_SORTED_ORDER is given.  Blocks of k
+ *   vectors are ndet x k row-major (the k values of one determinant are
+ *   contiguous).
+ * - Every call is issued on the stream given to hinqs_create.  Device
+ *   pointers must be valid on the context's device.  Calls that return
+ *   host results (energies, statistics) synchronize that stream.
+ * - Status: 0 on success, a negative HINQS_E_* code otherwise; the message
+ *   of the last failure is available from hinqs_last_error.  A context is
+ *   not thread-safe; concurrent calls on one context are undefined.
+ */
+#ifndef HINQS_H
+#define HINQS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define HINQS_OK                   0
+#define HINQS_E_INVALID_ARG       -1   /* bad pointer, size or option */
+#define HINQS_E_NOT_READY         -2   /* integrals or determinants not set */
+#define HINQS_E_ASYMMETRIC        -3   /* h or (pq|rs) lack real-orbital symmetry */
+#define HINQS_E_BAD_OCCUPATION    -4   /* wrong electron count or bits >= norb */
+#define HINQS_E_DUPLICATE         -5   /* a determinant appears twice */
+#define HINQS_E_UNSUPPORTED       -6   /* norb > 32, unsupported block size */
+#define HINQS_E_NOT_CONVERGED     -7   /* outputs hold the best estimate */
+#define HINQS_E_NONFINITE         -8   /* NaN or Inf in the inputs */
+#define HINQS_E_OOM               -9   /* device allocation failed */
+#define HINQS_E_HIP              -10   /* a HIP runtime call failed */
+
+/* arithmetic of sigma products */
+#define HINQS_FP64   0
+#define HINQS_FP32   1
+/* Davidson precision modes */
+#define HINQS_SOLVE_FP64   0   /* every sigma product in FP64 */
+#define HINQS_SOLVE_MIXED  1   /* FP32 sigma until the residual stalls, then FP64 refinement */
+
+/* flags */
+#define HINQS_SORTED_ORDER 1   /* vectors are in the library's internal sorted order */
+
+/* excitation classes stored in a coupling descriptor (bits 0..2) */
+#define HINQS_EXC_1A   1   /* single, alpha */
+#define HINQS_EXC_1B   2   /* single, beta */
+#define HINQS_EXC_2AA  3   /* double, both alpha */
+#define HINQS_EXC_2BB  4   /* double, both beta */
+#define HINQS_EXC_2AB  5   /* double, one alpha and one beta */
+
+typedef struct hinqs_ctx hinqs_ctx;
+
+typedef struct hinqs_opts {
+    int    block;          /* Davidson block size k in {1,2,4,8,16}; default 8 */
+    int    max_space;      /* largest subspace before a thick restart; default 4*block */
+    int    max_iter;       /* iteration cap; default 200 */
+    double tol;            /* stop when ||H c - E c||_2 <= tol for the lowest root; default 1e-8 */
+    int    precision;      /* HINQS_SOLVE_FP64 or HINQS_SOLVE_MIXED; default FP64 */
+    double precond_floor;  /* |theta - H_ii| is clamped below at this value; default 1e-8 */
+    double mixed_switch;   /* MIXED: switch to FP64 once the residual is below this; default 1e-5 */
+    int    flags;          /* HINQS_SORTED_ORDER for guess and coeffs */
+} hinqs_opts;
+
+typedef struct hinqs_stats {
+    int    iterations;         /* Davidson iterations (all precisions) */
+    int    iterations_fp32;    /* of which with FP32 sigma products */
+    int    sigma_blocks;       /* block sigma products applied */
+    int    restarts;
+    double residual;           /* final ||r||_2 of the lowest root */
+    double ms_total;           /* wall time of the call */
+    double ms_sigma;           /* time inside sigma kernels (HIP events) */
+    int64_t nnz;               /* stored off-diagonal couplings */
+} hinqs_stats;
+
+typedef struct hinqs_info {
+    int     norb, nalpha, nbeta;
+    int64_t ndet;
+    int64_t nnz;               /* off-diagonal couplings stored in the sparse H_B */
+    int32_t n_alpha_strings;   /* distinct alpha strings in B */
+    int32_t n_beta_strings;    /* distinct beta strings in B */
+    int64_t device_bytes;      /* device memory held by the context */
+    double  ms_sort;           /* last set_determinants: sort + string tables */
+    double  ms_connect;        /* last set_determinants: coupling enumeration */
+    double  ms_elements;       /* last element build (Slater-Condon) */
+} hinqs_info;
+
+/* Fill *opts with the defaults listed above. */
+void hinqs_opts_default(hinqs_opts *opts);
+
+/*
+ * Create a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the handle.
+ * Errors: INVALID_ARG, HIP.
+ */
+int hinqs_create(hinqs_ctx **out, int device, void *hip_stream);
+
+/* Release every device buffer of the context.  NULL is ignored. */
+void hinqs_destroy(hinqs_ctx *ctx);
+
+/* Message of the last failure on ctx ("" if none); valid until the next call. */
+const char *hinqs_last_error(const hinqs_ctx *ctx);
+
+/*
+ * Load the Hamiltonian of Sec. 2.2.
+ *   h      host, norb*norb doubles, row-major, symmetric (|h_pq - h_qp| <= 1e-12 max|h|)
+ *   eri    host, norb^4 doubles, row-major chemists' (pq|rs), 8-fold symmetric
+ *          (real orbitals) to 1e-12 of its largest magnitude
+ *   e_core constant energy (nuclear repulsion / frozen core), added on the diagonal
+ * The inputs are copied; the caller may free them on return.  If determinants
+ * are already set, the matrix elements are rebuilt (couplings are kept).
+ * Errors: INVALID_ARG (norb < 1), UNSUPPORTED (norb > 32), NONFINITE,
+ * ASYMMETRIC, OOM, HIP.  norb must equal that of the determinants if set.
+ */
+int hinqs_set_integrals(hinqs_ctx *ctx, int norb, const double *h, const double *eri,
+                        double e_core);
+
+/*
+ * Load the determinant set B (Sec. 2.2, Steps 1-3: the sampled basis).
+ *   alpha, beta  host, ndet uint64 strings each, any order (the caller order)
+ *   nalpha, nbeta electrons per spin; every string must have exactly that many
+ *                 bits set, all below norb
+ * The library sorts B, builds its string tables and enumerates every coupled
+ * pair (excitation degree 1 or 2) with its fermionic sign; if integrals are
+ * set it also evaluates the matrix elements.  Requires hinqs_set_integrals
+ * first (for norb).  Inputs are copied.
+ * Errors: NOT_READY (no integrals), INVALID_ARG (ndet < 1, nalpha/nbeta out of
+ * range), BAD_OCCUPATION, DUPLICATE, OOM, HIP.
+ */
+int hinqs_set_determinants(hinqs_ctx *ctx, int64_t ndet, const uint64_t *alpha,
+                           const uint64_t *beta, int nalpha, int nbeta);
+
+/*
+ * Block sigma product S = H_B X (the repeated operation of the Davidson
+ * iteration of Step 3).
+ *   k          number of vectors, 1 <= k <= 16
+ *   X          device, ndet x k row-major, doubles (FP64) or floats (FP32)
+ *   S          device, same shape and type; must not overlap X
+ *   precision  HINQS_FP64 or HINQS_FP32 (FP32 values, vectors and sums)
+ *   flags      HINQS_SORTED_ORDER: X and S are in internal sorted order
+ * Errors: NOT_READY, INVALID_ARG, UNSUPPORTED, HIP.
+ */
+int hinqs_sigma(hinqs_ctx *ctx, int k, const void *X, void *S, int precision, int flags);
+
+/*
+ * Lowest eigenpair of H_B by block Davidson (Step 3, warm-startable as the
+ * paper's incremental backend is).
+ *   opts    NULL for defaults
+ *   guess   device, ndet doubles or NULL; used as the first trial vector
+ *   energy  host, receives E_0 (including e_core)
+ *   coeffs  device, ndet doubles, receives Psi_0 normalized to 1 with its
+ *           largest-magnitude component positive
+ *   stats   host or NULL
+ * Errors: NOT_READY, INVALID_ARG, NOT_CONVERGED (energy/coeffs hold the last
+ * Ritz pair), OOM, HIP.
+ */
+int hinqs_lowest_eigenpair(hinqs_ctx *ctx, const hinqs_opts *opts, const double *guess,
+                           double *energy, double *coeffs, hinqs_stats *stats);
+
+/*
+ * One- and two-particle density matrices of the vector c (not renormalized):
+ *   rdm1[p,q]     = sum_s   <c| a+_{p s} a_{q s} |c>                (device, norb^2)
+ *   rdm2[p,q,r,s] = sum_st  <c| a+_{p s} a+_{r t} a_{s t} a_{q s} |c> (device, norb^4)
+ * so that E = e_core + sum h rdm1 + 1/2 sum (pq|rs) rdm2 for a normalized
+ * eigenvector.  These are the derivatives of the energy with respect to the
+ * integrals (Hellmann-Feynman), the gradient signal behind the autograd
+ * binding.  Accumulation uses floating-point atomics, so results are
+ * reproducible to rounding only.
+ * Errors: NOT_READY, INVALID_ARG, OOM, HIP.
+ */
+int hinqs_rdm12(hinqs_ctx *ctx, const double *coeffs, double *rdm1, double *rdm2, int flags);
+
+/*
+ * Energy gradient with respect to symmetric integrals for a normalized
+ * eigenvector c:  grad_h = scale * (rdm1 + rdm1^T)/2 and
+ * grad_eri = scale * 1/2 * (average of rdm2 over the 8 index permutations of
+ * real-orbital symmetry).  A perturbation that keeps the integrals symmetric
+ * changes E by sum(grad_h * dh) + sum(grad_eri * deri) to first order.
+ *   grad_h   device, norb^2;  grad_eri device, norb^4
+ * Errors: as hinqs_rdm12.
+ */
+int hinqs_integral_grad(hinqs_ctx *ctx, const double *coeffs, double scale, double *grad_h,
+                        double *grad_eri, int flags);
+
+/* Diagonal H_ii (device, ndet doubles). */
+int hinqs_diag(hinqs_ctx *ctx, double *diag, int flags);
+
+/*
+ * Export the couplings in caller order: for caller row i, entries
+ * rowptr[i]..rowptr[i+1]-1 of col (caller index j) and desc.  Pass NULL for
+ * col/desc to only fill rowptr (device, ndet+1 int64).  col (int32) and desc
+ * (uint32) are device arrays of nnz entries; entries within a row are in an
+ * unspecified order.  desc layout: bits 0-2 excitation class (HINQS_EXC_*),
+ * bit 3 sign (1 = negative), bits 4-8 h1, 9-13 h2, 14-18 p1, 19-23 p2
+ * (spatial orbitals; holes are occupied in x_j, particles in x_i; same-spin
+ * doubles have h1<h2 and p1<p2; for HINQS_EXC_2AB h1/p1 are alpha and h2/p2
+ * beta; singles leave h2 = p2 = 0).  The sign is that of the operator string
+ * a+_p a_h (single), a+_p1 a+_p2 a_h2 a_h1 (double) applied to |x_j>.
+ */
+int hinqs_connectivity(hinqs_ctx *ctx, int64_t *rowptr, int32_t *col, uint32_t *desc);
+
+/* Sorted position -> caller index (device, ndet int32). */
+int hinqs_permutation(hinqs_ctx *ctx, int32_t *perm);
+
+/*
+ * Tall-skinny Gram product G = A^T B, the Rayleigh-Ritz projection kernel of
+ * the Davidson solver (FP64 matrix cores, fixed-order reduction):
+ *   A  device, nrows x ma row-major with leading dimension lda >= ma
+ *   B  device, nrows x nb row-major with leading dimension ldb >= nb
+ *   G  device, ma x nb row-major
+ * Needs no integrals or determinants.  ma <= 96, nb <= 16.
+ * Errors: INVALID_ARG, UNSUPPORTED, OOM, HIP.
+ */
+int hinqs_gram(hinqs_ctx *ctx, int64_t nrows, const double *A, int lda, int ma, const double *B,
+               int ldb, int nb, double *G);
+
+/* Sizes and timings of the current state. */
+int hinqs_get_info(hinqs_ctx *ctx, hinqs_info *info);
+
+/*
+ * Host-only helper (no device work): descriptor of the pair x_i <- x_j as
+ * the coupling enumerator encodes it, or 0 if the pair differs by more than
+ * two electrons or not at all.  Used to check the sign rules on the CPU.
+ */
+uint32_t hinqs_pair_descriptor(uint64_t alpha_i, uint64_t beta_i, uint64_t alpha_j,
+                               uint64_t beta_j);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HINQS_H */

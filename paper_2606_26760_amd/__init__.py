@@ -1,0 +1,358 @@
+"""Python binding of ``libhinqs.so``, the gfx950 selected-CI subspace solver.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library (see ``include/hinqs.h``).  PyTorch supplies device
+memory and the stream; the library is loaded from this directory and the
+binding raises if it is missing -- there is no fallback path.
+
+    solver = Hinqs()                               # cuda:0, current stream
+    solver.set_integrals(h, eri, e_core)           # Sec. 2.2 Hamiltonian
+    solver.set_determinants(alpha, beta, na, nb)   # sampled basis B
+    S = solver.sigma(X)                            # S = H_B X
+    E, c, stats = solver.lowest_eigenpair()        # Step 3 Davidson
+    rdm1, rdm2 = solver.rdm12(c)
+    E = HinqsEnergy.apply(h_t, eri_t, solver)      # differentiable in h, eri
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhinqs.so")
+
+HINQS_OK = 0
+HINQS_E = {
+    -1: "INVALID_ARG", -2: "NOT_READY", -3: "ASYMMETRIC", -4: "BAD_OCCUPATION",
+    -5: "DUPLICATE", -6: "UNSUPPORTED", -7: "NOT_CONVERGED", -8: "NONFINITE", -9: "OOM",
+    -10: "HIP",
+}
+HINQS_FP64, HINQS_FP32 = 0, 1
+SOLVE_FP64, SOLVE_MIXED = 0, 1
+SORTED_ORDER = 1
+EXC_1A, EXC_1B, EXC_2AA, EXC_2BB, EXC_2AB = 1, 2, 3, 4, 5
+
+EXPORTED = ["hinqs_opts_default", "hinqs_create", "hinqs_destroy", "hinqs_last_error",
+            "hinqs_set_integrals", "hinqs_set_determinants", "hinqs_sigma",
+            "hinqs_lowest_eigenpair", "hinqs_rdm12", "hinqs_integral_grad", "hinqs_diag",
+            "hinqs_connectivity", "hinqs_permutation", "hinqs_get_info",
+            "hinqs_pair_descriptor", "hinqs_gram"]
+
+
+class HinqsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{HINQS_E.get(code, code)}: {msg}")
+        self.code = code
+        self.name = HINQS_E.get(code, str(code))
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int), ("max_space", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("tol", ctypes.c_double), ("precision", ctypes.c_int),
+                ("precond_floor", ctypes.c_double), ("mixed_switch", ctypes.c_double),
+                ("flags", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("iterations_fp32", ctypes.c_int),
+                ("sigma_blocks", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("residual", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("ms_sigma", ctypes.c_double), ("nnz", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("norb", ctypes.c_int), ("nalpha", ctypes.c_int), ("nbeta", ctypes.c_int),
+                ("ndet", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("n_alpha_strings", ctypes.c_int32), ("n_beta_strings", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64), ("ms_sort", ctypes.c_double),
+                ("ms_connect", ctypes.c_double), ("ms_elements", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load_library() -> ctypes.CDLL:
+    """Load ``libhinqs.so``; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2606_26760_amd.build` (no fallback exists)")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "hinqs_opts_default": (None, [P]),
+            "hinqs_create": (i32, [P, i32, P]),
+            "hinqs_destroy": (None, [P]),
+            "hinqs_last_error": (ctypes.c_char_p, [P]),
+            "hinqs_set_integrals": (i32, [P, i32, P, P, dbl]),
+            "hinqs_set_determinants": (i32, [P, i64, P, P, i32, i32]),
+            "hinqs_sigma": (i32, [P, i32, P, P, i32, i32]),
+            "hinqs_lowest_eigenpair": (i32, [P, P, P, P, P, P]),
+            "hinqs_rdm12": (i32, [P, P, P, P, i32]),
+            "hinqs_integral_grad": (i32, [P, P, dbl, P, P, i32]),
+            "hinqs_diag": (i32, [P, P, i32]),
+            "hinqs_connectivity": (i32, [P, P, P, P]),
+            "hinqs_permutation": (i32, [P, P]),
+            "hinqs_get_info": (i32, [P, P]),
+            "hinqs_pair_descriptor": (ctypes.c_uint32, [ctypes.c_uint64] * 4),
+            "hinqs_gram": (i32, [P, i64, P, i32, i32, P, i32, i32, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+        return lib
+
+
+def pair_descriptor(alpha_i: int, beta_i: int, alpha_j: int, beta_j: int) -> int:
+    """Descriptor the coupling enumerator stores for x_i <- x_j (host-only helper)."""
+    return int(load_library().hinqs_pair_descriptor(alpha_i, beta_i, alpha_j, beta_j))
+
+
+def decode_descriptor(d):
+    """(type, neg, h1, h2, p1, p2) arrays from descriptor values."""
+    d = np.asarray(d, dtype=np.uint32)
+    return (d & 7, (d >> 3) & 1, (d >> 4) & 31, (d >> 9) & 31, (d >> 14) & 31, (d >> 19) & 31)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _host_f64(a) -> np.ndarray:
+    t = _torch()
+    if isinstance(a, t.Tensor):
+        a = a.detach().to("cpu", t.float64).numpy()
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _host_u64(a) -> np.ndarray:
+    t = _torch()
+    if isinstance(a, t.Tensor):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(np.asarray(a).astype(np.uint64))
+
+
+class Hinqs:
+    """One solver context on one device and stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("Hinqs needs a ROCm GPU (gfx950); none is visible")
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self._lib = lib
+        h = ctypes.c_void_p()
+        rc = lib.hinqs_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if rc != HINQS_OK:
+            raise HinqsError(rc, "hinqs_create failed")
+        self._h = h
+        self.norb = self.na = self.nb = self.ndet = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hinqs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != HINQS_OK:
+            msg = self._lib.hinqs_last_error(self._h)
+            raise HinqsError(rc, msg.decode() if msg else "")
+
+    @staticmethod
+    def _ptr(t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _dev(self, t, dtype):
+        torch = _torch()
+        if not (isinstance(t, torch.Tensor) and t.device == self.device and t.dtype == dtype
+                and t.is_contiguous()):
+            raise ValueError(f"expected a contiguous {dtype} tensor on {self.device}")
+        return t
+
+    # ---------------------------------------------------------------- inputs
+    def set_integrals(self, h, eri, e_core: float = 0.0):
+        h = _host_f64(h)
+        eri = _host_f64(eri)
+        norb = h.shape[0]
+        if h.shape != (norb, norb) or eri.shape != (norb,) * 4:
+            raise ValueError("h must be (n, n) and eri (n, n, n, n)")
+        self._check(self._lib.hinqs_set_integrals(self._h, norb, h.ctypes.data_as(ctypes.c_void_p),
+                                                  eri.ctypes.data_as(ctypes.c_void_p),
+                                                  float(e_core)))
+        self.norb = norb
+
+    def set_determinants(self, alpha, beta, nalpha: int, nbeta: int):
+        a = _host_u64(alpha)
+        b = _host_u64(beta)
+        if a.shape != b.shape or a.ndim != 1:
+            raise ValueError("alpha and beta must be 1-D and equally long")
+        self._check(self._lib.hinqs_set_determinants(self._h, len(a), a.ctypes.data_as(ctypes.c_void_p),
+                                                     b.ctypes.data_as(ctypes.c_void_p), nalpha, nbeta))
+        self.na, self.nb, self.ndet = nalpha, nbeta, len(a)
+
+    # ------------------------------------------------------------- products
+    def sigma(self, X, out=None, sorted_order: bool = False):
+        torch = _torch()
+        squeeze = X.dim() == 1
+        if squeeze:
+            X = X.unsqueeze(1)
+        prec = HINQS_FP64 if X.dtype == torch.float64 else HINQS_FP32
+        self._dev(X, X.dtype)
+        if X.shape[0] != self.ndet:
+            raise ValueError("X must have ndet rows")
+        S = torch.empty_like(X) if out is None else self._dev(out, X.dtype)
+        self._check(self._lib.hinqs_sigma(self._h, X.shape[1], self._ptr(X), self._ptr(S), prec,
+                                          SORTED_ORDER if sorted_order else 0))
+        return S.squeeze(1) if squeeze else S
+
+    def lowest_eigenpair(self, guess=None, *, block=8, max_space=None, max_iter=200, tol=1e-8,
+                         mixed=False, precond_floor=1e-8, mixed_switch=1e-5, sorted_order=False,
+                         raise_on_not_converged=True):
+        torch = _torch()
+        o = Opts()
+        self._lib.hinqs_opts_default(ctypes.byref(o))
+        o.block = block
+        o.max_space = max_space if max_space is not None else 4 * block
+        o.max_iter = max_iter
+        o.tol = tol
+        o.precision = SOLVE_MIXED if mixed else SOLVE_FP64
+        o.precond_floor = precond_floor
+        o.mixed_switch = mixed_switch
+        o.flags = SORTED_ORDER if sorted_order else 0
+        c = torch.empty(self.ndet, dtype=torch.float64, device=self.device)
+        e = ctypes.c_double(0.0)
+        st = Stats()
+        gp = None
+        if guess is not None:
+            gp = self._ptr(self._dev(guess, torch.float64))
+        rc = self._lib.hinqs_lowest_eigenpair(self._h, ctypes.byref(o), gp, ctypes.byref(e),
+                                              self._ptr(c), ctypes.byref(st))
+        if rc == -7 and not raise_on_not_converged:
+            return e.value, c, dict(st.as_dict(), converged=False)
+        self._check(rc)
+        return e.value, c, dict(st.as_dict(), converged=True)
+
+    def rdm12(self, c, sorted_order=False):
+        torch = _torch()
+        self._dev(c, torch.float64)
+        n = self.norb
+        d1 = torch.empty((n, n), dtype=torch.float64, device=self.device)
+        d2 = torch.empty((n, n, n, n), dtype=torch.float64, device=self.device)
+        self._check(self._lib.hinqs_rdm12(self._h, self._ptr(c), self._ptr(d1), self._ptr(d2),
+                                          SORTED_ORDER if sorted_order else 0))
+        return d1, d2
+
+    def integral_grad(self, c, scale=1.0, sorted_order=False):
+        torch = _torch()
+        self._dev(c, torch.float64)
+        n = self.norb
+        gh = torch.empty((n, n), dtype=torch.float64, device=self.device)
+        ge = torch.empty((n, n, n, n), dtype=torch.float64, device=self.device)
+        self._check(self._lib.hinqs_integral_grad(self._h, self._ptr(c), float(scale), self._ptr(gh),
+                                                  self._ptr(ge), SORTED_ORDER if sorted_order else 0))
+        return gh, ge
+
+    # -------------------------------------------------------------- exports
+    def diag(self, sorted_order=False):
+        torch = _torch()
+        d = torch.empty(self.ndet, dtype=torch.float64, device=self.device)
+        self._check(self._lib.hinqs_diag(self._h, self._ptr(d), SORTED_ORDER if sorted_order else 0))
+        return d
+
+    def connectivity(self):
+        """(rowptr, col, desc) in caller order, as device tensors."""
+        torch = _torch()
+        rowptr = torch.empty(self.ndet + 1, dtype=torch.int64, device=self.device)
+        self._check(self._lib.hinqs_connectivity(self._h, self._ptr(rowptr), None, None))
+        nnz = int(rowptr[-1].item())
+        col = torch.empty(max(nnz, 1), dtype=torch.int32, device=self.device)
+        desc = torch.empty(max(nnz, 1), dtype=torch.int32, device=self.device)
+        self._check(self._lib.hinqs_connectivity(self._h, self._ptr(rowptr), self._ptr(col),
+                                                 self._ptr(desc)))
+        return rowptr, col[:nnz], desc[:nnz]
+
+    def permutation(self):
+        torch = _torch()
+        p = torch.empty(self.ndet, dtype=torch.int32, device=self.device)
+        self._check(self._lib.hinqs_permutation(self._h, self._ptr(p)))
+        return p
+
+    def gram(self, A, B):
+        """G = A^T B for device float64 tensors A (n x ma), B (n x nb) (row-major, contiguous)."""
+        torch = _torch()
+        self._dev(A, torch.float64)
+        self._dev(B, torch.float64)
+        n, ma = A.shape
+        nb = B.shape[1]
+        G = torch.empty((ma, nb), dtype=torch.float64, device=self.device)
+        self._check(self._lib.hinqs_gram(self._h, n, self._ptr(A), ma, ma, self._ptr(B), nb, nb,
+                                         self._ptr(G)))
+        return G
+
+    def info(self):
+        inf = Info()
+        self._check(self._lib.hinqs_get_info(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+
+def _make_energy_function():
+    torch = _torch()
+
+    class HinqsEnergy(torch.autograd.Function):
+        """E_0(h, eri) on a fixed determinant set; backward returns the
+        Hellmann-Feynman gradients (symmetrized 1- and 2-RDMs) from the
+        library's adjoint kernel."""
+
+        @staticmethod
+        def forward(ctx, h, eri, solver, e_core=0.0, tol=1e-10, guess=None):
+            solver.set_integrals(h, eri, e_core)
+            e, c, st = solver.lowest_eigenpair(guess=guess, tol=tol)
+            ctx.solver = solver
+            ctx.save_for_backward(c)
+            ctx.h_meta = (h.dtype, h.device)
+            ctx.e_meta = (eri.dtype, eri.device)
+            return torch.tensor(e, dtype=h.dtype, device=h.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (c,) = ctx.saved_tensors
+            gh, ge = ctx.solver.integral_grad(c, float(grad_out))
+            gh = gh.to(dtype=ctx.h_meta[0], device=ctx.h_meta[1])
+            ge = ge.to(dtype=ctx.e_meta[0], device=ctx.e_meta[1])
+            return gh, ge, None, None, None, None
+
+    return HinqsEnergy
+
+
+def __getattr__(name):
+    if name == "HinqsEnergy":
+        fn = _make_energy_function()
+        globals()["HinqsEnergy"] = fn
+        return fn
+    raise AttributeError(name)

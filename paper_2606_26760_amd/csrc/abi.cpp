@@ -1,0 +1,295 @@
+// extern "C" boundary of the library (declared in include/hinqs.h).
+// Each entry point validates its arguments on the host, converts internal
+// exceptions into status codes and records the message for hinqs_last_error.
+#include <chrono>
+#include <cmath>
+
+#include "common.hpp"
+
+using namespace hinqs;
+
+struct hinqs_ctx {
+    Ctx c;
+};
+
+namespace {
+
+template <typename F>
+int guarded(hinqs_ctx *ctx, F &&f) {
+    if (!ctx) return HINQS_E_INVALID_ARG;
+    ctx->c.err.clear();
+    try {
+        HQ_CHECK(hipSetDevice(ctx->c.device));
+        return f(ctx->c);
+    } catch (const Error &e) {
+        ctx->c.err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        ctx->c.err = "host allocation failed";
+        return HINQS_E_OOM;
+    } catch (const std::exception &e) {
+        ctx->c.err = e.what();
+        return HINQS_E_HIP;
+    }
+}
+
+void require_dets(const Ctx &c) {
+    if (!c.have_ints) throw Error(HINQS_E_NOT_READY, "integrals are not set");
+    if (!c.have_dets) throw Error(HINQS_E_NOT_READY, "determinants are not set");
+    if (!c.have_elements) throw Error(HINQS_E_NOT_READY, "matrix elements are not built");
+}
+
+}  // namespace
+
+size_t Ctx::device_bytes() const {
+    return d_h.bytes() + d_eri.bytes() + d_eri32.bytes() + sa.bytes() + sb.bytes() + perm.bytes() +
+           inv.bytes() + ua.bytes() + ub.bytes() + ga.bytes() + aidx.bytes() + bidx.bytes() +
+           gb.bytes() + bperm.bytes() + bm_alpha.bytes() + alink_ptr.bytes() + alink.bytes() +
+           alink_info.bytes() + rowptr.bytes() + col.bytes() + desc.bytes() + val.bytes() +
+           val32.bytes() + diag.bytes() + diag32.bytes() + work.bytes();
+}
+
+extern "C" {
+
+void hinqs_opts_default(hinqs_opts *o) {
+    if (!o) return;
+    o->block = 8;
+    o->max_space = 32;
+    o->max_iter = 200;
+    o->tol = 1e-8;
+    o->precision = HINQS_SOLVE_FP64;
+    o->precond_floor = 1e-8;
+    o->mixed_switch = 1e-5;
+    o->flags = 0;
+}
+
+int hinqs_create(hinqs_ctx **out, int device, void *hip_stream) {
+    if (!out) return HINQS_E_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HINQS_E_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return HINQS_E_HIP;
+    hinqs_ctx *ctx = new (std::nothrow) hinqs_ctx();
+    if (!ctx) return HINQS_E_OOM;
+    ctx->c.device = device;
+    ctx->c.stream = (hipStream_t)hip_stream;
+    *out = ctx;
+    return HINQS_OK;
+}
+
+void hinqs_destroy(hinqs_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->c.device);
+    (void)hipStreamSynchronize(ctx->c.stream);
+    delete ctx;
+}
+
+const char *hinqs_last_error(const hinqs_ctx *ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
+
+int hinqs_set_integrals(hinqs_ctx *ctx, int norb, const double *h, const double *eri, double e_core) {
+    return guarded(ctx, [&](Ctx &c) {
+        if (!h || !eri) throw Error(HINQS_E_INVALID_ARG, "null integral pointer");
+        if (norb < 1) throw Error(HINQS_E_INVALID_ARG, "norb must be >= 1");
+        if (norb > 32) throw Error(HINQS_E_UNSUPPORTED, "norb > 32 is not supported");
+        if (c.have_dets && norb != c.norb)
+            throw Error(HINQS_E_INVALID_ARG, "norb differs from that of the determinant set");
+        build_integrals(c, norb, h, eri, e_core);
+        if (c.have_dets) build_elements(c);
+        return HINQS_OK;
+    });
+}
+
+int hinqs_set_determinants(hinqs_ctx *ctx, int64_t ndet, const uint64_t *alpha, const uint64_t *beta,
+                           int nalpha, int nbeta) {
+    return guarded(ctx, [&](Ctx &c) {
+        if (!c.have_ints) throw Error(HINQS_E_NOT_READY, "set integrals first (they fix norb)");
+        if (!alpha || !beta) throw Error(HINQS_E_INVALID_ARG, "null determinant pointer");
+        if (ndet < 1 || ndet >= ((int64_t)1 << 31) - 1)
+            throw Error(HINQS_E_INVALID_ARG, "ndet must be in [1, 2^31 - 2]");
+        if (nalpha < 0 || nbeta < 0 || nalpha > c.norb || nbeta > c.norb)
+            throw Error(HINQS_E_INVALID_ARG, "electron counts out of range");
+        build_determinants(c, ndet, alpha, beta, nalpha, nbeta);
+        build_connectivity(c);
+        build_elements(c);
+        return HINQS_OK;
+    });
+}
+
+int hinqs_sigma(hinqs_ctx *ctx, int k, const void *X, void *S, int precision, int flags) {
+    return guarded(ctx, [&](Ctx &c) {
+        require_dets(c);
+        if (!X || !S) throw Error(HINQS_E_INVALID_ARG, "null vector pointer");
+        if (k < 1 || k > 16) throw Error(HINQS_E_UNSUPPORTED, "k must be in [1, 16]");
+        if (precision != HINQS_FP64 && precision != HINQS_FP32)
+            throw Error(HINQS_E_INVALID_ARG, "precision must be HINQS_FP64 or HINQS_FP32");
+        const int esz = precision == HINQS_FP64 ? 8 : 4;
+        const int K = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
+        const bool sorted = (flags & HINQS_SORTED_ORDER) != 0;
+        hipStream_t s = c.stream;
+        if (sorted && K == k) {
+            sigma_sorted(c, K, X, K, S, K, precision, s);
+            return HINQS_OK;
+        }
+        // stage through sorted-order buffers (gather X, scatter S); pad k up to K
+        const int64_t D = c.ndet;
+        DBuf<char> xs, ss, xp;
+        xs.ensure((size_t)D * K * esz);
+        ss.ensure((size_t)D * K * esz);
+        const void *src = X;
+        if (K != k) {
+            // pad to K columns: caller rows of k values -> rows of K values
+            xp.ensure((size_t)D * K * esz);
+            HQ_CHECK(hipMemsetAsync(xp.p, 0, (size_t)D * K * esz, s));
+            HQ_CHECK(hipMemcpy2DAsync(xp.p, (size_t)K * esz, X, (size_t)k * esz, (size_t)k * esz, D,
+                                      hipMemcpyDeviceToDevice, s));
+            src = xp.p;
+        }
+        if (sorted) HQ_CHECK(hipMemcpyAsync(xs.p, src, (size_t)D * K * esz, hipMemcpyDeviceToDevice, s));
+        else gather_rows(s, src, xs.p, c.perm.p, D, K * esz);
+        sigma_sorted(c, K, xs.p, K, ss.p, K, precision, s);
+        if (K == k) {
+            if (sorted) HQ_CHECK(hipMemcpyAsync(S, ss.p, (size_t)D * K * esz, hipMemcpyDeviceToDevice, s));
+            else scatter_rows(s, ss.p, S, c.perm.p, D, K * esz);
+        } else {
+            // unpad: scatter K-wide rows into a K-wide buffer, then copy k columns
+            if (!sorted) {
+                scatter_rows(s, ss.p, xs.p, c.perm.p, D, K * esz);
+                HQ_CHECK(hipMemcpy2DAsync(S, (size_t)k * esz, xs.p, (size_t)K * esz, (size_t)k * esz, D,
+                                          hipMemcpyDeviceToDevice, s));
+            } else {
+                HQ_CHECK(hipMemcpy2DAsync(S, (size_t)k * esz, ss.p, (size_t)K * esz, (size_t)k * esz, D,
+                                          hipMemcpyDeviceToDevice, s));
+            }
+        }
+        HQ_CHECK(hipStreamSynchronize(s));  // temporaries are released on return
+        return HINQS_OK;
+    });
+}
+
+int hinqs_lowest_eigenpair(hinqs_ctx *ctx, const hinqs_opts *opts, const double *guess, double *energy,
+                           double *coeffs, hinqs_stats *stats) {
+    return guarded(ctx, [&](Ctx &c) {
+        require_dets(c);
+        if (!energy || !coeffs) throw Error(HINQS_E_INVALID_ARG, "null output pointer");
+        hinqs_opts o;
+        hinqs_opts_default(&o);
+        if (opts) o = *opts;
+        if (!(o.tol > 0) || !(o.precond_floor > 0) || o.max_iter < 1)
+            throw Error(HINQS_E_INVALID_ARG, "tol, precond_floor and max_iter must be positive");
+        if (o.precision != HINQS_SOLVE_FP64 && o.precision != HINQS_SOLVE_MIXED)
+            throw Error(HINQS_E_INVALID_ARG, "unknown precision mode");
+        int rc = davidson(c, o, guess, energy, coeffs, stats);
+        if (rc == HINQS_E_NOT_CONVERGED) c.err = "Davidson did not reach the tolerance";
+        return rc;
+    });
+}
+
+int hinqs_rdm12(hinqs_ctx *ctx, const double *coeffs, double *rdm1, double *rdm2, int flags) {
+    return guarded(ctx, [&](Ctx &c) {
+        require_dets(c);
+        if (!coeffs || !rdm1 || !rdm2) throw Error(HINQS_E_INVALID_ARG, "null pointer");
+        if (flags & HINQS_SORTED_ORDER) {
+            rdm12_sorted(c, coeffs, rdm1, rdm2);
+        } else {
+            DBuf<double> cs;
+            cs.ensure(c.ndet);
+            gather_rows(c.stream, coeffs, cs.p, c.perm.p, c.ndet, 8);
+            rdm12_sorted(c, cs.p, rdm1, rdm2);
+        }
+        return HINQS_OK;
+    });
+}
+
+int hinqs_integral_grad(hinqs_ctx *ctx, const double *coeffs, double scale, double *grad_h,
+                        double *grad_eri, int flags) {
+    return guarded(ctx, [&](Ctx &c) {
+        require_dets(c);
+        if (!coeffs || !grad_h || !grad_eri) throw Error(HINQS_E_INVALID_ARG, "null pointer");
+        if (flags & HINQS_SORTED_ORDER) {
+            integral_grad_sorted(c, coeffs, scale, grad_h, grad_eri);
+        } else {
+            DBuf<double> cs;
+            cs.ensure(c.ndet);
+            gather_rows(c.stream, coeffs, cs.p, c.perm.p, c.ndet, 8);
+            integral_grad_sorted(c, cs.p, scale, grad_h, grad_eri);
+        }
+        return HINQS_OK;
+    });
+}
+
+int hinqs_diag(hinqs_ctx *ctx, double *diag, int flags) {
+    return guarded(ctx, [&](Ctx &c) {
+        require_dets(c);
+        if (!diag) throw Error(HINQS_E_INVALID_ARG, "null pointer");
+        if (flags & HINQS_SORTED_ORDER)
+            HQ_CHECK(hipMemcpyAsync(diag, c.diag.p, 8 * c.ndet, hipMemcpyDeviceToDevice, c.stream));
+        else
+            scatter_rows(c.stream, c.diag.p, diag, c.perm.p, c.ndet, 8);
+        HQ_CHECK(hipStreamSynchronize(c.stream));
+        return HINQS_OK;
+    });
+}
+
+int hinqs_permutation(hinqs_ctx *ctx, int32_t *perm) {
+    return guarded(ctx, [&](Ctx &c) {
+        if (!c.have_dets) throw Error(HINQS_E_NOT_READY, "determinants are not set");
+        if (!perm) throw Error(HINQS_E_INVALID_ARG, "null pointer");
+        HQ_CHECK(hipMemcpyAsync(perm, c.perm.p, 4 * c.ndet, hipMemcpyDeviceToDevice, c.stream));
+        HQ_CHECK(hipStreamSynchronize(c.stream));
+        return HINQS_OK;
+    });
+}
+
+int hinqs_gram(hinqs_ctx *ctx, int64_t nrows, const double *A, int lda, int ma, const double *B, int ldb,
+               int nb, double *G) {
+    return guarded(ctx, [&](Ctx &c) {
+        if (!A || !B || !G) throw Error(HINQS_E_INVALID_ARG, "null pointer");
+        if (nrows < 1 || ma < 1 || nb < 1 || lda < ma || ldb < nb)
+            throw Error(HINQS_E_INVALID_ARG, "bad Gram shape");
+        if (ma > 96 || nb > 16) throw Error(HINQS_E_UNSUPPORTED, "Gram product limited to 96 x 16");
+        gram_product(c, nrows, A, lda, ma, B, ldb, nb, G);
+        return HINQS_OK;
+    });
+}
+
+int hinqs_get_info(hinqs_ctx *ctx, hinqs_info *info) {
+    return guarded(ctx, [&](Ctx &c) {
+        if (!info) throw Error(HINQS_E_INVALID_ARG, "null pointer");
+        info->norb = c.norb;
+        info->nalpha = c.na;
+        info->nbeta = c.nb;
+        info->ndet = c.have_dets ? c.ndet : 0;
+        info->nnz = c.have_dets ? c.nnz : 0;
+        info->n_alpha_strings = c.nua;
+        info->n_beta_strings = c.nub;
+        info->device_bytes = (int64_t)c.device_bytes();
+        info->ms_sort = c.ms_sort;
+        info->ms_connect = c.ms_connect;
+        info->ms_elements = c.ms_elements;
+        return HINQS_OK;
+    });
+}
+
+uint32_t hinqs_pair_descriptor(uint64_t alpha_i, uint64_t beta_i, uint64_t alpha_j, uint64_t beta_j) {
+    const uint32_t ai = (uint32_t)alpha_i, bi = (uint32_t)beta_i, aj = (uint32_t)alpha_j,
+                   bj = (uint32_t)beta_j;
+    const int da = popc32(ai ^ aj), db = popc32(bi ^ bj);
+    if (da + db == 0 || da + db > 4) return 0u;
+    if (db == 0) return same_spin_desc(ai, aj, HINQS_EXC_1A, HINQS_EXC_2AA);
+    if (da == 0) return same_spin_desc(bi, bj, HINQS_EXC_1B, HINQS_EXC_2BB);
+    // one alpha and one beta move
+    const uint32_t ha_m = aj & ~ai, pa_m = ai & ~aj;
+    const int ha = lowbit(ha_m), pa = lowbit(pa_m);
+    return ab_desc(ha, pa, single_parity(aj, ha, pa), bi, bj);
+}
+
+int hinqs_connectivity(hinqs_ctx *ctx, int64_t *rowptr, int32_t *col, uint32_t *desc) {
+    return guarded(ctx, [&](Ctx &c) {
+        if (!c.have_dets) throw Error(HINQS_E_NOT_READY, "determinants are not set");
+        if (!rowptr) throw Error(HINQS_E_INVALID_ARG, "null rowptr");
+        export_connectivity(c, rowptr, col, desc);
+        return HINQS_OK;
+    });
+}
+
+}  // extern "C"

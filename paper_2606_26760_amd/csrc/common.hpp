@@ -1,0 +1,263 @@
+// Shared definitions of the gfx950 selected-CI library: error handling, device
+// buffers, the context, and the bit-string rules (excitation degree, holes,
+// particles and fermionic signs) used by every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/hinqs.h"
+
+namespace hinqs {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define HQ_CHECK(call)                                                                    \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw ::hinqs::Error(e_ == hipErrorOutOfMemory ? HINQS_E_OOM : HINQS_E_HIP,   \
+                                 std::string(#call) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+#define HQ_LAUNCH_CHECK() HQ_CHECK(hipGetLastError())
+
+// ---------------------------------------------------------- device buffer
+template <typename T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    // (Re)allocate to hold at least `count` elements; contents undefined.
+    void ensure(size_t count) {
+        if (count <= n && p) return;
+        release();
+        size_t bytes = (count ? count : 1) * sizeof(T);
+        hipError_t e = hipMalloc((void **)&p, bytes);
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw Error(HINQS_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                         hipGetErrorString(e));
+        }
+        n = count ? count : 1;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+    operator T *() const { return p; }
+};
+
+// --------------------------------------------------------- bit-string rules
+// Strings are uint32 (norb <= 32); bit p = spatial orbital p.
+
+__host__ __device__ inline int popc32(uint32_t x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    return __popc(x);
+#else
+    return __builtin_popcount(x);
+#endif
+}
+
+__host__ __device__ inline int lowbit(uint32_t x) {  // index of lowest set bit, x != 0
+#ifdef __HIP_DEVICE_COMPILE__
+    return __ffs(x) - 1;
+#else
+    return __builtin_ctz(x);
+#endif
+}
+
+__host__ __device__ inline int highbit(uint32_t x) {  // index of highest set bit, x != 0
+#ifdef __HIP_DEVICE_COMPILE__
+    return 31 - __clz(x);
+#else
+    return 31 - __builtin_clz(x);
+#endif
+}
+
+// Bits strictly between orbitals a and b (a != b, both < 32).
+__host__ __device__ inline uint32_t between(int a, int b) {
+    int lo = a < b ? a : b, hi = a < b ? b : a;
+    return ((hi >= 32 ? 0xffffffffu : ((1u << hi) - 1u))) & ~((2u << lo) - 1u);
+}
+
+// Parity (0 = +, 1 = -) of a+_p a_h |s>: occupied orbitals strictly between h and p.
+// The same-spin string of the other spin, and every orbital outside (h, p),
+// contribute an even count and drop out.
+__host__ __device__ inline uint32_t single_parity(uint32_t s, int h, int p) {
+    return (uint32_t)popc32(s & between(h, p)) & 1u;
+}
+
+// Parity of a+_p1 a+_p2 a_h2 a_h1 |s> with h1 < h2 (occupied in s) and p1 < p2
+// (empty in s).  The string equals -(a+_p1 a_h2)(a+_p2 a_h1): the move h1 -> p2
+// acts on s, the move h2 -> p1 on the intermediate string.
+__host__ __device__ inline uint32_t double_parity(uint32_t s, int h1, int h2, int p1, int p2) {
+    uint32_t s1 = s ^ (1u << h1) ^ (1u << p2);
+    return 1u ^ single_parity(s, h1, p2) ^ single_parity(s1, h2, p1);
+}
+
+// Descriptor layout (see hinqs_connectivity).
+__host__ __device__ inline uint32_t make_desc(uint32_t type, uint32_t neg, int h1, int h2, int p1,
+                                              int p2) {
+    return type | (neg << 3) | ((uint32_t)h1 << 4) | ((uint32_t)h2 << 9) | ((uint32_t)p1 << 14) |
+           ((uint32_t)p2 << 19);
+}
+__host__ __device__ inline uint32_t desc_type(uint32_t d) { return d & 7u; }
+__host__ __device__ inline uint32_t desc_neg(uint32_t d) { return (d >> 3) & 1u; }
+__host__ __device__ inline int desc_h1(uint32_t d) { return (d >> 4) & 31; }
+__host__ __device__ inline int desc_h2(uint32_t d) { return (d >> 9) & 31; }
+__host__ __device__ inline int desc_p1(uint32_t d) { return (d >> 14) & 31; }
+__host__ __device__ inline int desc_p2(uint32_t d) { return (d >> 19) & 31; }
+
+// Same-spin pair (bra string si, ket string sj) differing by one or two
+// electrons: class `type1` or `type2` descriptor.
+__host__ __device__ inline uint32_t same_spin_desc(uint32_t si, uint32_t sj, uint32_t type1,
+                                                   uint32_t type2) {
+    uint32_t holes = sj & ~si, parts = si & ~sj;
+    if (popc32(holes) == 1) {
+        int h = lowbit(holes), p = lowbit(parts);
+        return make_desc(type1, single_parity(sj, h, p), h, 0, p, 0);
+    }
+    int h1 = lowbit(holes), h2 = highbit(holes), p1 = lowbit(parts), p2 = highbit(parts);
+    return make_desc(type2, double_parity(sj, h1, h2, p1, p2), h1, h2, p1, p2);
+}
+
+// Opposite-spin double from an alpha move (ha -> pa on alpha string aj, parity na)
+// and a beta move (beta strings bi <- bj).
+__host__ __device__ inline uint32_t ab_desc(int ha, int pa, uint32_t na, uint32_t bi, uint32_t bj) {
+    uint32_t hb_m = bj & ~bi, pb_m = bi & ~bj;
+    int hb = lowbit(hb_m), pb = lowbit(pb_m);
+    return make_desc(HINQS_EXC_2AB, na ^ single_parity(bj, hb, pb), ha, hb, pa, pb);
+}
+
+// ------------------------------------------------- packed integral indexing
+// Pair index of (p, q) with p >= q: p(p+1)/2 + q; 8-fold symmetric (pq|rs) is
+// stored once per unordered pair of pair indices.
+__host__ __device__ inline int pair_index(int p, int q) {
+    return p >= q ? p * (p + 1) / 2 + q : q * (q + 1) / 2 + p;
+}
+__host__ __device__ inline int eri_index(int p, int q, int r, int s) {
+    int a = pair_index(p, q), b = pair_index(r, s);
+    return a >= b ? a * (a + 1) / 2 + b : b * (b + 1) / 2 + a;
+}
+inline int npair(int norb) { return norb * (norb + 1) / 2; }
+inline int neri_packed(int norb) { int m = npair(norb); return m * (m + 1) / 2; }
+
+// ------------------------------------------------------------- context
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    Timer() { (void)hipEventCreate(&a); (void)hipEventCreate(&b); }
+    ~Timer() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+};
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // integrals
+    int norb = 0;
+    bool have_ints = false;
+    double ecore = 0.0;
+    std::vector<double> h_host, eri_host;   // as given (norb^2, norb^4)
+    DBuf<double> d_h;                      // norb^2
+    DBuf<double> d_eri;                    // packed 8-fold
+    DBuf<float> d_eri32;                   // packed, FP32 copy
+
+    // determinants (sorted: alpha-major, then beta)
+    bool have_dets = false;
+    int na = 0, nb = 0;
+    int64_t ndet = 0;
+    DBuf<uint32_t> sa, sb;     // strings in sorted order
+    DBuf<int32_t> perm;        // sorted position -> caller index
+    DBuf<int32_t> inv;         // caller index -> sorted position
+    int32_t nua = 0, nub = 0;
+    DBuf<uint32_t> ua, ub;     // distinct alpha / beta strings, ascending
+    DBuf<int32_t> ga;          // alpha group offsets (nua+1) into sorted order
+    DBuf<int32_t> aidx, bidx;  // per determinant: index into ua / ub
+    DBuf<int32_t> gb;          // beta group offsets (nub+1) into bperm
+    DBuf<int32_t> bperm;       // beta-major listing of sorted positions
+    DBuf<uint32_t> bm_alpha;   // alpha string of bperm[t]
+    int alink_max = 0;         // row length of the padded link table
+    DBuf<int32_t> alink_ptr;   // per distinct alpha string: number of single moves to strings of B
+    DBuf<int32_t> alink;       // [nua][alink_max] target index into ua
+    DBuf<uint32_t> alink_info; // hole | particle << 5 | parity << 10
+
+    // couplings (sorted order, diagonal not stored)
+    int64_t nnz = 0;
+    DBuf<int64_t> rowptr;
+    DBuf<int32_t> col;
+    DBuf<uint32_t> desc;
+    DBuf<double> val;
+    DBuf<float> val32;
+    DBuf<double> diag;
+    DBuf<float> diag32;
+    bool have_elements = false;
+
+    // timings (ms)
+    double ms_sort = 0, ms_connect = 0, ms_elements = 0;
+
+    // workspace shared by calls
+    DBuf<char> work;
+
+    size_t device_bytes() const;
+};
+
+// ------------------------------------------------------ internal entry points
+void build_integrals(Ctx &c, int norb, const double *h, const double *eri, double ecore);
+void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint64_t *beta, int na,
+                        int nb);
+void build_connectivity(Ctx &c);
+void build_elements(Ctx &c);
+void export_connectivity(Ctx &c, int64_t *rowptr_c, int32_t *col_c, uint32_t *desc_c);
+
+// Scan / sort utilities (scan.hip).  All on c.stream.
+void exclusive_scan_i64(hipStream_t s, const int64_t *in, int64_t *out, int64_t n, DBuf<char> &tmp);
+void exclusive_scan_i32(hipStream_t s, const int32_t *in, int32_t *out, int64_t n, DBuf<char> &tmp);
+// Stable LSD radix sort of `keys` (nbits significant low bits) carrying `vals`.
+void radix_sort_u64(hipStream_t s, uint64_t *keys, int32_t *vals, int64_t n, int nbits,
+                    DBuf<char> &tmp);
+
+// Sigma (sigma.hip): S = H X in sorted order with leading dimensions.
+void sigma_sorted(Ctx &c, int k, const void *X, int ldx, void *S, int lds, int precision,
+                  hipStream_t s);
+
+// Davidson (davidson.hip)
+int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, double *coeffs,
+             hinqs_stats *st);
+
+// Tall-skinny Gram product G = A^T B (FP64 MFMA), A: nrows x ma, B: nrows x nb.
+void gram_product(Ctx &c, int64_t nrows, const double *A, int lda, int ma, const double *B, int ldb,
+                  int nb, double *G);
+
+// RDMs (rdm.hip): c in sorted order.
+void rdm12_sorted(Ctx &c, const double *cs, double *rdm1, double *rdm2);
+void integral_grad_sorted(Ctx &c, const double *cs, double scale, double *gh, double *geri);
+
+// permutation helpers (dets.hip)
+void gather_rows(hipStream_t s, const void *src, void *dst, const int32_t *idx, int64_t n,
+                 int rowbytes);   // dst[r] = src[idx[r]]
+void scatter_rows(hipStream_t s, const void *src, void *dst, const int32_t *idx, int64_t n,
+                  int rowbytes);  // dst[idx[r]] = src[r]
+
+inline unsigned grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+}  // namespace hinqs

@@ -1,0 +1,165 @@
+// Coupling enumeration: for every determinant x_i of B, every x_j of B that
+// differs from it by one or two electrons, i.e. every pair with a possibly
+// nonzero <x_i|H|x_j> (Slater-Condon rules; paper Sec. 2.2, Step 3 builds
+// [H_B]_ij over exactly these pairs).
+//
+// One thread per row (sorted order).  The three classes are found without an
+// O(|B|^2) scan:
+//   alpha-only moves   x_j shares beta_i: scan the beta group of beta_i;
+//   beta-only moves    x_j shares alpha_i: scan the alpha group of alpha_i;
+//   alpha+beta moves   alpha_j is a single move of alpha_i present in B (alpha
+//                      link table): scan that alpha group for beta strings one
+//                      move away.
+// Each candidate is tested with XOR + popcount; the sign comes from masked
+// popcounts (common.hpp).  Neighbouring threads usually share alpha_i and so
+// walk the same groups in lock step, which turns the string loads into
+// broadcasts.  A counting pass sizes each row; a fill pass writes (col, desc).
+#include <chrono>
+
+#include "common.hpp"
+
+namespace hinqs {
+
+namespace {
+
+struct ConnArgs {
+    int64_t ndet;
+    const uint32_t *sa, *sb;
+    const int32_t *aidx, *bidx, *ga, *gb, *bperm;
+    const uint32_t *bm_alpha;
+    const int32_t *alink_cnt, *alink;
+    const uint32_t *alink_info;
+    int alink_max;
+};
+
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_connect(ConnArgs a, int64_t *counts, const int64_t *rowptr,
+                                                 int32_t *col, uint32_t *desc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.ndet) return;
+    const uint32_t ai = a.sa[i], bi = a.sb[i];
+    const int32_t ag = a.aidx[i], bg = a.bidx[i];
+    int64_t out = FILL ? rowptr[i] : 0;
+    int64_t n = 0;
+    // alpha-only: determinants with the same beta string
+    for (int32_t t = a.gb[bg], e = a.gb[bg + 1]; t < e; ++t) {
+        const uint32_t aj = a.bm_alpha[t];
+        const int d = popc32(ai ^ aj);
+        if (d == 2 || d == 4) {
+            if (FILL) {
+                col[out] = a.bperm[t];
+                desc[out] = same_spin_desc(ai, aj, HINQS_EXC_1A, HINQS_EXC_2AA);
+                ++out;
+            }
+            ++n;
+        }
+    }
+    // beta-only: determinants with the same alpha string
+    for (int32_t j = a.ga[ag], e = a.ga[ag + 1]; j < e; ++j) {
+        const uint32_t bj = a.sb[j];
+        const int d = popc32(bi ^ bj);
+        if (d == 2 || d == 4) {
+            if (FILL) {
+                col[out] = j;
+                desc[out] = same_spin_desc(bi, bj, HINQS_EXC_1B, HINQS_EXC_2BB);
+                ++out;
+            }
+            ++n;
+        }
+    }
+    // alpha + beta: alpha string one move away, beta string one move away
+    const int64_t lbase = (int64_t)ag * a.alink_max;
+    for (int32_t l = 0, le = a.alink_cnt[ag]; l < le; ++l) {
+        const int32_t tgt = a.alink[lbase + l];
+        const uint32_t info = a.alink_info[lbase + l];
+        const int ha = info & 31, pa = (info >> 5) & 31;
+        const uint32_t npar = (info >> 10) & 1u;
+        for (int32_t j = a.ga[tgt], e = a.ga[tgt + 1]; j < e; ++j) {
+            const uint32_t bj = a.sb[j];
+            if (popc32(bi ^ bj) == 2) {
+                if (FILL) {
+                    col[out] = j;
+                    desc[out] = ab_desc(ha, pa, npar, bi, bj);
+                    ++out;
+                }
+                ++n;
+            }
+        }
+    }
+    if (!FILL) counts[i] = n;
+}
+
+__global__ void k_caller_counts(int64_t n, const int64_t *rowptr, const int32_t *perm, int64_t *counts) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    counts[perm[i]] = rowptr[i + 1] - rowptr[i];
+}
+
+// One wave per sorted row: copy its couplings to the caller-order position,
+// translating column indices to caller indices.
+__global__ void k_caller_copy(int64_t n, const int64_t *rowptr, const int32_t *col, const uint32_t *desc,
+                              const int32_t *perm, const int64_t *rowptr_c, int32_t *col_c,
+                              uint32_t *desc_c) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= n) return;
+    const int64_t beg = rowptr[row], end = rowptr[row + 1];
+    const int64_t dst = rowptr_c[perm[row]];
+    for (int64_t e = beg + lane; e < end; e += 64) {
+        if (col_c) col_c[dst + (e - beg)] = perm[col[e]];
+        if (desc_c) desc_c[dst + (e - beg)] = desc[e];
+    }
+}
+
+}  // namespace
+
+void export_connectivity(Ctx &c, int64_t *rowptr_c, int32_t *col_c, uint32_t *desc_c) {
+    hipStream_t s = c.stream;
+    const int64_t n = c.ndet;
+    DBuf<int64_t> counts;
+    counts.ensure(n + 1);
+    HQ_CHECK(hipMemsetAsync(counts.p + n, 0, sizeof(int64_t), s));
+    hipLaunchKernelGGL(k_caller_counts, dim3(grid_for(n, 256)), dim3(256), 0, s, n, c.rowptr.p, c.perm.p,
+                       counts.p);
+    HQ_LAUNCH_CHECK();
+    exclusive_scan_i64(s, counts.p, rowptr_c, n + 1, c.work);
+    if (col_c || desc_c) {
+        hipLaunchKernelGGL(k_caller_copy, dim3(grid_for(n * 64, 256)), dim3(256), 0, s, n, c.rowptr.p,
+                           c.col.p, c.desc.p, c.perm.p, rowptr_c, col_c, desc_c);
+        HQ_LAUNCH_CHECK();
+    }
+    HQ_CHECK(hipStreamSynchronize(s));
+}
+
+void build_connectivity(Ctx &c) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = c.stream;
+    const int64_t n = c.ndet;
+    ConnArgs a{n,          c.sa.p,        c.sb.p,    c.aidx.p,      c.bidx.p,
+               c.ga.p,     c.gb.p,        c.bperm.p, c.bm_alpha.p,  c.alink_ptr.p,
+               c.alink.p,  c.alink_info.p, c.alink_max};
+    DBuf<int64_t> counts;
+    counts.ensure(n + 1);
+    dim3 g(grid_for(n, 256)), b(256);
+    hipLaunchKernelGGL(k_connect<false>, g, b, 0, s, a, counts.p, (const int64_t *)nullptr,
+                       (int32_t *)nullptr, (uint32_t *)nullptr);
+    HQ_LAUNCH_CHECK();
+    HQ_CHECK(hipMemsetAsync(counts.p + n, 0, sizeof(int64_t), s));
+    c.rowptr.ensure(n + 1);
+    exclusive_scan_i64(s, counts.p, c.rowptr.p, n + 1, c.work);
+    int64_t nnz = 0;
+    HQ_CHECK(hipMemcpyAsync(&nnz, c.rowptr.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipStreamSynchronize(s));
+    if (nnz >= ((int64_t)1 << 40)) throw Error(HINQS_E_UNSUPPORTED, "too many couplings");
+    c.nnz = nnz;
+    c.col.ensure(nnz);
+    c.desc.ensure(nnz);
+    hipLaunchKernelGGL(k_connect<true>, g, b, 0, s, a, (int64_t *)nullptr, c.rowptr.p, c.col.p,
+                       c.desc.p);
+    HQ_LAUNCH_CHECK();
+    HQ_CHECK(hipStreamSynchronize(s));
+    c.ms_connect =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace hinqs

@@ -1,0 +1,308 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Bars (written in each test):
+  * couplings, excitation class, holes/particles and sign: bit-exact;
+  * FP64 sigma: |S - S_ref| <= 1e-12 * sum_j |H_ij| |X_j| per row and column;
+  * FP32 sigma: the same with 2e-6 (a few FP32 ulps times the row length);
+  * FP64 eigenvalue: 1e-10 Ha; eigenvector overlap >= 1 - 1e-10 (gap > 1e-6);
+  * density matrices from one seeded vector: 1e-12 (atomics reorder sums).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_helpers import (gpu_rows_as_tuples, log, oracle_for, oracle_rows_as_tuples, row_bound,
+                               solver_for)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+hq = pytest.importorskip("paper_2606_26760_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hq.load_library()
+
+
+# ------------------------------------------------------------- Gram (MFMA)
+@pytest.mark.parametrize("n,ma,nb", [(1000, 40, 8), (37, 3, 5), (4099, 96, 16), (1, 1, 1),
+                                     (70001, 17, 13)])
+def test_gram_matches_host(n, ma, nb):
+    log(f"gram n={n} ma={ma} nb={nb}")
+    rng = np.random.default_rng(n + ma)
+    A = rng.standard_normal((n, ma))
+    B = rng.standard_normal((n, nb))
+    s = hq.Hinqs()
+    G = s.gram(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()).cpu().numpy()
+    ref = A.T @ B
+    scale = np.abs(A).T @ np.abs(B)
+    assert np.all(np.abs(G - ref) <= 1e-13 * scale + 1e-300)
+
+
+# ------------------------------------------------------------- couplings
+def _check_couplings(ints, alpha, beta, na, nb, rows):
+    s = solver_for(ints, alpha, beta, na, nb)
+    o = oracle_for(ints, alpha, beta, na, nb)
+    got = gpu_rows_as_tuples(s, rows)
+    want, _ = oracle_rows_as_tuples(o, rows)
+    for i in rows:
+        assert got[int(i)] == want[int(i)], f"row {i}"
+    return s, o
+
+
+def test_couplings_full_space_cas6():
+    ints, a, b, cfg = W.config_inputs(0)
+    log("couplings cas6 full space, all rows")
+    s, _ = _check_couplings(ints, a, b, cfg.na, cfg.nb, np.arange(len(a)))
+    assert s.info()["nnz"] == 400 * 117
+
+
+def test_couplings_sampled_cas10_all_rows():
+    ints, a, b, cfg = W.config_inputs(1)
+    log("couplings cas10 20000 dets, all rows")
+    _check_couplings(ints, a, b, cfg.na, cfg.nb, np.arange(len(a)))
+
+
+def test_couplings_ragged_small_sets():
+    # sets of a few determinants, including ones with no couplings at all
+    for seed, (norb, na, nb, n) in enumerate([(5, 2, 2, 1), (5, 2, 2, 3), (7, 3, 1, 17),
+                                              (8, 4, 4, 257), (6, 0, 3, 20), (6, 6, 1, 6)]):
+        ints = W.gen_integrals(norb, norb, -2, -0.5, 300 + seed)
+        a, b = W.sample_determinants(norb, na, nb, n, 0.5, 0.3, 400 + seed)
+        log(f"couplings ragged norb={norb} na={na} nb={nb} n={n}")
+        _check_couplings(ints, a, b, na, nb, np.arange(len(a)))
+
+
+def test_couplings_1m_sampled_rows():
+    ints, a, b, cfg = W.config_inputs(2)
+    rows = np.random.default_rng(7).choice(len(a), 200, replace=False)
+    log("couplings cas16 1e6 dets, 200 sampled rows")
+    _check_couplings(ints, a, b, cfg.na, cfg.nb, rows)
+
+
+# ------------------------------------------------------------- sigma
+def _check_sigma(s, o, X, rows, tol, dtype=torch.float64, k=None):
+    Xd = torch.from_numpy(X).to(dtype).cuda()
+    S = s.sigma(Xd).double().cpu().numpy()
+    Xr = Xd.double().cpu().numpy()
+    ref = o.sigma_rows(Xr, rows)
+    _, r = oracle_rows_as_tuples(o, rows)
+    bound = row_bound(r, Xr, Xr.shape[1])
+    err = np.abs(S[rows] - ref)
+    assert np.all(err <= tol * bound + 1e-300), float((err / (bound + 1e-300)).max())
+
+
+def test_diag_matches_oracle():
+    ints, a, b, cfg = W.config_inputs(1, ndet=3000)
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    o = oracle_for(ints, a, b, cfg.na, cfg.nb)
+    d = s.diag().cpu().numpy()
+    ref = o.diag()
+    assert np.abs(d - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("k", [1, 3, 8, 16])
+def test_sigma_fp64_cas6(k):
+    ints, a, b, cfg = W.config_inputs(0)
+    log(f"sigma fp64 cas6 k={k}")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    o = oracle_for(ints, a, b, cfg.na, cfg.nb)
+    X = W.random_block(len(a), k, 11 + k)
+    _check_sigma(s, o, X, np.arange(len(a)), 1e-12)
+
+
+def test_sigma_fp64_cas10_all_rows():
+    ints, a, b, cfg = W.config_inputs(1)
+    log("sigma fp64 cas10 20000 dets k=8")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    o = oracle_for(ints, a, b, cfg.na, cfg.nb)
+    X = W.random_block(len(a), 8, 21)
+    _check_sigma(s, o, X, np.arange(len(a)), 1e-12)
+
+
+def test_sigma_fp32_cas10():
+    ints, a, b, cfg = W.config_inputs(1, ndet=5000)
+    log("sigma fp32 cas10 5000 dets k=8")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    o = oracle_for(ints, a, b, cfg.na, cfg.nb)
+    X = W.random_block(len(a), 8, 22)
+    _check_sigma(s, o, X, np.arange(len(a)), 2e-6, dtype=torch.float32)
+
+
+def test_sigma_1m_sampled_rows_fp64_and_fp32():
+    ints, a, b, cfg = W.config_inputs(2)
+    log("sigma cas16 1e6 dets, sampled rows")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    o = oracle_for(ints, a, b, cfg.na, cfg.nb)
+    rows = np.random.default_rng(8).choice(len(a), 150, replace=False)
+    X = W.random_block(len(a), 8, 23)
+    _check_sigma(s, o, X, rows, 1e-12)
+    _check_sigma(s, o, X, rows, 2e-6, dtype=torch.float32)
+
+
+def test_sigma_sorted_order_matches_caller_order():
+    ints, a, b, cfg = W.config_inputs(1, ndet=4000)
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    X = torch.from_numpy(W.random_block(len(a), 8, 24)).cuda()
+    S = s.sigma(X)
+    perm = s.permutation().long()
+    Ss = s.sigma(X[perm].contiguous(), sorted_order=True)
+    assert torch.equal(Ss, S[perm])
+
+
+# ------------------------------------------------------------- eigenpairs
+def _gap(o):
+    w = o.spectrum(2)
+    return w[1] - w[0]
+
+
+def test_eigenpair_full_space_cas6_vs_dense():
+    ints, a, b, cfg = W.config_inputs(0)
+    log("davidson cas6 full space vs dense eigh")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    o = oracle_for(ints, a, b, cfg.na, cfg.nb)
+    e_ref, c_ref = o.lowest_eigenpair()
+    assert _gap(o) > 1e-6
+    e, c, st = s.lowest_eigenpair(tol=1e-8)
+    log(f"  E={e!r} ref={e_ref!r} stats={st}")
+    assert abs(e - e_ref) <= 1e-10
+    c = c.cpu().numpy()
+    assert abs(np.dot(c, c_ref)) >= 1 - 1e-10
+    assert abs(np.linalg.norm(c) - 1) < 1e-12
+    assert c[np.argmax(np.abs(c))] > 0
+
+
+def test_eigenpair_cas10_vs_lanczos():
+    ints, a, b, cfg = W.config_inputs(1)
+    log("davidson cas10 20000 dets vs oracle Lanczos")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    o = oracle_for(ints, a, b, cfg.na, cfg.nb)
+    e_ref, c_ref = o.lowest_eigenpair(dense_max=0)
+    assert _gap(o) > 1e-6
+    e, c, st = s.lowest_eigenpair(tol=1e-8)
+    log(f"  E={e!r} ref={e_ref!r} stats={st}")
+    assert abs(e - e_ref) <= 1e-10
+    assert abs(np.dot(c.cpu().numpy(), c_ref)) >= 1 - 1e-9
+
+
+def test_eigenpair_small_sets_and_tiny_spaces():
+    for seed, (norb, na, nb, n) in enumerate([(5, 2, 2, 1), (5, 2, 2, 5), (6, 3, 2, 37),
+                                              (7, 3, 3, 150)]):
+        ints = W.gen_integrals(norb, norb, -2, -0.5, 500 + seed)
+        a, b = W.sample_determinants(norb, na, nb, n, 0.5, 0.3, 600 + seed)
+        log(f"davidson tiny norb={norb} n={n}")
+        s = solver_for(ints, a, b, na, nb)
+        o = oracle_for(ints, a, b, na, nb)
+        e_ref, c_ref = o.lowest_eigenpair()
+        e, c, st = s.lowest_eigenpair(tol=1e-9)
+        assert abs(e - e_ref) <= 1e-10
+        if n > 1:
+            w = o.spectrum(2)
+            if w[1] - w[0] > 1e-6:
+                assert abs(np.dot(c.cpu().numpy(), c_ref)) >= 1 - 1e-10
+
+
+def test_warm_start_converges_immediately():
+    ints, a, b, cfg = W.config_inputs(1, ndet=5000)
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    e, c, st = s.lowest_eigenpair(tol=1e-9)
+    e2, c2, st2 = s.lowest_eigenpair(guess=c, tol=1e-8)
+    log(f"  cold {st['iterations']} iterations, warm {st2['iterations']}")
+    assert abs(e2 - e) < 1e-10
+    assert st2["iterations"] <= 2
+
+
+def test_not_converged_returns_best_estimate():
+    ints, a, b, cfg = W.config_inputs(1, ndet=3000)
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    with pytest.raises(hq.HinqsError) as ei:
+        s.lowest_eigenpair(max_iter=1, tol=1e-12)
+    assert ei.value.name == "NOT_CONVERGED"
+    e, c, st = s.lowest_eigenpair(max_iter=1, tol=1e-12, raise_on_not_converged=False)
+    assert np.isfinite(e) and not st["converged"]
+
+
+def test_mixed_precision_matches_fp64():
+    ints, a, b, cfg = W.config_inputs(2, ndet=60_000)
+    log("mixed vs fp64, cas16 60000 dets")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    e64, c64, st64 = s.lowest_eigenpair(tol=1e-8)
+    em, cm, stm = s.lowest_eigenpair(tol=1e-8, mixed=True)
+    log(f"  fp64 E={e64!r} {st64}\n  mixed E={em!r} {stm}")
+    assert abs(em - e64) <= 1e-8
+    assert stm["iterations_fp32"] >= 1
+    assert abs(torch.dot(c64, cm).item()) >= 1 - 1e-8
+
+
+# ------------------------------------------------------------- RDMs
+def test_rdm12_matches_oracle_seeded_vector():
+    for idx, n in [(0, None), (3, 400)]:
+        ints, a, b, cfg = W.config_inputs(idx, ndet=n)
+        log(f"rdm12 config {idx} n={len(a)}")
+        s = solver_for(ints, a, b, cfg.na, cfg.nb)
+        o = oracle_for(ints, a, b, cfg.na, cfg.nb)
+        c = W.random_block(len(a), 1, 31)[:, 0]
+        d1, d2 = s.rdm12(torch.from_numpy(c).cuda())
+        r1, r2 = o.rdm12(c)
+        scale = float(np.sum(c * c))
+        assert np.abs(d1.cpu().numpy() - r1).max() <= 1e-12 * scale * cfg.norb
+        assert np.abs(d2.cpu().numpy() - r2).max() <= 1e-12 * scale * cfg.norb ** 2
+
+
+def test_rdm12_identities_on_eigenvector_200k():
+    ints, a, b, cfg = W.config_inputs(3)
+    log("rdm12 identities cas12 200000 dets")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    e, c, st = s.lowest_eigenpair(tol=1e-10)
+    d1, d2 = (t.cpu().numpy() for t in s.rdm12(c))
+    N = cfg.na + cfg.nb
+    assert abs(np.trace(d1) - N) < 1e-9
+    assert abs(np.einsum("pprr", d2) - N * (N - 1)) < 1e-8
+    assert np.abs(np.einsum("pqrr->pq", d2) - (N - 1) * d1).max() < 1e-9
+    e_rdm = ints.e_core + np.sum(ints.h * d1) + 0.5 * np.sum(ints.eri * d2)
+    assert abs(e_rdm - e) < 1e-8
+    # sampled elements against the oracle, one pass over B each
+    o = oracle_for(ints, a, b, cfg.na, cfg.nb)
+    idx = np.random.default_rng(5).integers(0, cfg.norb, size=(24, 4))
+    cc = c.cpu().numpy()
+    ref = o.rdm2_elements(cc, idx)
+    got = d2[idx[:, 0], idx[:, 1], idx[:, 2], idx[:, 3]]
+    assert np.abs(got - ref).max() < 1e-11
+
+
+# ------------------------------------------------------------- errors
+def test_error_paths():
+    ints, a, b, cfg = W.config_inputs(1, ndet=500)
+    s = hq.Hinqs()
+    with pytest.raises(hq.HinqsError) as ei:
+        s._check(s._lib.hinqs_sigma(s._h, 8, None, None, 0, 0))
+    assert ei.value.name == "NOT_READY"
+    with pytest.raises(hq.HinqsError) as ei:
+        s.set_determinants(a, b, cfg.na, cfg.nb)
+    assert ei.value.name == "NOT_READY"
+    bad = ints.eri.copy()
+    bad[0, 1, 2, 3] += 1e-3
+    with pytest.raises(hq.HinqsError) as ei:
+        s.set_integrals(ints.h, bad, 0.0)
+    assert ei.value.name == "ASYMMETRIC"
+    nan_h = ints.h.copy()
+    nan_h[0, 0] = np.nan
+    with pytest.raises(hq.HinqsError) as ei:
+        s.set_integrals(nan_h, ints.eri, 0.0)
+    assert ei.value.name == "NONFINITE"
+    s.set_integrals(ints.h, ints.eri, 0.0)
+    with pytest.raises(hq.HinqsError) as ei:
+        s.set_determinants(np.concatenate([a, a[:1]]), np.concatenate([b, b[:1]]), cfg.na, cfg.nb)
+    assert ei.value.name == "DUPLICATE"
+    a2 = a.copy()
+    a2[3] |= np.uint64(1 << 12)
+    with pytest.raises(hq.HinqsError) as ei:
+        s.set_determinants(a2, b, cfg.na, cfg.nb)
+    assert ei.value.name == "BAD_OCCUPATION"
+    s.set_determinants(a, b, cfg.na, cfg.nb)
+    with pytest.raises(hq.HinqsError) as ei:
+        s.sigma(torch.zeros((len(a), 17), dtype=torch.float64, device="cuda"))
+    assert ei.value.name == "UNSUPPORTED"
