@@ -86,6 +86,7 @@ typedef struct hinqs_stats {
     int    iterations;         /* Davidson iterations (all precisions) */
     int    iterations_fp32;    /* of which with FP32 sigma products */
     int    sigma_blocks;       /* block sigma products applied */
+    int    sigma_columns;      /* vectors those products carried (<= block each) */
     int    restarts;
     double residual;           /* final ||r||_2 of the lowest root */
     double ms_total;           /* wall time of the call */
@@ -149,6 +150,15 @@ int hinqs_set_integrals(hinqs_ctx *ctx, int norb, const double *h, const double 
  */
 int hinqs_set_determinants(hinqs_ctx *ctx, int64_t ndet, const uint64_t *alpha,
                            const uint64_t *beta, int nalpha, int nbeta);
+
+/*
+ * As hinqs_set_determinants, with alpha and beta already in device memory
+ * (ndet uint64 each, on the context's device); validation runs on the GPU.
+ * The arrays are copied; the caller keeps ownership.
+ * Errors: as hinqs_set_determinants.
+ */
+int hinqs_set_determinants_device(hinqs_ctx *ctx, int64_t ndet, const uint64_t *alpha,
+                                  const uint64_t *beta, int nalpha, int nbeta);
 
 /*
  * Block sigma product S = H_B X (the repeated operation of the Davidson

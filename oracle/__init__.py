@@ -64,6 +64,7 @@ def _load():
             lib.or_rows.restype = i64
             lib.or_rows.argtypes = [P, i64, P]
             lib.or_rows_export.argtypes = [P, P, P, P, P, P, P]
+            lib.or_sigma_rows.restype = i64
             lib.or_sigma_rows.argtypes = [P, i64, P, ctypes.c_int, P, P]
             lib.or_rdm12.argtypes = [P, P, P, P]
             lib.or_rdm2_elements.argtypes = [P, P, i64, P, P]
@@ -151,8 +152,10 @@ class Oracle:
         return o["val"][o["rowptr"][:-1]]
 
     # ------------------------------------------------------------- sigma
-    def sigma_rows(self, X, rows=None):
-        """S[r] = sum_j <x_rows[r]|H|x_j> X[j] by operator application (matrix-free)."""
+    def sigma_rows(self, X, rows=None, return_pairs=False):
+        """S[r] = sum_j <x_rows[r]|H|x_j> X[j] by operator application (matrix-free).
+
+        With return_pairs, also the number of stored (row, column) elements visited."""
         lib = _load()
         X = np.ascontiguousarray(X, dtype=np.float64)
         if X.ndim == 1:
@@ -161,8 +164,8 @@ class Oracle:
         r = np.arange(self.ndet, dtype=np.int64) if rows is None else \
             np.ascontiguousarray(rows, dtype=np.int64)
         S = np.empty((len(r), k), np.float64)
-        lib.or_sigma_rows(self._h, len(r), _ptr(r), k, _ptr(X), _ptr(S))
-        return S
+        pairs = lib.or_sigma_rows(self._h, len(r), _ptr(r), k, _ptr(X), _ptr(S))
+        return (S, int(pairs)) if return_pairs else S
 
     # ---------------------------------------------------------- eigenpair
     def lowest_eigenpair(self, dense_max: int = 5000, tol: float = 1e-13):

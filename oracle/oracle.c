@@ -422,12 +422,14 @@ void or_rows_export(void *handle, int64_t *rowptr, int64_t *col, double *val, in
     if (sgn) memcpy(sgn, o->sign, (size_t)tot);
 }
 
-/* S[r, :] = sum_j <x_rows[r]|H|x_j> X[j, :] for a k-column block X (ndet x k, row-major). */
-void or_sigma_rows(void *handle, int64_t nrows, const int64_t *rows, int k, const double *X,
-                   double *S)
+/* S[r, :] = sum_j <x_rows[r]|H|x_j> X[j, :] for a k-column block X (ndet x k, row-major).
+ * Returns the number of (row, determinant) pairs with a stored element, diagonal included. */
+int64_t or_sigma_rows(void *handle, int64_t nrows, const int64_t *rows, int k, const double *X,
+                      double *S)
 {
     oracle_t *o = (oracle_t *)handle;
-#pragma omp parallel
+    int64_t pairs = 0;
+#pragma omp parallel reduction(+ : pairs)
     {
         scratch_t *w = scratch_new(o);
 #pragma omp for schedule(dynamic, 4)
@@ -441,9 +443,11 @@ void or_sigma_rows(void *handle, int64_t nrows, const int64_t *rows, int k, cons
                 }
                 S[r * k + c] = s;
             }
+            pairs += w->ntouched;
         }
         scratch_free(w);
     }
+    return pairs;
 }
 
 /* --------------------------------------------------------------- RDMs */

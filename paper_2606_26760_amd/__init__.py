@@ -39,7 +39,7 @@ EXPORTED = ["hinqs_opts_default", "hinqs_create", "hinqs_destroy", "hinqs_last_e
             "hinqs_set_integrals", "hinqs_set_determinants", "hinqs_sigma",
             "hinqs_lowest_eigenpair", "hinqs_rdm12", "hinqs_integral_grad", "hinqs_diag",
             "hinqs_connectivity", "hinqs_permutation", "hinqs_get_info",
-            "hinqs_pair_descriptor", "hinqs_gram"]
+            "hinqs_pair_descriptor", "hinqs_gram", "hinqs_set_determinants_device"]
 
 
 class HinqsError(RuntimeError):
@@ -58,7 +58,8 @@ class Opts(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("iterations_fp32", ctypes.c_int),
-                ("sigma_blocks", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("sigma_blocks", ctypes.c_int), ("sigma_columns", ctypes.c_int),
+                ("restarts", ctypes.c_int),
                 ("residual", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("ms_sigma", ctypes.c_double), ("nnz", ctypes.c_int64)]
 
@@ -99,6 +100,7 @@ def load_library() -> ctypes.CDLL:
             "hinqs_last_error": (ctypes.c_char_p, [P]),
             "hinqs_set_integrals": (i32, [P, i32, P, P, dbl]),
             "hinqs_set_determinants": (i32, [P, i64, P, P, i32, i32]),
+            "hinqs_set_determinants_device": (i32, [P, i64, P, P, i32, i32]),
             "hinqs_sigma": (i32, [P, i32, P, P, i32, i32]),
             "hinqs_lowest_eigenpair": (i32, [P, P, P, P, P, P]),
             "hinqs_rdm12": (i32, [P, P, P, P, i32]),
@@ -208,6 +210,17 @@ class Hinqs:
         self.norb = norb
 
     def set_determinants(self, alpha, beta, nalpha: int, nbeta: int):
+        torch = _torch()
+        if isinstance(alpha, torch.Tensor) and alpha.device.type == "cuda":
+            # device-resident strings (int64 tensors holding the uint64 bit patterns)
+            self._dev(alpha, torch.int64)
+            self._dev(beta, torch.int64)
+            if alpha.shape != beta.shape or alpha.dim() != 1:
+                raise ValueError("alpha and beta must be 1-D and equally long")
+            self._check(self._lib.hinqs_set_determinants_device(
+                self._h, alpha.numel(), self._ptr(alpha), self._ptr(beta), nalpha, nbeta))
+            self.na, self.nb, self.ndet = nalpha, nbeta, alpha.numel()
+            return
         a = _host_u64(alpha)
         b = _host_u64(beta)
         if a.shape != b.shape or a.ndim != 1:

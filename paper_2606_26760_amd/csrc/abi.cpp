@@ -108,7 +108,23 @@ int hinqs_set_determinants(hinqs_ctx *ctx, int64_t ndet, const uint64_t *alpha, 
             throw Error(HINQS_E_INVALID_ARG, "ndet must be in [1, 2^31 - 2]");
         if (nalpha < 0 || nbeta < 0 || nalpha > c.norb || nbeta > c.norb)
             throw Error(HINQS_E_INVALID_ARG, "electron counts out of range");
-        build_determinants(c, ndet, alpha, beta, nalpha, nbeta);
+        build_determinants(c, ndet, alpha, beta, nalpha, nbeta, false);
+        build_connectivity(c);
+        build_elements(c);
+        return HINQS_OK;
+    });
+}
+
+int hinqs_set_determinants_device(hinqs_ctx *ctx, int64_t ndet, const uint64_t *alpha,
+                                  const uint64_t *beta, int nalpha, int nbeta) {
+    return guarded(ctx, [&](Ctx &c) {
+        if (!c.have_ints) throw Error(HINQS_E_NOT_READY, "set integrals first (they fix norb)");
+        if (!alpha || !beta) throw Error(HINQS_E_INVALID_ARG, "null determinant pointer");
+        if (ndet < 1 || ndet >= ((int64_t)1 << 31) - 1)
+            throw Error(HINQS_E_INVALID_ARG, "ndet must be in [1, 2^31 - 2]");
+        if (nalpha < 0 || nbeta < 0 || nalpha > c.norb || nbeta > c.norb)
+            throw Error(HINQS_E_INVALID_ARG, "electron counts out of range");
+        build_determinants(c, ndet, alpha, beta, nalpha, nbeta, true);
         build_connectivity(c);
         build_elements(c);
         return HINQS_OK;

@@ -220,7 +220,7 @@ struct Ctx {
 // ------------------------------------------------------ internal entry points
 void build_integrals(Ctx &c, int norb, const double *h, const double *eri, double ecore);
 void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint64_t *beta, int na,
-                        int nb);
+                        int nb, bool on_device);
 void build_connectivity(Ctx &c);
 void build_elements(Ctx &c);
 void export_connectivity(Ctx &c, int64_t *rowptr_c, int32_t *col_c, uint32_t *desc_c);

@@ -36,7 +36,7 @@ constexpr int GRAM_MAX_BLOCKS = 1024;
 // partial[blk][a][b] = sum over this block's rows of A[i][a] * B[i][b]
 // (a < ma <= 16*MT, b < nb <= 16).  MFMA operand layout (16x16x4 f64):
 // lane l supplies A_mat[l%16][l/16] and B_mat[l/16][l%16] and receives
-// D[4*(l/16)+r][l%16] in element r.
+// D[l/16 + 4r][l%16] in element r of its 4-wide accumulator.
 template <int MT>
 __global__ __launch_bounds__(GRAM_BLOCK) void k_gram(int64_t nrows, const double *__restrict__ A,
                                                      int lda, int ma, const double *__restrict__ B,
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram(int64_t nrows, const double
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < GRAM_BLOCK / 64; ++w) s += red[w][t][ln][r];
-        const int a = t * 16 + 4 * (ln >> 4) + r;
+        const int a = t * 16 + (ln >> 4) + 4 * r;
         const int b = ln & 15;
         if (a < ma && b < nb) partial[(int64_t)blockIdx.x * ma * nb + a * nb + b] = s;
     }
@@ -422,7 +422,7 @@ struct Solver {
     int nblk_gram = 1;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double ms_sigma = 0.0;
-    int sigma_blocks = 0;
+    int sigma_blocks = 0, sigma_columns = 0;
 
     Solver(Ctx &cc, int k, int m_max) : c(cc), s(cc.stream), D(cc.ndet), K(k), mmax(m_max) {
         ld = mmax + K;
@@ -509,14 +509,33 @@ struct Solver {
         HQ_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
         ms_sigma += ms;
         ++sigma_blocks;
+        sigma_columns += nc;
     }
 
     // Orthonormalize T[:, 0:n] against V[:, 0:m] and within itself; returns the
-    // number of kept directions, written to V[:, m : m+kept].
+    // number of kept directions, written to V[:, m : m+kept].  Columns are first
+    // scaled to unit norm, so the thresholds below are relative: a direction is
+    // dropped when less than 1e-7 of it lies outside span(V) and the other
+    // new directions.
     int orthonormalize_into_v(int m, int n) {
         const int ldt = K;
-        double *C = small.p;  // m x n
-        int kept = n;
+        double *C = small.p;                   // m x n
+        double *Zd = small.p + 96 * 96;        // n x n
+        int kept = 0;
+        {
+            std::vector<double> g = gram_host(T.p, ldt, n, T.p, ldt, n);
+            std::vector<int> nz;
+            for (int q = 0; q < n; ++q) {
+                double d = g[(size_t)q * n + q];
+                if (std::isfinite(d) && d > 0.0) nz.push_back(q);
+            }
+            kept = (int)nz.size();
+            if (kept == 0) return 0;
+            std::vector<double> Dg((size_t)n * kept, 0.0);
+            for (int q = 0; q < kept; ++q) Dg[(size_t)nz[q] * kept + q] = 1.0 / std::sqrt(g[(size_t)nz[q] * n + nz[q]]);
+            upload_small(Dg, Zd);
+            tsmm(T.p, ldt, n, Zd, kept, 1.0, 0.0, T.p, ldt);
+        }
         for (int round = 0; round < 2; ++round) {
             if (m > 0) {
                 for (int pass = 0; pass < 2; ++pass) {
@@ -532,33 +551,25 @@ struct Solver {
                 }
             std::vector<double> w, Z;
             jacobi_eig(kept, g, w, Z);
-            double wmax = 0.0;
-            for (double x : w) wmax = std::max(wmax, x);
-            if (!(wmax > 0.0)) return 0;
+            const double thresh = round == 0 ? 1e-14 : 1e-4;
             std::vector<int> keep;
             for (int j = kept - 1; j >= 0; --j)  // largest first
-                if (w[j] > 1e-14 * std::max(wmax, 1e-300) && w[j] > 1e-300) keep.push_back(j);
-            if (round == 0) {
-                // drop directions that are numerically inside span(V)
-                std::vector<int> k2;
-                for (int j : keep)
-                    if (w[j] > 1e-24) k2.push_back(j);
-                keep.swap(k2);
-            }
-            int nk = (int)keep.size();
+                if (std::isfinite(w[j]) && w[j] > thresh) keep.push_back(j);
+            const int nk = (int)keep.size();
             if (nk == 0) return 0;
             std::vector<double> Zk((size_t)kept * nk);
             for (int a = 0; a < kept; ++a)
-                for (int q = 0; q < nk; ++q) Zk[(size_t)a * nk + q] = Z[(size_t)a * kept + keep[q]] / std::sqrt(w[keep[q]]);
-            upload_small(Zk, small.p + 96 * 96);
-            tsmm(T.p, ldt, kept, small.p + 96 * 96, nk, 1.0, 0.0, T.p, ldt);
+                for (int q = 0; q < nk; ++q)
+                    Zk[(size_t)a * nk + q] = Z[(size_t)a * kept + keep[q]] / std::sqrt(w[keep[q]]);
+            upload_small(Zk, Zd);
+            tsmm(T.p, ldt, kept, Zd, nk, 1.0, 0.0, T.p, ldt);
             kept = nk;
         }
         // append
         std::vector<double> eye((size_t)kept * kept, 0.0);
         for (int q = 0; q < kept; ++q) eye[(size_t)q * kept + q] = 1.0;
-        upload_small(eye, small.p + 96 * 96);
-        tsmm(T.p, ldt, kept, small.p + 96 * 96, kept, 1.0, 0.0, V.p + m, ld);
+        upload_small(eye, Zd);
+        tsmm(T.p, ldt, kept, Zd, kept, 1.0, 0.0, V.p + m, ld);
         return kept;
     }
 
@@ -768,7 +779,22 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
             S.tsmm(S.T.p, K, K, S.small.p + 96 * 96, nadd, 1.0, 0.0, S.T.p, K);
         }
         int kept = S.orthonormalize_into_v(m, nadd);
-        if (kept == 0) { converged = !fp32 && res0 <= 10 * o.tol; break; }
+        if (kept == 0) {
+            if (!fp32) break;  // no new direction: report the current Ritz pair, not converged
+            // FP32 images cannot resolve further directions: refine in FP64
+            std::vector<double> Yk((size_t)m * nroots_eff);
+            for (int a = 0; a < m; ++a)
+                for (int q = 0; q < nroots_eff; ++q) Yk[(size_t)a * nroots_eff + q] = Y[(size_t)a * K + q];
+            S.upload_small(Yk, S.small.p + 96 * 96);
+            S.tsmm(S.V.p, S.ld, m, S.small.p + 96 * 96, nroots_eff, 1.0, 0.0, S.V.p, S.ld);
+            fp32 = false;
+            m = nroots_eff;
+            S.apply_h(0, m, false);
+            std::fill(G.begin(), G.end(), 0.0);
+            load_g_block(0, m, m);
+            ++restarts;
+            continue;
+        }
         S.apply_h(m, kept, fp32);
         load_g_block(m, kept, m + kept);
         m += kept;
@@ -779,6 +805,7 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
         st->iterations = iters;
         st->iterations_fp32 = it_fp32;
         st->sigma_blocks = S.sigma_blocks;
+        st->sigma_columns = S.sigma_columns;
         st->restarts = restarts;
         st->residual = res0;
         st->ms_sigma = S.ms_sigma;

@@ -191,37 +191,69 @@ void scatter_rows(hipStream_t s, const void *src, void *dst, const int32_t *idx,
     row_copy(s, src, dst, idx, n, rowbytes, false);
 }
 
+namespace {
+
+// Checks every determinant (electron counts, no orbital >= norb) and narrows the
+// strings to uint32.  bad[0] receives the lowest offending index (INT64_MAX if
+// none), bad[1] a bit set: 1 = orbital >= norb, 2 = wrong electron count.
+__global__ void k_validate(const uint64_t *a64, const uint64_t *b64, int64_t n, int norb, int na, int nb,
+                           uint32_t *a32, uint32_t *b32, unsigned long long *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t full = (norb >= 64) ? ~0ull : ((1ull << norb) - 1ull);
+    const uint64_t a = a64[i], b = b64[i];
+    unsigned long long kind = 0;
+    if ((a & ~full) || (b & ~full)) kind |= 1ull;
+    if (__popcll(a) != na || __popcll(b) != nb) kind |= 2ull;
+    if (kind) {
+        atomicMin(&bad[0], (unsigned long long)i);
+        atomicOr(&bad[1], kind);
+    }
+    a32[i] = (uint32_t)a;
+    b32[i] = (uint32_t)b;
+}
+
+}  // namespace
+
 void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint64_t *beta, int na,
-                        int nb) {
+                        int nb, bool on_device) {
     const int norb = c.norb;
     auto t0 = std::chrono::steady_clock::now();
-    // ---- host validation (inputs are host arrays)
-    const uint64_t full = (norb >= 64) ? ~0ull : ((1ull << norb) - 1ull);
-    for (int64_t i = 0; i < ndet; ++i) {
-        uint64_t a = alpha[i], b = beta[i];
-        if ((a & ~full) || (b & ~full))
-            throw Error(HINQS_E_BAD_OCCUPATION, "determinant " + std::to_string(i) +
-                                                    " has an occupied orbital >= norb");
-        if (__builtin_popcountll(a) != na || __builtin_popcountll(b) != nb)
-            throw Error(HINQS_E_BAD_OCCUPATION,
-                        "determinant " + std::to_string(i) + " has the wrong electron count");
-    }
     c.have_dets = false;
     c.have_elements = false;
-    c.ndet = ndet;
-    c.na = na;
-    c.nb = nb;
     hipStream_t s = c.stream;
-    std::vector<uint32_t> ha(ndet), hb(ndet);
-    for (int64_t i = 0; i < ndet; ++i) {
-        ha[i] = (uint32_t)alpha[i];
-        hb[i] = (uint32_t)beta[i];
+    DBuf<uint64_t> up_a, up_b;
+    const uint64_t *da64 = alpha, *db64 = beta;
+    if (!on_device) {
+        up_a.ensure(ndet);
+        up_b.ensure(ndet);
+        HQ_CHECK(hipMemcpyAsync(up_a.p, alpha, 8 * ndet, hipMemcpyHostToDevice, s));
+        HQ_CHECK(hipMemcpyAsync(up_b.p, beta, 8 * ndet, hipMemcpyHostToDevice, s));
+        da64 = up_a.p;
+        db64 = up_b.p;
     }
     DBuf<uint32_t> da, db;
     da.ensure(ndet);
     db.ensure(ndet);
-    HQ_CHECK(hipMemcpyAsync(da.p, ha.data(), 4 * ndet, hipMemcpyHostToDevice, s));
-    HQ_CHECK(hipMemcpyAsync(db.p, hb.data(), 4 * ndet, hipMemcpyHostToDevice, s));
+    DBuf<unsigned long long> bad;
+    bad.ensure(2);
+    unsigned long long init[2] = {~0ull, 0ull};
+    HQ_CHECK(hipMemcpyAsync(bad.p, init, sizeof(init), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(ndet, 256)), dim3(256), 0, s, da64, db64, ndet, norb, na,
+                       nb, da.p, db.p, bad.p);
+    HQ_LAUNCH_CHECK();
+    unsigned long long hbad[2];
+    HQ_CHECK(hipMemcpyAsync(hbad, bad.p, sizeof(hbad), hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipStreamSynchronize(s));
+    if (hbad[1] & 1ull)
+        throw Error(HINQS_E_BAD_OCCUPATION, "determinant " + std::to_string(hbad[0]) +
+                                                " (or another) has an occupied orbital >= norb");
+    if (hbad[1] & 2ull)
+        throw Error(HINQS_E_BAD_OCCUPATION,
+                    "determinant " + std::to_string(hbad[0]) + " (or another) has the wrong electron count");
+    c.ndet = ndet;
+    c.na = na;
+    c.nb = nb;
 
     DBuf<uint64_t> keys;
     DBuf<int32_t> vals, flag, scan;
