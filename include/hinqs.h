@@ -73,7 +73,7 @@ typedef struct hinqs_ctx hinqs_ctx;
 
 typedef struct hinqs_opts {
     int    block;          /* Davidson block size k in {1,2,4,8,16}; default 8 */
-    int    max_space;      /* largest subspace before a thick restart; default 4*block */
+    int    max_space;      /* largest subspace before a thick restart, in [3*block, 96]; default 6*block */
     int    max_iter;       /* iteration cap; default 200 */
     double tol;            /* stop when ||H c - E c||_2 <= tol for the lowest root; default 1e-8 */
     int    precision;      /* HINQS_SOLVE_FP64 or HINQS_SOLVE_MIXED; default FP64 */

@@ -251,7 +251,7 @@ class Hinqs:
         o = Opts()
         self._lib.hinqs_opts_default(ctypes.byref(o))
         o.block = block
-        o.max_space = max_space if max_space is not None else 4 * block
+        o.max_space = max_space if max_space is not None else 6 * block
         o.max_iter = max_iter
         o.tol = tol
         o.precision = SOLVE_MIXED if mixed else SOLVE_FP64

@@ -54,7 +54,7 @@ extern "C" {
 void hinqs_opts_default(hinqs_opts *o) {
     if (!o) return;
     o->block = 8;
-    o->max_space = 32;
+    o->max_space = 48;
     o->max_iter = 200;
     o->tol = 1e-8;
     o->precision = HINQS_SOLVE_FP64;
@@ -142,7 +142,8 @@ int hinqs_sigma(hinqs_ctx *ctx, int k, const void *X, void *S, int precision, in
         const int K = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
         const bool sorted = (flags & HINQS_SORTED_ORDER) != 0;
         hipStream_t s = c.stream;
-        if (sorted && K == k) {
+        const bool aligned = ((uintptr_t)X % 16 == 0) && ((uintptr_t)S % 16 == 0);
+        if (sorted && K == k && aligned) {
             sigma_sorted(c, K, X, K, S, K, precision, s);
             return HINQS_OK;
         }

@@ -2,24 +2,33 @@
 // Step 3: "diagonalized with a Davidson eigensolver", warm-started from the
 // previous eigenvector).
 //
-// Basis V and images W = H V live in HBM as ndet x ld row-major arrays (one
-// determinant's coefficients contiguous), in sorted determinant order, so a
-// block of new columns is directly the strided X of the sigma kernel.
+// Storage.  The basis V and its images W = H V live in HBM column-blocked:
+// block b holds columns [bK, bK+K) as a contiguous ndet x K row-major array
+// (K = Davidson block size), in sorted determinant order.  New directions are
+// formed in a contiguous ndet x K array T, so every sigma product reads one
+// 64-byte row per coupling from a compact 8*K*ndet-byte array that stays in
+// the caches, and its output Wn is appended to W afterwards.
+//
 // Per iteration:
-//   G[:, new] = V^T W_new          FP64 MFMA (v_mfma_f64_16x16x4f64) partials,
-//                                  reduced in a fixed order (deterministic)
-//   Rayleigh-Ritz on G             host cyclic Jacobi (m <= 96)
+//   Rayleigh-Ritz on G = V^T W         host cyclic Jacobi (m <= 96)
 //   T = (W y - theta V y) / (theta - H_ii)   fused Ritz/residual/preconditioner
 //   CGS2 of T against V, then symmetric orthonormalization of T (eigen-
-//   decomposition of T^T T, nearly dependent directions dropped)
-//   W_new = H T                    sigma kernel
-// with a thick restart to the current Ritz vectors when the space is full.
+//   decomposition of T^T T; nearly dependent directions dropped)
+//   Wn = H T                           sigma kernel
+//   G[:, new] = V^T Wn                 FP64 MFMA (v_mfma_f64_16x16x4f64) partials
+//                                      reduced in a fixed order (deterministic)
+// Restart (GD+k): when the space is full it is replaced by an orthonormal
+// basis of the current Ritz vectors and those of the previous iteration,
+// which keeps the convergence of the unrestarted method far better than a
+// restart on the Ritz vectors alone.
 // MIXED precision: FP32 sigma products while the residual is above a switch
 // threshold (or stalls), then a restart on the Ritz vectors, W recomputed
 // with FP64 sigma, and FP64 iterations to the requested tolerance.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 
 #include "common.hpp"
@@ -30,18 +39,32 @@ namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int GRAM_BLOCK = 256;
-constexpr int GRAM_MAX_BLOCKS = 1024;
+// Column-blocked tall matrix: element (i, j) at p[(j / kb) * bs + i * kb + j % kb].
+// A plain row-major array with leading dimension ld is {p, ld, 0} with j < ld.
+struct Mat {
+    double *p;
+    int kb;
+    int64_t bs;
+    __host__ __device__ double *at(int64_t i, int j) const {
+        return p + (int64_t)(j / kb) * bs + i * kb + (j % kb);
+    }
+    __host__ __device__ Mat cols(int c0) const {  // view from column c0 (c0 % kb == 0)
+        return Mat{p + (int64_t)(c0 / kb) * bs, kb, bs};
+    }
+};
 
-// partial[blk][a][b] = sum over this block's rows of A[i][a] * B[i][b]
+constexpr int GRAM_BLOCK = 256;
+constexpr int GRAM_MAX_BLOCKS = 512;
+constexpr int GRAM_UNROLL = 4;
+
+// partial[blk][a][b] = sum over this block's rows of A(i, a) * B(i, b)
 // (a < ma <= 16*MT, b < nb <= 16).  MFMA operand layout (16x16x4 f64):
 // lane l supplies A_mat[l%16][l/16] and B_mat[l/16][l%16] and receives
-// D[l/16 + 4r][l%16] in element r of its 4-wide accumulator.
+// D[l/16 + 4r][l%16] in element r of its 4-wide accumulator.  Loads for
+// GRAM_UNROLL steps are issued before their MFMAs to keep loads in flight.
 template <int MT>
-__global__ __launch_bounds__(GRAM_BLOCK) void k_gram(int64_t nrows, const double *__restrict__ A,
-                                                     int lda, int ma, const double *__restrict__ B,
-                                                     int ldb, int nb, int64_t rows_per_wave,
-                                                     double *__restrict__ partial) {
+__global__ __launch_bounds__(GRAM_BLOCK) void k_gram(int64_t nrows, Mat A, int ma, Mat B, int nb,
+                                                     int64_t rows_per_wave, double *__restrict__ partial) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t gw = (int64_t)blockIdx.x * (GRAM_BLOCK / 64) + wave;
     const int64_t r0 = gw * rows_per_wave;
@@ -51,17 +74,24 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram(int64_t nrows, const double
 #pragma unroll
     for (int t = 0; t < MT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
     const bool bok = col < nb;
-
-    for (int64_t i = r0; i < r1; i += 4) {
-        const int64_t row = i + kk;
-        const bool rok = row < r1;
-        const double bv = (rok && bok) ? B[row * ldb + col] : 0.0;
+    for (int64_t i = r0; i < r1; i += 4 * GRAM_UNROLL) {
+        double bv[GRAM_UNROLL], av[GRAM_UNROLL][MT];
 #pragma unroll
-        for (int t = 0; t < MT; ++t) {
-            const int a = t * 16 + col;
-            const double av = (rok && a < ma) ? A[row * lda + a] : 0.0;
-            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+        for (int u = 0; u < GRAM_UNROLL; ++u) {
+            const int64_t row = i + 4 * u + kk;
+            const bool rok = row < r1;
+            bv[u] = (rok && bok) ? *B.at(row, col) : 0.0;
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
+                const int a = t * 16 + col;
+                av[u][t] = (rok && a < ma) ? *A.at(row, a) : 0.0;
+            }
         }
+#pragma unroll
+        for (int u = 0; u < GRAM_UNROLL; ++u)
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][t], bv[u], acc[t], 0, 0, 0);
     }
     __shared__ double red[GRAM_BLOCK / 64][MT][64][4];
 #pragma unroll
@@ -80,33 +110,37 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram(int64_t nrows, const double
     }
 }
 
-// out[e] = sum_blk partial[blk][e], fixed order.
-__global__ void k_sum_partials(const double *partial, int nblk, int n, double *out) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
+// out[e] = sum_blk partial[blk][e]: one workgroup per output, fixed-shape tree.
+__global__ __launch_bounds__(256) void k_reduce_partials(const double *__restrict__ partial, int nblk,
+                                                         int n, double *__restrict__ out) {
+    __shared__ double red[256];
+    const int e = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * n + e];
-    out[e] = s;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += partial[(int64_t)b * n + e];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[e] = red[0];
 }
 
 // Fused Ritz vector, residual, norm and diagonal preconditioner for KK roots:
 //   r_c = W y_c - theta_c V y_c,   T[:, c] = r_c / clamp(theta_c - H_ii)
-// partial[blk][c] = sum over the block's rows of r_c^2.  Rows of V and W are
-// staged through LDS in 16-column chunks (coalesced loads); thread (r, c)
-// owns row r of the tile and root c.
-constexpr int JC = 16;
-
+// partial[blk][c] = sum over the block's rows of r_c^2.  One column block of
+// V and W (ROWS x KK, contiguous) is staged through LDS at a time; thread
+// (r, c) owns row r of the tile and root c.
 template <int KK>
-__global__ __launch_bounds__(256) void k_ritz(int64_t nrows, int m, const double *__restrict__ V,
-                                              const double *__restrict__ W, int ld,
+__global__ __launch_bounds__(256) void k_ritz(int64_t nrows, int m, Mat V, Mat W,
                                               const double *__restrict__ Y,
                                               const double *__restrict__ theta,
                                               const double *__restrict__ diag, double floor_,
-                                              int nroots, double *__restrict__ T, int ldt,
+                                              int nroots, double *__restrict__ T,
                                               double *__restrict__ partial) {
     constexpr int ROWS = 256 / KK;
-    __shared__ double sV[ROWS * JC];
-    __shared__ double sW[ROWS * JC];
+    __shared__ double sV[ROWS * KK];
+    __shared__ double sW[ROWS * KK];
     __shared__ double sY[96 * KK];
     __shared__ double red[256];
     for (int t = threadIdx.x; t < m * KK; t += 256) sY[t] = Y[t];
@@ -115,30 +149,33 @@ __global__ __launch_bounds__(256) void k_ritz(int64_t nrows, int m, const double
     double nrm = 0.0;
     for (int64_t i0 = (int64_t)blockIdx.x * ROWS; i0 < nrows; i0 += (int64_t)gridDim.x * ROWS) {
         double x = 0.0, w = 0.0;
-        for (int j0 = 0; j0 < m; j0 += JC) {
-            const int jn = min(JC, m - j0);
+        for (int j0 = 0; j0 < m; j0 += KK) {
+            const int jn = min(KK, m - j0);
             __syncthreads();
-            for (int f = threadIdx.x; f < ROWS * JC; f += 256) {
-                const int rr = f / JC, j = f % JC;
-                const int64_t row = i0 + rr;
-                const bool ok = row < nrows && j < jn;
-                sV[f] = ok ? V[row * ld + j0 + j] : 0.0;
-                sW[f] = ok ? W[row * ld + j0 + j] : 0.0;
+            {
+                const int64_t row = i0 + r;
+                const bool ok = row < nrows && c < jn;
+                sV[threadIdx.x] = ok ? *V.at(row, j0 + c) : 0.0;
+                sW[threadIdx.x] = ok ? *W.at(row, j0 + c) : 0.0;
             }
             __syncthreads();
             for (int j = 0; j < jn; ++j) {
                 const double y = sY[(j0 + j) * KK + c];
-                x += sV[r * JC + j] * y;
-                w += sW[r * JC + j] * y;
+                x += sV[r * KK + j] * y;
+                w += sW[r * KK + j] * y;
             }
         }
         const int64_t row = i0 + r;
-        if (row < nrows && c < nroots) {
-            const double res = w - th * x;
-            nrm += res * res;
-            double den = th - diag[row];
-            if (fabs(den) < floor_) den = den < 0.0 ? -floor_ : floor_;
-            T[row * ldt + c] = res / den;
+        if (row < nrows) {
+            double out = 0.0;
+            if (c < nroots) {
+                const double res = w - th * x;
+                nrm += res * res;
+                double den = th - diag[row];
+                if (fabs(den) < floor_) den = den < 0.0 ? -floor_ : floor_;
+                out = res / den;
+            }
+            T[row * KK + c] = out;
         }
     }
     __syncthreads();
@@ -151,55 +188,64 @@ __global__ __launch_bounds__(256) void k_ritz(int64_t nrows, int m, const double
     }
 }
 
-// Out[i, c] = beta * Out[i, c] + alpha * sum_j A[i, j] B[j, c],  c < nc <= NC, j < m <= 96.
-// Every global read of a tile's A rows precedes (across a barrier) every
-// write of the tile, so Out may alias A (in-place basis rotation, nc <= m).
+// Out(i, c) = beta * Out(i, c) + alpha * sum_j A(i, j) B[j][c],  c < nc <= NC, j < m <= 96.
+// A is read one column block (kb <= 16 columns) at a time through LDS.  Every
+// global read of a tile's A rows precedes (across a barrier) every write of
+// the tile, so Out may alias A (in-place basis rotation, nc <= m).
 template <int NC>
-__global__ __launch_bounds__(256) void k_tsmm(int64_t nrows, int m, const double *A, int lda,
-                                              const double *__restrict__ B, int nc, double alpha,
-                                              double beta, double *Out, int ldo) {
+__global__ __launch_bounds__(256) void k_tsmm(int64_t nrows, int m, Mat A, const double *__restrict__ B,
+                                              int nc, double alpha, double beta, Mat Out) {
     constexpr int ROWS = 256 / NC;
-    __shared__ double sA[ROWS * JC];
+    __shared__ double sA[ROWS * 16];
     __shared__ double sB[96 * NC];
     for (int t = threadIdx.x; t < m * NC; t += 256) {
         const int j = t / NC, cc = t % NC;
         sB[t] = cc < nc ? B[j * nc + cc] : 0.0;
     }
     const int r = threadIdx.x / NC, c = threadIdx.x % NC;
+    const int kb = A.kb;
     for (int64_t i0 = (int64_t)blockIdx.x * ROWS; i0 < nrows; i0 += (int64_t)gridDim.x * ROWS) {
         double acc = 0.0;
-        for (int j0 = 0; j0 < m; j0 += JC) {
-            const int jn = min(JC, m - j0);
+        for (int j0 = 0; j0 < m; j0 += kb) {
+            const int jn = min(kb, m - j0);
             __syncthreads();
-            for (int f = threadIdx.x; f < ROWS * JC; f += 256) {
-                const int rr = f / JC, j = f % JC;
+            for (int f = threadIdx.x; f < ROWS * kb; f += 256) {
+                const int rr = f / kb, j = f % kb;
                 const int64_t row = i0 + rr;
-                sA[f] = (row < nrows && j < jn) ? A[row * lda + j0 + j] : 0.0;
+                sA[rr * 16 + j] = (row < nrows && j < jn) ? *A.at(row, j0 + j) : 0.0;
             }
             __syncthreads();
-            for (int j = 0; j < jn; ++j) acc += sA[r * JC + j] * sB[(j0 + j) * NC + c];
+            for (int j = 0; j < jn; ++j) acc += sA[r * 16 + j] * sB[(j0 + j) * NC + c];
         }
         __syncthreads();  // all reads of this tile's A rows are done
         const int64_t row = i0 + r;
         if (row < nrows && c < nc) {
-            double *o = Out + row * ldo + c;
+            double *o = Out.at(row, c);
             *o = (beta == 0.0 ? 0.0 : beta * *o) + alpha * acc;
         }
     }
 }
 
-// Columns [c0, c0+nc) of an ndet x ld array set to zero, except unit entries
-// at rows idx[c] (idx may be null).
-__global__ void k_unit_columns(int64_t nrows, double *V, int ld, int c0, int nc, const int32_t *idx) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nrows) return;
-    for (int c = 0; c < nc; ++c) V[i * ld + c0 + c] = (idx && idx[c] == i) ? 1.0 : 0.0;
+// dst(i, c0 + c) = src[i * K + c] for c < nc.
+__global__ void k_put_columns(int64_t nrows, const double *src, int K, int nc, Mat dst, int c0) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrows * K) return;
+    const int64_t i = t / K;
+    const int c = (int)(t % K);
+    if (c < nc) *dst.at(i, c0 + c) = src[t];
 }
 
-__global__ void k_copy_column(int64_t nrows, const double *src, double *V, int ld, int c) {
+// Columns [c0, c0+nc) of a row-major ndet x K array: unit entries at rows idx[c].
+__global__ void k_unit_columns(int64_t nrows, double *T, int K, int c0, int nc, const int32_t *idx) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nrows) return;
-    V[i * ld + c] = src[i];
+    for (int c = 0; c < nc; ++c) T[i * K + c0 + c] = (idx[c] == i) ? 1.0 : 0.0;
+}
+
+__global__ void k_copy_column(int64_t nrows, const double *src, double *T, int K, int c) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    T[i * K + c] = src[i];
 }
 
 // Lexicographic (value, index) minimum of diag over rows not in excl[0..nex).
@@ -309,27 +355,27 @@ __global__ void k_finalize(int64_t nrows, const double *x, double scale, const d
     out[perm ? perm[i] : i] = v;
 }
 
-// X32[i, c] = (float) V[i, c0 + c] for c < nc, zero for nc <= c < K32.
-__global__ void k_to_f32(int64_t nrows, const double *V, int ld, int c0, int nc, float *X, int K32) {
+__global__ void k_to_f32(int64_t n, const double *x, float *y) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nrows * K32) return;
-    int64_t i = t / K32;
-    int c = (int)(t % K32);
-    X[t] = c < nc ? (float)V[i * ld + c0 + c] : 0.0f;
+    if (t < n) y[t] = (float)x[t];
 }
 
-__global__ void k_from_f32(int64_t nrows, const float *S, int K32, double *W, int ld, int c0, int nc) {
+__global__ void k_to_f64(int64_t n, const float *x, double *y) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nrows * K32) return;
-    int64_t i = t / K32;
-    int c = (int)(t % K32);
-    if (c < nc) W[i * ld + c0 + c] = (double)S[t];
+    if (t < n) y[t] = (double)x[t];
+}
+
+// ------------------------------------------------------------ host helpers
+
+int gram_blocks_for(int64_t nrows) {
+    int64_t waves = (nrows + 63) / 64;
+    return (int)std::min<int64_t>(GRAM_MAX_BLOCKS, std::max<int64_t>(1, (waves + 3) / 4));
 }
 
 // G (ma x nb) = A^T B over nrows rows: MFMA partials per block, then a
 // fixed-order reduction.  partial must hold nblk * ma * nb doubles.
-void launch_gram(hipStream_t s, int64_t nrows, int nblk, const double *A, int lda, int ma,
-                 const double *B, int ldb, int nb, double *partial, double *out) {
+void launch_gram(hipStream_t s, int64_t nrows, int nblk, Mat A, int ma, Mat B, int nb, double *partial,
+                 double *out) {
     if (nb > 16 || ma > 96 || ma < 1 || nb < 1) throw Error(HINQS_E_UNSUPPORTED, "Gram block shape");
     int64_t waves = (int64_t)nblk * (GRAM_BLOCK / 64);
     int64_t rpw = (nrows + waves - 1) / waves;
@@ -337,25 +383,18 @@ void launch_gram(hipStream_t s, int64_t nrows, int nblk, const double *A, int ld
     const int mt = (ma + 15) / 16;
     dim3 g(nblk), b(GRAM_BLOCK);
     switch (mt) {
-        case 1: hipLaunchKernelGGL(k_gram<1>, g, b, 0, s, nrows, A, lda, ma, B, ldb, nb, rpw, partial); break;
-        case 2: hipLaunchKernelGGL(k_gram<2>, g, b, 0, s, nrows, A, lda, ma, B, ldb, nb, rpw, partial); break;
-        case 3: hipLaunchKernelGGL(k_gram<3>, g, b, 0, s, nrows, A, lda, ma, B, ldb, nb, rpw, partial); break;
-        case 4: hipLaunchKernelGGL(k_gram<4>, g, b, 0, s, nrows, A, lda, ma, B, ldb, nb, rpw, partial); break;
-        case 5: hipLaunchKernelGGL(k_gram<5>, g, b, 0, s, nrows, A, lda, ma, B, ldb, nb, rpw, partial); break;
-        default: hipLaunchKernelGGL(k_gram<6>, g, b, 0, s, nrows, A, lda, ma, B, ldb, nb, rpw, partial); break;
+        case 1: hipLaunchKernelGGL(k_gram<1>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial); break;
+        case 2: hipLaunchKernelGGL(k_gram<2>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial); break;
+        case 3: hipLaunchKernelGGL(k_gram<3>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial); break;
+        case 4: hipLaunchKernelGGL(k_gram<4>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial); break;
+        case 5: hipLaunchKernelGGL(k_gram<5>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial); break;
+        default: hipLaunchKernelGGL(k_gram<6>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial); break;
     }
     HQ_LAUNCH_CHECK();
     const int n = ma * nb;
-    hipLaunchKernelGGL(k_sum_partials, dim3((n + 255) / 256), dim3(256), 0, s, partial, nblk, n, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(n), dim3(256), 0, s, partial, nblk, n, out);
     HQ_LAUNCH_CHECK();
 }
-
-int gram_blocks_for(int64_t nrows) {
-    int64_t waves = (nrows + 63) / 64;
-    return (int)std::min<int64_t>(GRAM_MAX_BLOCKS, std::max<int64_t>(1, (waves + 3) / 4));
-}
-
-// ------------------------------------------------------------ host helpers
 
 // Cyclic Jacobi eigendecomposition of a symmetric n x n matrix (row-major).
 // Eigenvalues ascending in w; eigenvectors as columns of Z (row-major n x n).
@@ -406,14 +445,46 @@ void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w, std::vecto
     }
 }
 
+// Orthonormal basis (modified Gram-Schmidt, twice) of the columns of the
+// m x q row-major matrix M; columns whose remaining norm falls below `drop`
+// times their original norm are dropped.  Returns m x qk row-major.
+std::vector<double> small_orth(int m, int q, const std::vector<double> &M, double drop, int &qk) {
+    std::vector<std::vector<double>> cols;
+    for (int c = 0; c < q; ++c) {
+        std::vector<double> v(m);
+        double n0 = 0.0;
+        for (int a = 0; a < m; ++a) { v[a] = M[(size_t)a * q + c]; n0 += v[a] * v[a]; }
+        n0 = std::sqrt(n0);
+        if (!(n0 > 0.0)) continue;
+        for (int pass = 0; pass < 2; ++pass)
+            for (const auto &u : cols) {
+                double d = 0.0;
+                for (int a = 0; a < m; ++a) d += u[a] * v[a];
+                for (int a = 0; a < m; ++a) v[a] -= d * u[a];
+            }
+        double n1 = 0.0;
+        for (int a = 0; a < m; ++a) n1 += v[a] * v[a];
+        n1 = std::sqrt(n1);
+        if (n1 <= drop * n0) continue;
+        for (int a = 0; a < m; ++a) v[a] /= n1;
+        cols.push_back(v);
+    }
+    qk = (int)cols.size();
+    std::vector<double> Q((size_t)m * qk);
+    for (int c = 0; c < qk; ++c)
+        for (int a = 0; a < m; ++a) Q[(size_t)a * qk + c] = cols[c][a];
+    return Q;
+}
+
 struct Solver {
     Ctx &c;
     hipStream_t s;
     int64_t D;
     int K;        // block size (compile-time kernel variant)
     int mmax;     // largest subspace
-    int ld;       // leading dimension of V, W
-    DBuf<double> V, W, T, small, partial, nrm;
+    int nblocks;  // column blocks of V and W
+    DBuf<double> Vb, Wb, T, Wn, small, partial, nrm;
+    Mat V{}, W{}, Tm{}, Wnm{};
     DBuf<float> X32, S32;
     DBuf<int32_t> guess_idx;
     DBuf<double> argv;
@@ -425,18 +496,24 @@ struct Solver {
     int sigma_blocks = 0, sigma_columns = 0;
 
     Solver(Ctx &cc, int k, int m_max) : c(cc), s(cc.stream), D(cc.ndet), K(k), mmax(m_max) {
-        ld = mmax + K;
-        if (ld % 2) ++ld;
-        V.ensure((size_t)D * ld);
-        W.ensure((size_t)D * ld);
-        T.ensure((size_t)D * K);
-        small.ensure(96 * 96 + 4096);
+        nblocks = (mmax + K - 1) / K;
+        const size_t bsz = (size_t)D * K;
+        Vb.ensure(bsz * nblocks);
+        Wb.ensure(bsz * nblocks);
+        T.ensure(bsz);
+        Wn.ensure(bsz);
+        V = Mat{Vb.p, K, (int64_t)bsz};
+        W = Mat{Wb.p, K, (int64_t)bsz};
+        Tm = Mat{T.p, K, (int64_t)bsz};
+        Wnm = Mat{Wn.p, K, (int64_t)bsz};
+        small.ensure(96 * 96 * 2 + 4096);
         nblk_gram = gram_blocks_for(D);
         partial.ensure(std::max<size_t>((size_t)nblk_gram * 96 * 16, 2048 * 16) + 4096);
         nrm.ensure(64);
-        HQ_CHECK(hipMemsetAsync(V.p, 0, sizeof(double) * (size_t)D * ld, s));
-        HQ_CHECK(hipMemsetAsync(W.p, 0, sizeof(double) * (size_t)D * ld, s));
-        HQ_CHECK(hipMemsetAsync(T.p, 0, sizeof(double) * (size_t)D * K, s));
+        HQ_CHECK(hipMemsetAsync(Vb.p, 0, sizeof(double) * bsz * nblocks, s));
+        HQ_CHECK(hipMemsetAsync(Wb.p, 0, sizeof(double) * bsz * nblocks, s));
+        HQ_CHECK(hipMemsetAsync(T.p, 0, sizeof(double) * bsz, s));
+        HQ_CHECK(hipMemsetAsync(Wn.p, 0, sizeof(double) * bsz, s));
         HQ_CHECK(hipEventCreate(&ev0));
         HQ_CHECK(hipEventCreate(&ev1));
     }
@@ -445,37 +522,40 @@ struct Solver {
         if (ev1) (void)hipEventDestroy(ev1);
     }
 
-    // G (ma x nb, row-major, device `out`) = A^T B over all rows.
-    void gram(const double *A, int lda, int ma, const double *B, int ldb, int nb, double *out) {
-        launch_gram(s, D, nblk_gram, A, lda, ma, B, ldb, nb, partial.p, out);
+    // small.p regions: [0, 96*96) gram outputs / Y, [96*96, 2*96*96) coefficient uploads
+    double *scratch_a() { return small.p; }
+    double *scratch_b() { return small.p + 96 * 96; }
+
+    void gram(Mat A, int ma, Mat B, int nb, double *out) {
+        launch_gram(s, D, nblk_gram, A, ma, B, nb, partial.p, out);
     }
 
-    std::vector<double> gram_host(const double *A, int lda, int ma, const double *B, int ldb, int nb) {
-        gram(A, lda, ma, B, ldb, nb, small.p);
+    std::vector<double> gram_host(Mat A, int ma, Mat B, int nb) {
+        gram(A, ma, B, nb, scratch_a());
         std::vector<double> h((size_t)ma * nb);
-        HQ_CHECK(hipMemcpyAsync(h.data(), small.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+        HQ_CHECK(hipMemcpyAsync(h.data(), scratch_a(), sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
         HQ_CHECK(hipStreamSynchronize(s));
         return h;
     }
 
-    // Out[:, 0:nc] = beta Out + alpha A[:, 0:m] Bsmall (m x nc, device)
-    void tsmm(const double *A, int lda, int m, const double *Bs, int nc, double alpha, double beta,
-              double *Out, int ldo) {
+    // Out[:, 0:nc] = beta Out + alpha A[:, 0:m] Bs (m x nc row-major, device)
+    void tsmm(Mat A, int m, const double *Bs, int nc, double alpha, double beta, Mat Out) {
         if (m <= 0 || nc <= 0) return;
-        int NC = nc <= 1 ? 1 : nc <= 2 ? 2 : nc <= 4 ? 4 : nc <= 8 ? 8 : 16;
-        if (nc > 16) throw Error(HINQS_E_UNSUPPORTED, "tsmm width");
+        if (nc > 32) throw Error(HINQS_E_UNSUPPORTED, "tsmm width");
         if (m > 96) throw Error(HINQS_E_UNSUPPORTED, "tsmm depth");
-        const size_t lds = 0;
-        int rows = 256 / NC;
-        int64_t tiles = (D + rows - 1) / rows;
-        unsigned grid = (unsigned)std::min<int64_t>(tiles, 4096);
+        if (A.kb > 16) throw Error(HINQS_E_UNSUPPORTED, "tsmm column block");
+        const int NC = nc <= 1 ? 1 : nc <= 2 ? 2 : nc <= 4 ? 4 : nc <= 8 ? 8 : nc <= 16 ? 16 : 32;
+        const int rows = 256 / NC;
+        const int64_t tiles = (D + rows - 1) / rows;
+        const unsigned grid = (unsigned)std::min<int64_t>(tiles, 4096);
         dim3 g(grid), b(256);
         switch (NC) {
-            case 1: hipLaunchKernelGGL(k_tsmm<1>, g, b, lds, s, D, m, A, lda, Bs, nc, alpha, beta, Out, ldo); break;
-            case 2: hipLaunchKernelGGL(k_tsmm<2>, g, b, lds, s, D, m, A, lda, Bs, nc, alpha, beta, Out, ldo); break;
-            case 4: hipLaunchKernelGGL(k_tsmm<4>, g, b, lds, s, D, m, A, lda, Bs, nc, alpha, beta, Out, ldo); break;
-            case 8: hipLaunchKernelGGL(k_tsmm<8>, g, b, lds, s, D, m, A, lda, Bs, nc, alpha, beta, Out, ldo); break;
-            default: hipLaunchKernelGGL(k_tsmm<16>, g, b, lds, s, D, m, A, lda, Bs, nc, alpha, beta, Out, ldo); break;
+            case 1: hipLaunchKernelGGL(k_tsmm<1>, g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
+            case 2: hipLaunchKernelGGL(k_tsmm<2>, g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
+            case 4: hipLaunchKernelGGL(k_tsmm<4>, g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
+            case 8: hipLaunchKernelGGL(k_tsmm<8>, g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
+            case 16: hipLaunchKernelGGL(k_tsmm<16>, g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
+            default: hipLaunchKernelGGL(k_tsmm<32>, g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
         }
         HQ_LAUNCH_CHECK();
     }
@@ -486,21 +566,25 @@ struct Solver {
         HQ_CHECK(hipStreamSynchronize(s));
     }
 
-    // W[:, c0:c0+nc] = H V[:, c0:c0+nc]
-    void apply_h(int c0, int nc, bool fp32) {
+    void put_columns(const double *src, int nc, Mat dst, int c0) {
+        const int64_t n = D * K;
+        hipLaunchKernelGGL(k_put_columns, dim3(grid_for(n, 256)), dim3(256), 0, s, D, src, K, nc, dst, c0);
+        HQ_LAUNCH_CHECK();
+    }
+
+    // Wn = H X for a contiguous ndet x K block X (columns >= nc are zero).
+    void apply_h(const double *X, int nc, bool fp32) {
         HQ_CHECK(hipEventRecord(ev0, s));
         if (!fp32) {
-            sigma_sorted(c, K, V.p + c0, ld, W.p + c0, ld, HINQS_FP64, s);
+            sigma_sorted(c, K, X, K, Wn.p, K, HINQS_FP64, s);
         } else {
             X32.ensure((size_t)D * K);
             S32.ensure((size_t)D * K);
-            int64_t n = D * K;
-            hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n, 256)), dim3(256), 0, s, D, V.p, ld, c0, nc,
-                               X32.p, K);
+            const int64_t n = D * K;
+            hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n, 256)), dim3(256), 0, s, n, X, X32.p);
             HQ_LAUNCH_CHECK();
             sigma_sorted(c, K, X32.p, K, S32.p, K, HINQS_FP32, s);
-            hipLaunchKernelGGL(k_from_f32, dim3(grid_for(n, 256)), dim3(256), 0, s, D, S32.p, K, W.p, ld,
-                               c0, nc);
+            hipLaunchKernelGGL(k_to_f64, dim3(grid_for(n, 256)), dim3(256), 0, s, n, S32.p, Wn.p);
             HQ_LAUNCH_CHECK();
         }
         HQ_CHECK(hipEventRecord(ev1, s));
@@ -513,17 +597,16 @@ struct Solver {
     }
 
     // Orthonormalize T[:, 0:n] against V[:, 0:m] and within itself; returns the
-    // number of kept directions, written to V[:, m : m+kept].  Columns are first
-    // scaled to unit norm, so the thresholds below are relative: a direction is
-    // dropped when less than 1e-7 of it lies outside span(V) and the other
-    // new directions.
-    int orthonormalize_into_v(int m, int n) {
-        const int ldt = K;
-        double *C = small.p;                   // m x n
-        double *Zd = small.p + 96 * 96;        // n x n
+    // number of kept directions, left in T[:, 0:kept] (other columns zeroed).
+    // Columns are first scaled to unit norm, so the thresholds are relative: a
+    // direction is dropped when less than 1e-7 of it lies outside span(V) and
+    // the other new directions.
+    int orthonormalize(int m, int n) {
+        double *C = scratch_a();   // m x n
+        double *Zd = scratch_b();  // K x K
         int kept = 0;
         {
-            std::vector<double> g = gram_host(T.p, ldt, n, T.p, ldt, n);
+            std::vector<double> g = gram_host(Tm, n, Tm, n);
             std::vector<int> nz;
             for (int q = 0; q < n; ++q) {
                 double d = g[(size_t)q * n + q];
@@ -531,19 +614,20 @@ struct Solver {
             }
             kept = (int)nz.size();
             if (kept == 0) return 0;
-            std::vector<double> Dg((size_t)n * kept, 0.0);
-            for (int q = 0; q < kept; ++q) Dg[(size_t)nz[q] * kept + q] = 1.0 / std::sqrt(g[(size_t)nz[q] * n + nz[q]]);
+            std::vector<double> Dg((size_t)K * K, 0.0);
+            for (int q = 0; q < kept; ++q)
+                Dg[(size_t)nz[q] * K + q] = 1.0 / std::sqrt(g[(size_t)nz[q] * n + nz[q]]);
             upload_small(Dg, Zd);
-            tsmm(T.p, ldt, n, Zd, kept, 1.0, 0.0, T.p, ldt);
+            tsmm(Tm, K, Zd, K, 1.0, 0.0, Tm);
         }
         for (int round = 0; round < 2; ++round) {
             if (m > 0) {
                 for (int pass = 0; pass < 2; ++pass) {
-                    gram(V.p, ld, m, T.p, ldt, kept, C);
-                    tsmm(V.p, ld, m, C, kept, -1.0, 1.0, T.p, ldt);
+                    gram(V, m, Tm, kept, C);
+                    tsmm(V, m, C, kept, -1.0, 1.0, Tm);
                 }
             }
-            std::vector<double> g = gram_host(T.p, ldt, kept, T.p, ldt, kept);
+            std::vector<double> g = gram_host(Tm, kept, Tm, kept);
             for (int a = 0; a < kept; ++a)
                 for (int b = a + 1; b < kept; ++b) {
                     double v = 0.5 * (g[(size_t)a * kept + b] + g[(size_t)b * kept + a]);
@@ -557,19 +641,16 @@ struct Solver {
                 if (std::isfinite(w[j]) && w[j] > thresh) keep.push_back(j);
             const int nk = (int)keep.size();
             if (nk == 0) return 0;
-            std::vector<double> Zk((size_t)kept * nk);
+            // K x K transform: rows >= kept and columns >= nk are zero, so the
+            // unused columns of T are cleared as well
+            std::vector<double> Zk((size_t)K * K, 0.0);
             for (int a = 0; a < kept; ++a)
                 for (int q = 0; q < nk; ++q)
-                    Zk[(size_t)a * nk + q] = Z[(size_t)a * kept + keep[q]] / std::sqrt(w[keep[q]]);
+                    Zk[(size_t)a * K + q] = Z[(size_t)a * kept + keep[q]] / std::sqrt(w[keep[q]]);
             upload_small(Zk, Zd);
-            tsmm(T.p, ldt, kept, Zd, nk, 1.0, 0.0, T.p, ldt);
+            tsmm(Tm, K, Zd, K, 1.0, 0.0, Tm);
             kept = nk;
         }
-        // append
-        std::vector<double> eye((size_t)kept * kept, 0.0);
-        for (int q = 0; q < kept; ++q) eye[(size_t)q * kept + q] = 1.0;
-        upload_small(eye, Zd);
-        tsmm(T.p, ldt, kept, Zd, kept, 1.0, 0.0, V.p + m, ld);
         return kept;
     }
 
@@ -591,9 +672,10 @@ struct Solver {
     void finalize(int m, const std::vector<double> &y0, double *out, bool sorted) {
         xfin.ensure(D);
         signbuf.ensure(1);
-        upload_small(y0, small.p);
-        tsmm(V.p, ld, m, small.p, 1, 1.0, 0.0, xfin.p, 1);
-        std::vector<double> nn = gram_host(xfin.p, 1, 1, xfin.p, 1, 1);
+        upload_small(y0, scratch_b());
+        Mat X{xfin.p, 1, (int64_t)D};
+        tsmm(V, m, scratch_b(), 1, 1.0, 0.0, X);
+        std::vector<double> nn = gram_host(X, 1, X, 1);
         double scale = nn[0] > 0 ? 1.0 / std::sqrt(nn[0]) : 1.0;
         unsigned nblk = (unsigned)std::min<int64_t>(grid_for(D, 256), 1024);
         argv.ensure(nblk);
@@ -613,8 +695,8 @@ struct Solver {
 template <int KK>
 void launch_ritz(Solver &S, int m, const double *Yd, const double *thd, double floor_, int nroots,
                  unsigned grid) {
-    hipLaunchKernelGGL(k_ritz<KK>, dim3(grid), dim3(256), 0, S.s, S.D, m, S.V.p, S.W.p, S.ld, Yd, thd,
-                       S.c.diag.p, floor_, nroots, S.T.p, S.K, S.partial.p);
+    hipLaunchKernelGGL(k_ritz<KK>, dim3(grid), dim3(256), 0, S.s, S.D, m, S.V, S.W, Yd, thd, S.c.diag.p,
+                       floor_, nroots, S.T.p, S.partial.p);
     HQ_LAUNCH_CHECK();
 }
 
@@ -624,35 +706,39 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
              hinqs_stats *st) {
     auto t0 = std::chrono::steady_clock::now();
     const int64_t D = c.ndet;
-    int K = o.block;
+    const int K = o.block;
     if (K != 1 && K != 2 && K != 4 && K != 8 && K != 16)
         throw Error(HINQS_E_UNSUPPORTED, "block size must be 1, 2, 4, 8 or 16");
-    int mmax = o.max_space > 0 ? o.max_space : 4 * K;
-    if (mmax < 2 * K) mmax = 2 * K;
-    if (mmax + K > 96) throw Error(HINQS_E_UNSUPPORTED, "max_space + block must be <= 96");
+    int mmax = o.max_space > 0 ? o.max_space : 6 * K;
+    if (mmax < 3 * K) mmax = 3 * K;
+    if (mmax > 96) throw Error(HINQS_E_UNSUPPORTED, "max_space must be <= 96 (and >= 3 * block)");
     const bool sorted = (o.flags & HINQS_SORTED_ORDER) != 0;
     const int kroots = (int)std::min<int64_t>(K, D);  // roots tracked
     Solver S(c, K, mmax);
     hipStream_t s = c.stream;
     bool fp32 = (o.precision == HINQS_SOLVE_MIXED);
     int it_fp32 = 0, restarts = 0, iters = 0;
+    const int maxit = o.max_iter > 0 ? o.max_iter : 200;
+    const char *vb = std::getenv("HINQS_VERBOSE");
+    const bool verbose = vb && vb[0] && vb[0] != '0';
 
     // ---- initial block: warm start + lowest-diagonal unit vectors
     S.guess_idx.ensure(K + 1);
-    int nunit = guess ? kroots - 1 : kroots;
+    const int nunit = guess ? kroots - 1 : kroots;
     S.lowest_diag_indices(nunit, S.guess_idx.p);
     int n0 = 0;
     if (guess) {
-        if (sorted) hipLaunchKernelGGL(k_copy_column, dim3(grid_for(D, 256)), dim3(256), 0, s, D, guess, S.T.p, K, 0);
-        else {
-            // gather caller-order guess into sorted order: T[i, 0] = guess[perm[i]]
+        if (sorted) {
+            hipLaunchKernelGGL(k_copy_column, dim3(grid_for(D, 256)), dim3(256), 0, s, D, guess, S.T.p, K, 0);
+            HQ_LAUNCH_CHECK();
+        } else {
             DBuf<double> tmp;
             tmp.ensure(D);
             gather_rows(s, guess, tmp.p, c.perm.p, D, 8);
             hipLaunchKernelGGL(k_copy_column, dim3(grid_for(D, 256)), dim3(256), 0, s, D, tmp.p, S.T.p, K, 0);
+            HQ_LAUNCH_CHECK();
             HQ_CHECK(hipStreamSynchronize(s));
         }
-        HQ_LAUNCH_CHECK();
         n0 = 1;
     }
     if (nunit > 0) {
@@ -660,20 +746,19 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
                            S.guess_idx.p);
         HQ_LAUNCH_CHECK();
     }
-    int m = S.orthonormalize_into_v(0, n0 + nunit);
+    int m = S.orthonormalize(0, n0 + nunit);
     if (m == 0) throw Error(HINQS_E_INVALID_ARG, "initial guess is zero");
-    S.apply_h(0, m, fp32);
+    S.apply_h(S.T.p, m, fp32);
+    S.put_columns(S.T.p, m, S.V, 0);
+    S.put_columns(S.Wn.p, m, S.W, 0);
+
     std::vector<double> G((size_t)96 * 96, 0.0);  // host copy, leading dimension 96
-    auto load_g_block = [&](int c0, int nc, int mrows) {
-        for (int b0 = c0; b0 < c0 + nc; b0 += 16) {
-            int nb = std::min(16, c0 + nc - b0);
-            std::vector<double> g = S.gram_host(S.V.p, S.ld, mrows, S.W.p + b0, S.ld, nb);
-            for (int a = 0; a < mrows; ++a)
-                for (int b = 0; b < nb; ++b) {
-                    G[(size_t)a * 96 + b0 + b] = g[(size_t)a * nb + b];
-                }
-        }
-        // mirror: new columns -> rows; symmetrize the new-new block
+    // G[0:mrows, c0:c0+nc] = V[:, 0:mrows]^T B with B holding those nc columns
+    auto load_g_cols = [&](int c0, int nc, int mrows, Mat B) {
+        std::vector<double> g = S.gram_host(S.V, mrows, B, nc);
+        for (int a = 0; a < mrows; ++a)
+            for (int b = 0; b < nc; ++b) G[(size_t)a * 96 + c0 + b] = g[(size_t)a * nc + b];
+        // mirror into rows; symmetrize the new-new block
         for (int a = 0; a < mrows; ++a)
             for (int b = c0; b < c0 + nc; ++b) {
                 if (a >= c0 && a < b) {
@@ -684,15 +769,39 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
                 }
             }
     };
-    load_g_block(0, m, m);
+    // full G of the current V, W (after a restart)
+    auto load_g_all = [&](int mm) {
+        std::fill(G.begin(), G.end(), 0.0);
+        for (int b0 = 0; b0 < mm; b0 += K) {
+            const int nb = std::min(K, mm - b0);
+            std::vector<double> g = S.gram_host(S.V, mm, S.W.cols(b0), nb);
+            for (int a = 0; a < mm; ++a)
+                for (int b = 0; b < nb; ++b) G[(size_t)a * 96 + b0 + b] = g[(size_t)a * nb + b];
+        }
+        for (int a = 0; a < mm; ++a)
+            for (int b = a + 1; b < mm; ++b) {
+                double v = 0.5 * (G[(size_t)a * 96 + b] + G[(size_t)b * 96 + a]);
+                G[(size_t)a * 96 + b] = G[(size_t)b * 96 + a] = v;
+            }
+    };
+    // Replace the basis by V Q (m x q, host), recompute W and G.
+    auto rotate_basis = [&](const std::vector<double> &Q, int q) {
+        S.upload_small(Q, S.scratch_b());
+        S.tsmm(S.V, m, S.scratch_b(), q, 1.0, 0.0, S.V);
+        S.tsmm(S.W, m, S.scratch_b(), q, 1.0, 0.0, S.W);
+        m = q;
+        load_g_all(m);
+        ++restarts;
+    };
+    load_g_cols(0, m, m, S.Wnm);
 
-    std::vector<double> theta, Y;  // Y: m x K row-major
+    std::vector<double> theta, Y, Yprev;  // Y: m x K row-major; Yprev: previous Ritz coefficients
+    int mprev = 0;
     double res0 = INFINITY;
     double best_res_fp32 = INFINITY;
     int stall = 0;
     bool converged = false;
     std::vector<double> y0;
-    const int maxit = o.max_iter > 0 ? o.max_iter : 200;
     int nroots_eff = std::min(kroots, m);
     for (;;) {
         // ---- Rayleigh-Ritz
@@ -710,12 +819,12 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
         }
         y0.assign(m, 0.0);
         for (int a = 0; a < m; ++a) y0[a] = Z[(size_t)a * m + 0];
-        // ---- residuals + preconditioned corrections
-        double *Yd = S.small.p;
-        double *thd = S.small.p + 96 * 16;
+        // ---- residuals + preconditioned corrections (T)
+        double *Yd = S.scratch_a();
+        double *thd = S.scratch_a() + 96 * 16;
         S.upload_small(Y, Yd);
         S.upload_small(theta, thd);
-        unsigned grid = (unsigned)std::min<int64_t>(grid_for(D, 256 / K), 2048);
+        const unsigned grid = (unsigned)std::min<int64_t>(grid_for(D, 256 / K), 2048);
         switch (K) {
             case 1: launch_ritz<1>(S, m, Yd, thd, o.precond_floor, nroots_eff, grid); break;
             case 2: launch_ritz<2>(S, m, Yd, thd, o.precond_floor, nroots_eff, grid); break;
@@ -723,7 +832,7 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
             case 8: launch_ritz<8>(S, m, Yd, thd, o.precond_floor, nroots_eff, grid); break;
             default: launch_ritz<16>(S, m, Yd, thd, o.precond_floor, nroots_eff, grid); break;
         }
-        hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, s, S.partial.p, (int)grid, K, S.nrm.p);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(K), dim3(256), 0, s, S.partial.p, (int)grid, K, S.nrm.p);
         HQ_LAUNCH_CHECK();
         std::vector<double> rn(K);
         HQ_CHECK(hipMemcpyAsync(rn.data(), S.nrm.p, sizeof(double) * K, hipMemcpyDeviceToHost, s));
@@ -732,71 +841,99 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
         res0 = rn[0];
         ++iters;
         if (fp32) ++it_fp32;
+        if (verbose)
+            std::fprintf(stderr, "[hinqs] it %3d m %2d %s theta0 %.14f |r0| %.3e |r1| %.3e\n", iters, m,
+                         fp32 ? "fp32" : "fp64", theta[0], rn[0], nroots_eff > 1 ? rn[1] : 0.0);
         if (!fp32 && res0 <= o.tol) { converged = true; break; }
-        if (m >= D) {  // the subspace is the whole space: Ritz pairs are exact
-            converged = true;
-            break;
-        }
+        if (!fp32 && m >= D) { converged = true; break; }  // whole space: Ritz pairs are exact
         if (iters >= maxit) break;
         // ---- mixed precision: switch to FP64 products
         bool do_switch = false;
         if (fp32) {
             if (res0 < best_res_fp32 * 0.7) { best_res_fp32 = res0; stall = 0; }
             else ++stall;
-            if (res0 <= std::max(o.mixed_switch, o.tol) || stall >= 3) do_switch = true;
+            if (res0 <= std::max(o.mixed_switch, o.tol) || stall >= 3 || m >= D) do_switch = true;
         }
-        // ---- restart / switch: rotate V, W onto the current Ritz vectors
-        int nadd = 0;
+        if (do_switch) {
+            // basis := current Ritz vectors; images recomputed with FP64 products
+            int q = 0;
+            std::vector<double> Yc((size_t)m * nroots_eff);
+            for (int a = 0; a < m; ++a)
+                for (int r = 0; r < nroots_eff; ++r) Yc[(size_t)a * nroots_eff + r] = Y[(size_t)a * K + r];
+            std::vector<double> Q = small_orth(m, nroots_eff, Yc, 1e-8, q);
+            S.upload_small(Q, S.scratch_b());
+            S.tsmm(S.V, m, S.scratch_b(), q, 1.0, 0.0, S.V);
+            m = q;
+            fp32 = false;
+            // V's first block now holds the q basis vectors (q <= K)
+            S.apply_h(S.V.p, q, false);
+            S.put_columns(S.Wn.p, q, S.W, 0);
+            load_g_all(m);
+            ++restarts;
+            Yprev.clear();
+            mprev = 0;
+            continue;  // fresh Rayleigh-Ritz with FP64 images
+        }
+        // ---- which roots get a correction
         std::vector<int> add;
         for (int q = 0; q < nroots_eff; ++q)
             if (rn[q] > o.tol) add.push_back(q);
         if (add.empty()) add.push_back(0);
-        nadd = (int)add.size();
-        if (do_switch || m + nadd > mmax) {
-            int kk = nroots_eff;
-            std::vector<double> Yk((size_t)m * kk);
-            for (int a = 0; a < m; ++a)
-                for (int q = 0; q < kk; ++q) Yk[(size_t)a * kk + q] = Y[(size_t)a * K + q];
-            S.upload_small(Yk, S.small.p + 96 * 96);
-            S.tsmm(S.V.p, S.ld, m, S.small.p + 96 * 96, kk, 1.0, 0.0, S.V.p, S.ld);
-            if (do_switch) {
-                fp32 = false;
-                S.apply_h(0, kk, false);
-            } else {
-                S.tsmm(S.W.p, S.ld, m, S.small.p + 96 * 96, kk, 1.0, 0.0, S.W.p, S.ld);
+        const int nadd = (int)add.size();
+        // ---- restart (GD+k): keep current and previous Ritz vectors
+        std::vector<double> Ycur((size_t)m * nroots_eff);
+        for (int a = 0; a < m; ++a)
+            for (int r = 0; r < nroots_eff; ++r) Ycur[(size_t)a * nroots_eff + r] = Y[(size_t)a * K + r];
+        if (m + nadd > mmax) {
+            const int nprev = (mprev > 0 && !Yprev.empty()) ? nroots_eff : 0;
+            const int qq = nroots_eff + nprev;
+            std::vector<double> M((size_t)m * qq, 0.0);
+            for (int a = 0; a < m; ++a) {
+                for (int r = 0; r < nroots_eff; ++r) M[(size_t)a * qq + r] = Ycur[(size_t)a * nroots_eff + r];
+                if (a < mprev)
+                    for (int r = 0; r < nprev; ++r)
+                        M[(size_t)a * qq + nroots_eff + r] = Yprev[(size_t)a * nroots_eff + r];
             }
-            m = kk;
-            std::fill(G.begin(), G.end(), 0.0);
-            load_g_block(0, m, m);
-            ++restarts;
-            if (do_switch) continue;  // fresh Rayleigh-Ritz with FP64 images
+            int q = 0;
+            std::vector<double> Q = small_orth(m, qq, M, 1e-8, q);
+            const int qfull = q;
+            if (q + nadd > mmax) q = std::max(nroots_eff, mmax - nadd);  // keep the current Ritz vectors
+            std::vector<double> Qk((size_t)m * q);
+            for (int a = 0; a < m; ++a)
+                for (int r = 0; r < q; ++r) Qk[(size_t)a * q + r] = Q[(size_t)a * qfull + r];
+            // current Ritz coefficients in the new basis: Q^T Ycur
+            std::vector<double> Yn((size_t)q * nroots_eff, 0.0);
+            for (int r = 0; r < q; ++r)
+                for (int cc = 0; cc < nroots_eff; ++cc) {
+                    double d = 0.0;
+                    for (int a = 0; a < m; ++a) d += Qk[(size_t)a * q + r] * Ycur[(size_t)a * nroots_eff + cc];
+                    Yn[(size_t)r * nroots_eff + cc] = d;
+                }
+            rotate_basis(Qk, q);
+            Ycur.swap(Yn);
         }
-        // compact T's columns to the unconverged roots
-        if (nadd < nroots_eff) {
-            std::vector<double> P((size_t)K * nadd, 0.0);
-            for (int q = 0; q < nadd; ++q) P[(size_t)add[q] * nadd + q] = 1.0;
-            S.upload_small(P, S.small.p + 96 * 96);
-            S.tsmm(S.T.p, K, K, S.small.p + 96 * 96, nadd, 1.0, 0.0, S.T.p, K);
+        // compact T's columns to the roots that need a correction
+        if (nadd < K) {
+            std::vector<double> P((size_t)K * K, 0.0);
+            for (int q = 0; q < nadd; ++q) P[(size_t)add[q] * K + q] = 1.0;
+            S.upload_small(P, S.scratch_b());
+            S.tsmm(S.Tm, K, S.scratch_b(), K, 1.0, 0.0, S.Tm);
         }
-        int kept = S.orthonormalize_into_v(m, nadd);
+        int kept = S.orthonormalize(m, nadd);
         if (kept == 0) {
             if (!fp32) break;  // no new direction: report the current Ritz pair, not converged
-            // FP32 images cannot resolve further directions: refine in FP64
-            std::vector<double> Yk((size_t)m * nroots_eff);
-            for (int a = 0; a < m; ++a)
-                for (int q = 0; q < nroots_eff; ++q) Yk[(size_t)a * nroots_eff + q] = Y[(size_t)a * K + q];
-            S.upload_small(Yk, S.small.p + 96 * 96);
-            S.tsmm(S.V.p, S.ld, m, S.small.p + 96 * 96, nroots_eff, 1.0, 0.0, S.V.p, S.ld);
-            fp32 = false;
-            m = nroots_eff;
-            S.apply_h(0, m, false);
-            std::fill(G.begin(), G.end(), 0.0);
-            load_g_block(0, m, m);
-            ++restarts;
+            best_res_fp32 = 0.0;  // FP32 images cannot resolve further directions: refine in FP64
+            stall = 3;
+            --iters;
+            if (it_fp32 > 0) --it_fp32;
             continue;
         }
-        S.apply_h(m, kept, fp32);
-        load_g_block(m, kept, m + kept);
+        S.apply_h(S.T.p, kept, fp32);
+        S.put_columns(S.T.p, kept, S.V, m);
+        S.put_columns(S.Wn.p, kept, S.W, m);
+        load_g_cols(m, kept, m + kept, S.Wnm);
+        Yprev.swap(Ycur);
+        mprev = m;
         m += kept;
     }
     *energy = theta.empty() ? 0.0 : theta[0];
@@ -820,7 +957,8 @@ void gram_product(Ctx &c, int64_t nrows, const double *A, int lda, int ma, const
     const int nblk = gram_blocks_for(nrows);
     DBuf<double> partial;
     partial.ensure((size_t)nblk * ma * nb);
-    launch_gram(c.stream, nrows, nblk, A, lda, ma, B, ldb, nb, partial.p, G);
+    launch_gram(c.stream, nrows, nblk, Mat{const_cast<double *>(A), lda, 0}, ma,
+                Mat{const_cast<double *>(B), ldb, 0}, nb, partial.p, G);
     HQ_CHECK(hipStreamSynchronize(c.stream));
 }
 

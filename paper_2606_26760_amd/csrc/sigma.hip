@@ -3,12 +3,13 @@
 //
 // Layout: CSR over sorted rows (rowptr int64, col int32, val fp64/fp32) plus
 // the diagonal; X and S are ndet x K row-major with leading dimensions, so a
-// row of X for K = 8 doubles is one 64-byte segment.  A team of TEAM lanes
-// owns one row: lanes stride over the row's couplings (coalesced, streamed
-// with non-temporal loads so the CSR does not evict X from the caches),
-// gather X rows with 16-byte vector loads, accumulate K sums in registers and
-// combine them with a butterfly of cross-lane shuffles.  Every row is written
-// by exactly one team, so the result is deterministic and atomic-free.
+// row of X for K = 8 doubles is one 64-byte segment.  A team of lanes owns
+// one row; groups of lanes inside the team share one coupling and gather its
+// X row as one contiguous segment (16 bytes per lane), while the CSR stream is
+// read with non-temporal loads so it does not evict X from the caches.  The
+// partial sums are combined with a butterfly of cross-lane shuffles.  Every
+// row is written by exactly one team, so the result is deterministic and
+// atomic-free.
 //
 // Workgroups are remapped so each XCD (8 on MI355X, round-robin dispatch)
 // receives a contiguous range of rows: rows with the same alpha string gather
@@ -22,37 +23,45 @@ namespace {
 constexpr int SIGMA_BLOCK = 256;
 constexpr int NUM_XCD = 8;
 
+// One 16-byte vector of T (2 doubles or 4 floats).
 template <typename T>
-struct Vec2;
+struct Vec16;
 template <>
-struct Vec2<double> { using type = double2; static constexpr int n = 2; };
+struct Vec16<double> { using type = double2; static constexpr int n = 2; };
 template <>
-struct Vec2<float> { using type = float4; static constexpr int n = 4; };
+struct Vec16<float> { using type = float4; static constexpr int n = 4; };
 
-template <typename T, int K>
-__device__ inline void load_row(const T *p, T (&x)[K]) {
-    using V = typename Vec2<T>::type;
-    constexpr int W = Vec2<T>::n;
-    if constexpr (K % W == 0) {
-#pragma unroll
-        for (int c = 0; c < K; c += W) {
-            V v = *(const V *)(p + c);
-            if constexpr (W == 2) {
-                x[c] = v.x;
-                x[c + 1] = v.y;
-            } else {
-                x[c] = v.x;
-                x[c + 1] = v.y;
-                x[c + 2] = v.z;
-                x[c + 3] = v.w;
-            }
-        }
+template <typename T, int N>
+__device__ inline void load_vec(const T *p, T (&x)[N]) {
+    if constexpr (N * sizeof(T) == 16) {
+        using V = typename Vec16<T>::type;
+        V v = *(const V *)p;
+        if constexpr (N == 2) { x[0] = v.x; x[1] = v.y; }
+        else { x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w; }
     } else {
 #pragma unroll
-        for (int c = 0; c < K; ++c) x[c] = p[c];
+        for (int c = 0; c < N; ++c) x[c] = p[c];
     }
 }
 
+template <typename T, int N>
+__device__ inline void store_vec(T *p, const T (&x)[N]) {
+    if constexpr (N * sizeof(T) == 16) {
+        using V = typename Vec16<T>::type;
+        V v;
+        if constexpr (N == 2) { v.x = x[0]; v.y = x[1]; }
+        else { v.x = x[0]; v.y = x[1]; v.z = x[2]; v.w = x[3]; }
+        *(V *)p = v;
+    } else {
+#pragma unroll
+        for (int c = 0; c < N; ++c) p[c] = x[c];
+    }
+}
+
+// A team of TEAM lanes owns one row.  LPN lanes share one coupling: each loads
+// EPL consecutive entries (16 bytes) of the gathered X row, so one load
+// instruction touches 64 / LPN distinct rows and every row is read as one
+// contiguous segment.  Each lane keeps UNR couplings in flight.
 template <typename T, int K, int TEAM>
 __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(int64_t nrows, const int64_t *__restrict__ rowptr,
                                                        const int32_t *__restrict__ col,
@@ -60,35 +69,62 @@ __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(int64_t nrows, const int6
                                                        const T *__restrict__ diag,
                                                        const T *__restrict__ X, int ldx,
                                                        T *__restrict__ S, int lds) {
+    constexpr int VW = Vec16<T>::n;
+    constexpr int LPN = (K >= VW) ? K / VW : 1;   // lanes per coupling
+    constexpr int EPL = K / LPN;                   // entries of X per lane
+    constexpr int NPT = TEAM / LPN;                // couplings per team step
+    constexpr int UNR = 2;
+    static_assert(TEAM % LPN == 0 && TEAM <= 64, "team shape");
     // XCD-aware block order: hardware block b runs on XCD b % 8.
     const unsigned per_xcd = gridDim.x / NUM_XCD;
     const unsigned lb = (blockIdx.x % NUM_XCD) * per_xcd + blockIdx.x / NUM_XCD;
     const int sub = threadIdx.x % TEAM;
+    const int q = sub % LPN, g = sub / LPN;
     const int64_t row = ((int64_t)lb * SIGMA_BLOCK + threadIdx.x) / TEAM;
     if (row >= nrows) return;  // uniform across the team
-    T acc[K];
+    T acc[EPL];
 #pragma unroll
-    for (int c = 0; c < K; ++c) acc[c] = T(0);
+    for (int c = 0; c < EPL; ++c) acc[c] = T(0);
     const int64_t beg = rowptr[row], end = rowptr[row + 1];
-    for (int64_t e = beg + sub; e < end; e += TEAM) {
+    const T *Xq = X + q * EPL;
+    int64_t e = beg + g;
+    for (; e + (UNR - 1) * NPT < end; e += UNR * NPT) {
+        int32_t j[UNR];
+        T v[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            j[u] = __builtin_nontemporal_load(col + e + u * NPT);
+            v[u] = __builtin_nontemporal_load(val + e + u * NPT);
+        }
+        T x[UNR][EPL];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) load_vec<T, EPL>(Xq + (int64_t)j[u] * ldx, x[u]);
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+#pragma unroll
+            for (int c = 0; c < EPL; ++c) acc[c] += v[u] * x[u][c];
+    }
+    for (; e < end; e += NPT) {
         const int32_t j = __builtin_nontemporal_load(col + e);
         const T v = __builtin_nontemporal_load(val + e);
-        T x[K];
-        load_row<T, K>(X + (int64_t)j * ldx, x);
+        T x[EPL];
+        load_vec<T, EPL>(Xq + (int64_t)j * ldx, x);
 #pragma unroll
-        for (int c = 0; c < K; ++c) acc[c] += v * x[c];
+        for (int c = 0; c < EPL; ++c) acc[c] += v * x[c];
     }
 #pragma unroll
-    for (int off = TEAM / 2; off > 0; off >>= 1) {
+    for (int off = LPN; off < TEAM; off <<= 1) {
 #pragma unroll
-        for (int c = 0; c < K; ++c) acc[c] += __shfl_xor(acc[c], off, TEAM);
+        for (int c = 0; c < EPL; ++c) acc[c] += __shfl_xor(acc[c], off, TEAM);
     }
-    const T d = diag[row];
-    const T *xr = X + row * ldx;
-    T *sr = S + row * lds;
+    if (g == 0) {
+        const T d = diag[row];
+        T xr[EPL];
+        load_vec<T, EPL>(Xq + row * ldx, xr);
 #pragma unroll
-    for (int c = 0; c < K; ++c)
-        if (c % TEAM == sub) sr[c] = acc[c] + d * xr[c];
+        for (int c = 0; c < EPL; ++c) acc[c] += d * xr[c];
+        store_vec<T, EPL>(S + row * lds + q * EPL, acc);
+    }
 }
 
 template <typename T, int K, int TEAM>
@@ -105,11 +141,24 @@ void launch_sigma(const Ctx &c, const T *val, const T *diag, const T *X, int ldx
 template <typename T, int K>
 void dispatch_team(const Ctx &c, const T *val, const T *diag, const T *X, int ldx, T *S, int lds,
                    hipStream_t s) {
-    double avg = c.ndet > 0 ? (double)c.nnz / (double)c.ndet : 0.0;
-    if (avg <= 24) launch_sigma<T, K, 4>(c, val, diag, X, ldx, S, lds, s);
-    else if (avg <= 64) launch_sigma<T, K, 8>(c, val, diag, X, ldx, S, lds, s);
-    else if (avg <= 256) launch_sigma<T, K, 16>(c, val, diag, X, ldx, S, lds, s);
-    else launch_sigma<T, K, 32>(c, val, diag, X, ldx, S, lds, s);
+    // lanes per coupling times couplings in flight per row, sized to the mean row length
+    constexpr int VW = Vec16<T>::n;
+    constexpr int LPN = (K >= VW) ? K / VW : 1;
+    const double avg = c.ndet > 0 ? (double)c.nnz / (double)c.ndet : 0.0;
+    const double per_step = avg / 4.0;  // aim at >= 4 team steps (x2 unroll) per row
+    if constexpr (LPN <= 2) {
+        if (per_step <= 4) launch_sigma<T, K, 8>(c, val, diag, X, ldx, S, lds, s);
+        else if (per_step <= 8 * 2 / LPN) launch_sigma<T, K, 16>(c, val, diag, X, ldx, S, lds, s);
+        else if (per_step <= 16 * 2 / LPN) launch_sigma<T, K, 32>(c, val, diag, X, ldx, S, lds, s);
+        else launch_sigma<T, K, 64>(c, val, diag, X, ldx, S, lds, s);
+    } else if constexpr (LPN == 4) {
+        if (per_step <= 4) launch_sigma<T, K, 16>(c, val, diag, X, ldx, S, lds, s);
+        else if (per_step <= 8) launch_sigma<T, K, 32>(c, val, diag, X, ldx, S, lds, s);
+        else launch_sigma<T, K, 64>(c, val, diag, X, ldx, S, lds, s);
+    } else {
+        if (per_step <= 4) launch_sigma<T, K, 32>(c, val, diag, X, ldx, S, lds, s);
+        else launch_sigma<T, K, 64>(c, val, diag, X, ldx, S, lds, s);
+    }
 }
 
 template <typename T>

@@ -33,7 +33,7 @@ def test_opts_defaults_match_header():
     import ctypes
     o = hq.Opts()
     hq.load_library().hinqs_opts_default(ctypes.byref(o))
-    assert (o.block, o.max_space, o.max_iter, o.tol, o.precision) == (8, 32, 200, 1e-8, 0)
+    assert (o.block, o.max_space, o.max_iter, o.tol, o.precision) == (8, 48, 200, 1e-8, 0)
     assert o.precond_floor == 1e-8 and o.mixed_switch == 1e-5 and o.flags == 0
 
 
