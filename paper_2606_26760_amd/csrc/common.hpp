@@ -207,6 +207,8 @@ struct Ctx {
     DBuf<double> diag;
     DBuf<float> diag32;
     bool have_elements = false;
+    // row ranges with equal coupling counts, one per XCD (rows xcd_rows[x] .. xcd_rows[x+1])
+    int64_t xcd_rows[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 
     // timings (ms)
     double ms_sort = 0, ms_connect = 0, ms_elements = 0;

@@ -89,6 +89,22 @@ __global__ __launch_bounds__(256) void k_connect(ConnArgs a, int64_t *counts, co
     if (!FILL) counts[i] = n;
 }
 
+// bounds[x] = first row whose couplings start at or after x * total / 8 (x = 0..8).
+__global__ void k_balance_bounds(int64_t n, const int64_t *rowptr, int64_t *bounds) {
+    const int x = threadIdx.x;
+    if (x > 8) return;
+    const int64_t total = rowptr[n];
+    if (x == 8) { bounds[8] = n; return; }
+    const int64_t target = (total / 8) * x + (total % 8) * x / 8;
+    int64_t lo = 0, hi = n;  // smallest r in [0, n] with rowptr[r] >= target
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (rowptr[mid] < target) lo = mid + 1;
+        else hi = mid;
+    }
+    bounds[x] = lo;
+}
+
 __global__ void k_caller_counts(int64_t n, const int64_t *rowptr, const int32_t *perm, int64_t *counts) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -157,7 +173,14 @@ void build_connectivity(Ctx &c) {
     hipLaunchKernelGGL(k_connect<true>, g, b, 0, s, a, (int64_t *)nullptr, c.rowptr.p, c.col.p,
                        c.desc.p);
     HQ_LAUNCH_CHECK();
-    HQ_CHECK(hipStreamSynchronize(s));
+    {
+        DBuf<int64_t> bnd;
+        bnd.ensure(9);
+        hipLaunchKernelGGL(k_balance_bounds, dim3(1), dim3(64), 0, s, n, c.rowptr.p, bnd.p);
+        HQ_LAUNCH_CHECK();
+        HQ_CHECK(hipMemcpyAsync(c.xcd_rows, bnd.p, sizeof(c.xcd_rows), hipMemcpyDeviceToHost, s));
+        HQ_CHECK(hipStreamSynchronize(s));
+    }
     c.ms_connect =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }

@@ -14,6 +14,9 @@
 // Workgroups are remapped so each XCD (8 on MI355X, round-robin dispatch)
 // receives a contiguous range of rows: rows with the same alpha string gather
 // the same X rows, and keeping them on one XCD keeps those X rows in its L2.
+#include <algorithm>
+#include <cstdlib>
+
 #include "common.hpp"
 
 namespace hinqs {
@@ -30,6 +33,19 @@ template <>
 struct Vec16<double> { using type = double2; static constexpr int n = 2; };
 template <>
 struct Vec16<float> { using type = float4; static constexpr int n = 4; };
+
+// A value known to be equal on all lanes of the wave, moved to a scalar register
+// so that loops over it branch on the scalar unit.
+template <bool UNIFORM>
+__device__ inline int64_t uniform_if(int64_t v) {
+    if constexpr (UNIFORM) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+        return (int64_t)(((uint64_t)hi << 32) | lo);
+    } else {
+        return v;
+    }
+}
 
 template <typename T, int N>
 __device__ inline void load_vec(const T *p, T (&x)[N]) {
@@ -58,12 +74,28 @@ __device__ inline void store_vec(T *p, const T (&x)[N]) {
     }
 }
 
-// A team of TEAM lanes owns one row.  LPN lanes share one coupling: each loads
-// EPL consecutive entries (16 bytes) of the gathered X row, so one load
-// instruction touches 64 / LPN distinct rows and every row is read as one
-// contiguous segment.  Each lane keeps UNR couplings in flight.
-template <typename T, int K, int TEAM>
-__global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(int64_t nrows, const int64_t *__restrict__ rowptr,
+// Persistent teams: TEAM lanes own one row at a time and walk a strided list
+// of rows.  Rows are split into 8 contiguous ranges holding equal numbers of
+// couplings, one per XCD (hardware block b runs on XCD b % 8; the coupling
+// count per row varies several-fold along the sorted order, so equal row
+// counts would leave most XCDs idle behind the densest one), and inside a
+// range consecutive teams take
+// consecutive rows, so the rows in flight on an XCD are neighbours in the
+// sorted order and gather overlapping X rows from that XCD's L2.  LPN lanes
+// share one coupling: each loads EPL consecutive entries (16 bytes) of the
+// gathered X row, so one load instruction touches 64 / LPN distinct rows and
+// every row is read as one contiguous segment.
+// The CSR stream is software-pipelined: while the X rows of one step (UNR
+// couplings per lane) are in flight, the (col, val) of the next step and the
+// bounds of the team's next row are already being fetched, so the dependent
+// load chain rowptr -> col -> X costs one memory latency per step, not three.
+struct XcdRows {
+    int64_t b[NUM_XCD + 1];
+};
+
+template <typename T, int K, int TEAM, int UNR>
+__global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges,
+                                                       const int64_t *__restrict__ rowptr,
                                                        const int32_t *__restrict__ col,
                                                        const T *__restrict__ val,
                                                        const T *__restrict__ diag,
@@ -72,92 +104,152 @@ __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(int64_t nrows, const int6
     constexpr int VW = Vec16<T>::n;
     constexpr int LPN = (K >= VW) ? K / VW : 1;   // lanes per coupling
     constexpr int EPL = K / LPN;                   // entries of X per lane
-    constexpr int NPT = TEAM / LPN;                // couplings per team step
-    constexpr int UNR = 2;
+    constexpr int NPT = TEAM / LPN;                // couplings per team per unrolled slot
+    constexpr int STEP = UNR * NPT;                // couplings per team step
+    constexpr int TPB = SIGMA_BLOCK / TEAM;        // teams per block
     static_assert(TEAM % LPN == 0 && TEAM <= 64, "team shape");
-    // XCD-aware block order: hardware block b runs on XCD b % 8.
-    const unsigned per_xcd = gridDim.x / NUM_XCD;
-    const unsigned lb = (blockIdx.x % NUM_XCD) * per_xcd + blockIdx.x / NUM_XCD;
+    const int xcd = blockIdx.x % NUM_XCD;
+    const int64_t blocks_per_xcd = gridDim.x / NUM_XCD;
+    const int64_t team0 = (int64_t)(blockIdx.x / NUM_XCD) * TPB + threadIdx.x / TEAM;
+    const int64_t nteams = blocks_per_xcd * TPB;
+    const int64_t r0 = ranges.b[xcd];
+    const int64_t r1 = ranges.b[xcd + 1];
     const int sub = threadIdx.x % TEAM;
     const int q = sub % LPN, g = sub / LPN;
-    const int64_t row = ((int64_t)lb * SIGMA_BLOCK + threadIdx.x) / TEAM;
-    if (row >= nrows) return;  // uniform across the team
-    T acc[EPL];
-#pragma unroll
-    for (int c = 0; c < EPL; ++c) acc[c] = T(0);
-    const int64_t beg = rowptr[row], end = rowptr[row + 1];
     const T *Xq = X + q * EPL;
-    int64_t e = beg + g;
-    for (; e + (UNR - 1) * NPT < end; e += UNR * NPT) {
-        int32_t j[UNR];
-        T v[UNR];
+    int64_t row = r0 + team0;
+    if (row >= r1) return;  // uniform across the team
+    int64_t beg = uniform_if<TEAM == 64>(rowptr[row]), end = uniform_if<TEAM == 64>(rowptr[row + 1]);
+    for (;;) {
+        const int64_t nrow = row + nteams;
+        // next row's bounds, in flight during this row (clamped, not predicated)
+        const int64_t nrc = nrow < r1 ? nrow : row;
+        const int64_t nbeg = rowptr[nrc], nend = rowptr[nrc + 1];
+        T acc[EPL];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            j[u] = __builtin_nontemporal_load(col + e + u * NPT);
-            v[u] = __builtin_nontemporal_load(val + e + u * NPT);
+        for (int c = 0; c < EPL; ++c) acc[c] = T(0);
+        // Software pipeline with two register sets (a, b): while the X rows of
+        // one step are in flight, the (col, val) of the next step are fetched
+        // into the other set, so no loop-carried copy has to wait for a load.
+        // Loads are never predicated: indices past the row are clamped to a
+        // valid entry and their value is replaced by 0 at the point of use.
+        const int64_t last = end > 0 ? end - 1 : 0;
+        int32_t ja[UNR], jb[UNR];
+        T va[UNR], vb[UNR];
+        bool oka[UNR], okb[UNR];
+        auto fetch = [&](int64_t eb, int32_t (&jj)[UNR], T (&vv)[UNR], bool (&ok)[UNR]) {
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int64_t idx = eb + g + u * NPT;
+                ok[u] = idx < end;
+                const int64_t idc = ok[u] ? idx : last;
+                jj[u] = __builtin_nontemporal_load(col + idc);
+                vv[u] = __builtin_nontemporal_load(val + idc);
+            }
+        };
+        auto step = [&](const int32_t (&jj)[UNR], const T (&vv)[UNR], const bool (&ok)[UNR],
+                        int64_t eb_next, int32_t (&jn)[UNR], T (&vn)[UNR], bool (&okn)[UNR]) {
+            T x[UNR][EPL];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int32_t jr = ok[u] ? jj[u] : (int32_t)row;
+                load_vec<T, EPL>(Xq + (int64_t)jr * ldx, x[u]);
+            }
+            fetch(eb_next, jn, vn, okn);
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const T w = ok[u] ? vv[u] : T(0);
+#pragma unroll
+                for (int c = 0; c < EPL; ++c) acc[c] += w * x[u][c];
+            }
+        };
+        int64_t eb = beg;
+        fetch(eb, ja, va, oka);
+        while (eb < end) {  // same trip count on every lane of the team
+            step(ja, va, oka, eb + STEP, jb, vb, okb);
+            eb += STEP;
+            if (eb >= end) break;
+            step(jb, vb, okb, eb + STEP, ja, va, oka);
+            eb += STEP;
         }
-        T x[UNR][EPL];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) load_vec<T, EPL>(Xq + (int64_t)j[u] * ldx, x[u]);
+        for (int off = LPN; off < TEAM; off <<= 1) {
 #pragma unroll
-        for (int u = 0; u < UNR; ++u)
+            for (int c = 0; c < EPL; ++c) acc[c] += __shfl_xor(acc[c], off, TEAM);
+        }
+        if (g == 0) {
+            const T d = diag[row];
+            T xr[EPL];
+            load_vec<T, EPL>(Xq + row * ldx, xr);
 #pragma unroll
-            for (int c = 0; c < EPL; ++c) acc[c] += v[u] * x[u][c];
+            for (int c = 0; c < EPL; ++c) acc[c] += d * xr[c];
+            store_vec<T, EPL>(S + row * lds + q * EPL, acc);
+        }
+        if (nrow >= r1) break;
+        row = nrow;
+        beg = uniform_if<TEAM == 64>(nbeg);
+        end = uniform_if<TEAM == 64>(nend);
     }
-    for (; e < end; e += NPT) {
-        const int32_t j = __builtin_nontemporal_load(col + e);
-        const T v = __builtin_nontemporal_load(val + e);
-        T x[EPL];
-        load_vec<T, EPL>(Xq + (int64_t)j * ldx, x);
-#pragma unroll
-        for (int c = 0; c < EPL; ++c) acc[c] += v * x[c];
+}
+
+int env_int(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    return (v && *v) ? std::atoi(v) : dflt;
+}
+
+template <typename T, int K, int TEAM, int UNR>
+void launch_sigma_u(const Ctx &c, const T *val, const T *diag, const T *X, int ldx, T *S, int lds,
+                    hipStream_t s) {
+    static int cus = 0;
+    if (!cus) {
+        cus = 256;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
     }
-#pragma unroll
-    for (int off = LPN; off < TEAM; off <<= 1) {
-#pragma unroll
-        for (int c = 0; c < EPL; ++c) acc[c] += __shfl_xor(acc[c], off, TEAM);
-    }
-    if (g == 0) {
-        const T d = diag[row];
-        T xr[EPL];
-        load_vec<T, EPL>(Xq + row * ldx, xr);
-#pragma unroll
-        for (int c = 0; c < EPL; ++c) acc[c] += d * xr[c];
-        store_vec<T, EPL>(S + row * lds + q * EPL, acc);
-    }
+    // workgroups per CU resident at once (4 waves each)
+    const int occ = std::max(1, env_int("HINQS_SIGMA_OCC", 8));
+    const int64_t teams_needed = (c.ndet + 0) / 1;
+    int64_t nblk = (int64_t)cus * occ;
+    const int64_t max_blk = (teams_needed + SIGMA_BLOCK / TEAM - 1) / (SIGMA_BLOCK / TEAM);
+    nblk = std::min(nblk, std::max<int64_t>(max_blk, 1));
+    nblk = (nblk + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
+    XcdRows ranges;
+    for (int x = 0; x <= NUM_XCD; ++x) ranges.b[x] = c.xcd_rows[x];
+    hipLaunchKernelGGL((k_sigma<T, K, TEAM, UNR>), dim3((unsigned)nblk), dim3(SIGMA_BLOCK), 0, s,
+                       ranges, c.rowptr.p, c.col.p, val, diag, X, ldx, S, lds);
+    HQ_LAUNCH_CHECK();
 }
 
 template <typename T, int K, int TEAM>
 void launch_sigma(const Ctx &c, const T *val, const T *diag, const T *X, int ldx, T *S, int lds,
                   hipStream_t s) {
-    int64_t teams_per_block = SIGMA_BLOCK / TEAM;
-    int64_t nblk = (c.ndet + teams_per_block - 1) / teams_per_block;
-    nblk = (nblk + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
-    hipLaunchKernelGGL((k_sigma<T, K, TEAM>), dim3((unsigned)nblk), dim3(SIGMA_BLOCK), 0, s, c.ndet,
-                       c.rowptr.p, c.col.p, val, diag, X, ldx, S, lds);
-    HQ_LAUNCH_CHECK();
+    const int unr = env_int("HINQS_SIGMA_UNR", 4);
+    if (unr <= 2) launch_sigma_u<T, K, TEAM, 2>(c, val, diag, X, ldx, S, lds, s);
+    else if (unr <= 4) launch_sigma_u<T, K, TEAM, 4>(c, val, diag, X, ldx, S, lds, s);
+    else launch_sigma_u<T, K, TEAM, 8>(c, val, diag, X, ldx, S, lds, s);
 }
 
 template <typename T, int K>
 void dispatch_team(const Ctx &c, const T *val, const T *diag, const T *X, int ldx, T *S, int lds,
                    hipStream_t s) {
-    // lanes per coupling times couplings in flight per row, sized to the mean row length
+    // team size: lanes per coupling times couplings per step, sized to the mean row length
     constexpr int VW = Vec16<T>::n;
     constexpr int LPN = (K >= VW) ? K / VW : 1;
     const double avg = c.ndet > 0 ? (double)c.nnz / (double)c.ndet : 0.0;
-    const double per_step = avg / 4.0;  // aim at >= 4 team steps (x2 unroll) per row
-    if constexpr (LPN <= 2) {
-        if (per_step <= 4) launch_sigma<T, K, 8>(c, val, diag, X, ldx, S, lds, s);
-        else if (per_step <= 8 * 2 / LPN) launch_sigma<T, K, 16>(c, val, diag, X, ldx, S, lds, s);
-        else if (per_step <= 16 * 2 / LPN) launch_sigma<T, K, 32>(c, val, diag, X, ldx, S, lds, s);
-        else launch_sigma<T, K, 64>(c, val, diag, X, ldx, S, lds, s);
-    } else if constexpr (LPN == 4) {
-        if (per_step <= 4) launch_sigma<T, K, 16>(c, val, diag, X, ldx, S, lds, s);
-        else if (per_step <= 8) launch_sigma<T, K, 32>(c, val, diag, X, ldx, S, lds, s);
-        else launch_sigma<T, K, 64>(c, val, diag, X, ldx, S, lds, s);
-    } else {
-        if (per_step <= 4) launch_sigma<T, K, 32>(c, val, diag, X, ldx, S, lds, s);
-        else launch_sigma<T, K, 64>(c, val, diag, X, ldx, S, lds, s);
+    int team = env_int("HINQS_SIGMA_TEAM", 0);
+    if (team == 0) {
+        // about four unrolled steps per mean row
+        const double want = avg / 8.0 * LPN;
+        team = want <= 8 ? 8 : want <= 16 ? 16 : want <= 32 ? 32 : 64;
+    }
+    if (team < LPN) team = LPN;
+    switch (team) {
+        case 1: if constexpr (LPN <= 1) { launch_sigma<T, K, 1>(c, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
+        case 2: if constexpr (LPN <= 2) { launch_sigma<T, K, 2>(c, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
+        case 4: if constexpr (LPN <= 4) { launch_sigma<T, K, 4>(c, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
+        case 8: if constexpr (LPN <= 8) { launch_sigma<T, K, 8>(c, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
+        case 16: launch_sigma<T, K, 16>(c, val, diag, X, ldx, S, lds, s); break;
+        case 32: launch_sigma<T, K, 32>(c, val, diag, X, ldx, S, lds, s); break;
+        default: launch_sigma<T, K, 64>(c, val, diag, X, ldx, S, lds, s); break;
     }
 }
 
