@@ -55,6 +55,42 @@ def cpu_baseline(ints, alpha, beta, cfg, target_s=10.0):
                       f"{len(alpha)}-determinant set ({pairs} stored elements), {dt:.1f} s"}
 
 
+def sigma_counter_run(hq, ints, alpha, beta, cfg, reps):
+    """Repeated FP64 block-sigma launches on the workload, then an elementwise
+    kernel that reads and writes 512 MiB each (the calibration reference for
+    FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    s = hq.Hinqs(0)
+    s.set_integrals(ints.h, ints.eri, ints.e_core)
+    s.set_determinants(alpha, beta, cfg.na, cfg.nb)
+    X = torch.randn(len(alpha), cfg.k, dtype=torch.float64, device="cuda")
+    S = torch.empty_like(X)
+    for _ in range(max(1, reps)):
+        s.sigma(X, out=S, sorted_order=True)
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "sigma", "ndet": len(alpha), "nnz": s.info()["nnz"], "launches": reps}))
+
+
+def recorded_traffic():
+    """HBM bytes per FP64 sigma launch from the committed counter summary, or None
+    when the sigma kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sigma_traffic.json")
+    src = os.path.join(ROOT, "paper_2606_26760_amd", "csrc", "sigma.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("sigma_source_sha256") != sha:
+        return None
+    return float(rec["bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +99,9 @@ def main():
     ap.add_argument("--ndet", type=int, default=None, help="override the determinant count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--mode", choices=["step", "sigma"], default="step",
+                    help="sigma: only repeated FP64 sigma launches plus a copy kernel of known "
+                         "size (for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU path is "
@@ -77,6 +116,9 @@ def main():
 
     ints, alpha, beta, cfg = W.config_inputs(2, ndet=args.ndet)
     D = len(alpha)
+    if args.mode == "sigma":
+        sigma_counter_run(hq, ints, alpha, beta, cfg, args.steps)
+        return
     dev = torch.device("cuda", 0)
     a_d = torch.from_numpy(alpha.view(np.int64).copy()).to(dev)
     b_d = torch.from_numpy(beta.view(np.int64).copy()).to(dev)
@@ -138,8 +180,8 @@ def main():
                                "(h_pp in [-15,1], 16 eri factors), Davidson block k=8, tol 1e-8",
                    "ndet": D, "nnz": nnz, "block": k, "tol": cfg.tol},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sigma<double,8,16> (FP64 block sigma)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(),
+                     "kernel": "k_sigma (FP64 block sigma, k=8)",
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": t_launch * 1e3},
         "sigma_kernel": {"elements_per_s": (nnz + D) * k / t_launch, "launches": n_sig},
         "solve_ms": {"fp64": med([r[0]["fp64"] for r in res]) * 1e3,

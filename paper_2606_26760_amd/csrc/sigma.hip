@@ -94,7 +94,7 @@ struct XcdRows {
 };
 
 template <typename T, int K, int TEAM, int UNR>
-__global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges,
+__global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges, int xcd_map,
                                                        const int64_t *__restrict__ rowptr,
                                                        const int32_t *__restrict__ col,
                                                        const T *__restrict__ val,
@@ -108,9 +108,10 @@ __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges,
     constexpr int STEP = UNR * NPT;                // couplings per team step
     constexpr int TPB = SIGMA_BLOCK / TEAM;        // teams per block
     static_assert(TEAM % LPN == 0 && TEAM <= 64, "team shape");
-    const int xcd = blockIdx.x % NUM_XCD;
     const int64_t blocks_per_xcd = gridDim.x / NUM_XCD;
-    const int64_t team0 = (int64_t)(blockIdx.x / NUM_XCD) * TPB + threadIdx.x / TEAM;
+    const int xcd = xcd_map ? blockIdx.x % NUM_XCD : blockIdx.x / blocks_per_xcd;
+    const int64_t bix = xcd_map ? blockIdx.x / NUM_XCD : blockIdx.x % blocks_per_xcd;
+    const int64_t team0 = bix * TPB + threadIdx.x / TEAM;
     const int64_t nteams = blocks_per_xcd * TPB;
     const int64_t r0 = ranges.b[xcd];
     const int64_t r1 = ranges.b[xcd + 1];
@@ -206,7 +207,7 @@ void launch_sigma_u(const Ctx &c, const T *val, const T *diag, const T *X, int l
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
     }
     // workgroups per CU resident at once (4 waves each)
-    const int occ = std::max(1, env_int("HINQS_SIGMA_OCC", 8));
+    const int occ = std::max(1, env_int("HINQS_SIGMA_OCC", 4));
     const int64_t teams_needed = (c.ndet + 0) / 1;
     int64_t nblk = (int64_t)cus * occ;
     const int64_t max_blk = (teams_needed + SIGMA_BLOCK / TEAM - 1) / (SIGMA_BLOCK / TEAM);
@@ -215,14 +216,15 @@ void launch_sigma_u(const Ctx &c, const T *val, const T *diag, const T *X, int l
     XcdRows ranges;
     for (int x = 0; x <= NUM_XCD; ++x) ranges.b[x] = c.xcd_rows[x];
     hipLaunchKernelGGL((k_sigma<T, K, TEAM, UNR>), dim3((unsigned)nblk), dim3(SIGMA_BLOCK), 0, s,
-                       ranges, c.rowptr.p, c.col.p, val, diag, X, ldx, S, lds);
+                       ranges, env_int("HINQS_SIGMA_XCDMAP", 1), c.rowptr.p, c.col.p, val, diag, X, ldx,
+                       S, lds);
     HQ_LAUNCH_CHECK();
 }
 
 template <typename T, int K, int TEAM>
 void launch_sigma(const Ctx &c, const T *val, const T *diag, const T *X, int ldx, T *S, int lds,
                   hipStream_t s) {
-    const int unr = env_int("HINQS_SIGMA_UNR", 4);
+    const int unr = env_int("HINQS_SIGMA_UNR", 2);
     if (unr <= 2) launch_sigma_u<T, K, TEAM, 2>(c, val, diag, X, ldx, S, lds, s);
     else if (unr <= 4) launch_sigma_u<T, K, TEAM, 4>(c, val, diag, X, ldx, S, lds, s);
     else launch_sigma_u<T, K, TEAM, 8>(c, val, diag, X, ldx, S, lds, s);
