@@ -61,6 +61,7 @@ extern "C" {
 
 /* flags */
 #define HINQS_SORTED_ORDER 1   /* vectors are in the library's internal sorted order */
+#define HINQS_AUTOTUNE     2   /* hinqs_opts.flags: tune the sigma launch shape before solving */
 
 /* excitation classes stored in a coupling descriptor (bits 0..2) */
 #define HINQS_EXC_1A   1   /* single, alpha */
@@ -79,7 +80,7 @@ typedef struct hinqs_opts {
     int    precision;      /* HINQS_SOLVE_FP64 or HINQS_SOLVE_MIXED; default FP64 */
     double precond_floor;  /* |theta - H_ii| is clamped below at this value; default 1e-8 */
     double mixed_switch;   /* MIXED: switch to FP64 once the residual is below this; default 1e-5 */
-    int    flags;          /* HINQS_SORTED_ORDER for guess and coeffs */
+    int    flags;          /* HINQS_SORTED_ORDER for guess and coeffs; HINQS_AUTOTUNE */
 } hinqs_opts;
 
 typedef struct hinqs_stats {
@@ -243,6 +244,21 @@ int hinqs_permutation(hinqs_ctx *ctx, int32_t *perm);
  */
 int hinqs_gram(hinqs_ctx *ctx, int64_t nrows, const double *A, int lda, int ma, const double *B,
                int ldb, int nb, double *G);
+
+/*
+ * Pick the launch shape of the block-sigma kernel (workgroup team width,
+ * software-pipeline depth, workgroups per CU) for blocks of k vectors in
+ * `precision` (HINQS_FP64 / HINQS_FP32) on the current Hamiltonian, by
+ * timing each candidate on the device; later sigma products of that k and
+ * precision use it.  Results are cached per process by device architecture,
+ * k, precision and problem-size class (and in the text file named by the
+ * environment variable HINQS_TUNE_CACHE, when set), so a second call on a
+ * similar problem costs no device time.  shape (host, may be NULL) receives
+ * {team, unroll, workgroups per CU}; *ms (may be NULL) the tuned launch time
+ * in milliseconds.  Sigma results do not depend on the shape.
+ * Errors: NOT_READY, INVALID_ARG, OOM, HIP.
+ */
+int hinqs_autotune(hinqs_ctx *ctx, int k, int precision, int *shape, double *ms);
 
 /* Sizes and timings of the current state. */
 int hinqs_get_info(hinqs_ctx *ctx, hinqs_info *info);

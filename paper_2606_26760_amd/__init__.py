@@ -33,13 +33,15 @@ HINQS_E = {
 HINQS_FP64, HINQS_FP32 = 0, 1
 SOLVE_FP64, SOLVE_MIXED = 0, 1
 SORTED_ORDER = 1
+AUTOTUNE = 2
 EXC_1A, EXC_1B, EXC_2AA, EXC_2BB, EXC_2AB = 1, 2, 3, 4, 5
 
 EXPORTED = ["hinqs_opts_default", "hinqs_create", "hinqs_destroy", "hinqs_last_error",
             "hinqs_set_integrals", "hinqs_set_determinants", "hinqs_sigma",
             "hinqs_lowest_eigenpair", "hinqs_rdm12", "hinqs_integral_grad", "hinqs_diag",
             "hinqs_connectivity", "hinqs_permutation", "hinqs_get_info",
-            "hinqs_pair_descriptor", "hinqs_gram", "hinqs_set_determinants_device"]
+            "hinqs_pair_descriptor", "hinqs_gram", "hinqs_set_determinants_device",
+            "hinqs_autotune"]
 
 
 class HinqsError(RuntimeError):
@@ -111,6 +113,7 @@ def load_library() -> ctypes.CDLL:
             "hinqs_get_info": (i32, [P, P]),
             "hinqs_pair_descriptor": (ctypes.c_uint32, [ctypes.c_uint64] * 4),
             "hinqs_gram": (i32, [P, i64, P, i32, i32, P, i32, i32, P]),
+            "hinqs_autotune": (i32, [P, i32, i32, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -246,7 +249,7 @@ class Hinqs:
 
     def lowest_eigenpair(self, guess=None, *, block=8, max_space=None, max_iter=200, tol=1e-8,
                          mixed=False, precond_floor=1e-8, mixed_switch=1e-5, sorted_order=False,
-                         raise_on_not_converged=True):
+                         raise_on_not_converged=True, autotune=False):
         torch = _torch()
         o = Opts()
         self._lib.hinqs_opts_default(ctypes.byref(o))
@@ -257,7 +260,7 @@ class Hinqs:
         o.precision = SOLVE_MIXED if mixed else SOLVE_FP64
         o.precond_floor = precond_floor
         o.mixed_switch = mixed_switch
-        o.flags = SORTED_ORDER if sorted_order else 0
+        o.flags = (SORTED_ORDER if sorted_order else 0) | (AUTOTUNE if autotune else 0)
         c = torch.empty(self.ndet, dtype=torch.float64, device=self.device)
         e = ctypes.c_double(0.0)
         st = Stats()
@@ -327,6 +330,14 @@ class Hinqs:
         self._check(self._lib.hinqs_gram(self._h, n, self._ptr(A), ma, ma, self._ptr(B), nb, nb,
                                          self._ptr(G)))
         return G
+
+    def autotune(self, k=8, precision=HINQS_FP64):
+        """Tune the block-sigma launch shape for blocks of k vectors; returns
+        ((team, unroll, workgroups per CU), tuned launch ms)."""
+        shape = (ctypes.c_int * 3)()
+        ms = ctypes.c_double(0.0)
+        self._check(self._lib.hinqs_autotune(self._h, k, precision, shape, ctypes.byref(ms)))
+        return tuple(shape), ms.value
 
     def info(self):
         inf = Info()

@@ -269,6 +269,22 @@ int hinqs_gram(hinqs_ctx *ctx, int64_t nrows, const double *A, int lda, int ma, 
     });
 }
 
+int hinqs_autotune(hinqs_ctx *ctx, int k, int precision, int *shape, double *ms) {
+    return guarded(ctx, [&](Ctx &c) {
+        require_dets(c);
+        if (k != 1 && k != 2 && k != 4 && k != 8 && k != 16)
+            throw Error(HINQS_E_UNSUPPORTED, "block size must be 1, 2, 4, 8 or 16");
+        const SigmaCfg g = autotune_sigma(c, k, precision);
+        if (shape) {
+            shape[0] = g.team;
+            shape[1] = g.unr;
+            shape[2] = g.occ;
+        }
+        if (ms) *ms = g.ms;
+        return HINQS_OK;
+    });
+}
+
 int hinqs_get_info(hinqs_ctx *ctx, hinqs_info *info) {
     return guarded(ctx, [&](Ctx &c) {
         if (!info) throw Error(HINQS_E_INVALID_ARG, "null pointer");

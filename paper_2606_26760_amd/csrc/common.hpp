@@ -157,6 +157,13 @@ __host__ __device__ inline int eri_index(int p, int q, int r, int s) {
 inline int npair(int norb) { return norb * (norb + 1) / 2; }
 inline int neri_packed(int norb) { int m = npair(norb); return m * (m + 1) / 2; }
 
+// Launch shape of the sigma kernel: lanes per row team, couplings in flight per
+// lane, resident workgroups per CU.
+struct SigmaCfg {
+    int team = 0, unr = 0, occ = 0;
+    double ms = 0.0;  // measured time of one launch when chosen by the tuner
+};
+
 // ------------------------------------------------------------- context
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
@@ -209,6 +216,8 @@ struct Ctx {
     bool have_elements = false;
     // row ranges with equal coupling counts, one per XCD (rows xcd_rows[x] .. xcd_rows[x+1])
     int64_t xcd_rows[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // tuned sigma launch shapes, [precision][log2 k]
+    SigmaCfg sigma_cfg[2][5];
 
     // timings (ms)
     double ms_sort = 0, ms_connect = 0, ms_elements = 0;
@@ -226,6 +235,8 @@ void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint6
 void build_connectivity(Ctx &c);
 void build_elements(Ctx &c);
 void export_connectivity(Ctx &c, int64_t *rowptr_c, int32_t *col_c, uint32_t *desc_c);
+// Row ranges with equal coupling counts, one per XCD, from c.rowptr.
+void compute_xcd_rows(Ctx &c);
 
 // Scan / sort utilities (scan.hip).  All on c.stream.
 void exclusive_scan_i64(hipStream_t s, const int64_t *in, int64_t *out, int64_t n, DBuf<char> &tmp);
@@ -237,6 +248,11 @@ void radix_sort_u64(hipStream_t s, uint64_t *keys, int32_t *vals, int64_t n, int
 // Sigma (sigma.hip): S = H X in sorted order with leading dimensions.
 void sigma_sorted(Ctx &c, int k, const void *X, int ldx, void *S, int lds, int precision,
                   hipStream_t s);
+// Time the candidate launch shapes on c's couplings, keep the fastest in c
+// (and in a process-wide cache keyed by problem shape).  Returns it.
+SigmaCfg autotune_sigma(Ctx &c, int k, int precision);
+// Shape the next sigma launch will use for (k, precision).
+SigmaCfg sigma_config(const Ctx &c, int k, int precision);
 
 // Davidson (davidson.hip)
 int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, double *coeffs,

@@ -147,6 +147,16 @@ void export_connectivity(Ctx &c, int64_t *rowptr_c, int32_t *col_c, uint32_t *de
     HQ_CHECK(hipStreamSynchronize(s));
 }
 
+void compute_xcd_rows(Ctx &c) {
+    hipStream_t s = c.stream;
+    DBuf<int64_t> bnd;
+    bnd.ensure(9);
+    hipLaunchKernelGGL(k_balance_bounds, dim3(1), dim3(64), 0, s, c.ndet, c.rowptr.p, bnd.p);
+    HQ_LAUNCH_CHECK();
+    HQ_CHECK(hipMemcpyAsync(c.xcd_rows, bnd.p, sizeof(c.xcd_rows), hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipStreamSynchronize(s));
+}
+
 void build_connectivity(Ctx &c) {
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = c.stream;
@@ -173,14 +183,9 @@ void build_connectivity(Ctx &c) {
     hipLaunchKernelGGL(k_connect<true>, g, b, 0, s, a, (int64_t *)nullptr, c.rowptr.p, c.col.p,
                        c.desc.p);
     HQ_LAUNCH_CHECK();
-    {
-        DBuf<int64_t> bnd;
-        bnd.ensure(9);
-        hipLaunchKernelGGL(k_balance_bounds, dim3(1), dim3(64), 0, s, n, c.rowptr.p, bnd.p);
-        HQ_LAUNCH_CHECK();
-        HQ_CHECK(hipMemcpyAsync(c.xcd_rows, bnd.p, sizeof(c.xcd_rows), hipMemcpyDeviceToHost, s));
-        HQ_CHECK(hipStreamSynchronize(s));
-    }
+    compute_xcd_rows(c);
+    for (auto &row : c.sigma_cfg)
+        for (auto &g : row) g = SigmaCfg{};
     c.ms_connect =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }

@@ -714,6 +714,10 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
     if (mmax > 96) throw Error(HINQS_E_UNSUPPORTED, "max_space must be <= 96 (and >= 3 * block)");
     const bool sorted = (o.flags & HINQS_SORTED_ORDER) != 0;
     const int kroots = (int)std::min<int64_t>(K, D);  // roots tracked
+    if (o.flags & HINQS_AUTOTUNE) {
+        autotune_sigma(c, K, HINQS_FP64);
+        if (o.precision == HINQS_SOLVE_MIXED) autotune_sigma(c, K, HINQS_FP32);
+    }
     Solver S(c, K, mmax);
     hipStream_t s = c.stream;
     bool fp32 = (o.precision == HINQS_SOLVE_MIXED);

@@ -15,7 +15,12 @@
 // receives a contiguous range of rows: rows with the same alpha string gather
 // the same X rows, and keeping them on one XCD keeps those X rows in its L2.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <string>
 
 #include "common.hpp"
 
@@ -198,19 +203,24 @@ int env_int(const char *name, int dflt) {
     return (v && *v) ? std::atoi(v) : dflt;
 }
 
+int kindex(int k) { return k <= 1 ? 0 : k <= 2 ? 1 : k <= 4 ? 2 : k <= 8 ? 3 : 4; }
+
+template <typename T, int K>
+constexpr int lanes_per_coupling() {
+    return (K >= Vec16<T>::n) ? K / Vec16<T>::n : 1;
+}
+
 template <typename T, int K, int TEAM, int UNR>
-void launch_sigma_u(const Ctx &c, const T *val, const T *diag, const T *X, int ldx, T *S, int lds,
-                    hipStream_t s) {
+void launch_sigma_u(const Ctx &c, const SigmaCfg &cfg, const T *val, const T *diag, const T *X, int ldx,
+                    T *S, int lds, hipStream_t s) {
     static int cus = 0;
     if (!cus) {
         cus = 256;
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
     }
-    // workgroups per CU resident at once (4 waves each)
-    const int occ = std::max(1, env_int("HINQS_SIGMA_OCC", 4));
-    const int64_t teams_needed = (c.ndet + 0) / 1;
-    int64_t nblk = (int64_t)cus * occ;
-    const int64_t max_blk = (teams_needed + SIGMA_BLOCK / TEAM - 1) / (SIGMA_BLOCK / TEAM);
+    // workgroups resident per CU (4 waves each), capped by the number of row teams
+    int64_t nblk = (int64_t)cus * std::max(1, cfg.occ);
+    const int64_t max_blk = (c.ndet + SIGMA_BLOCK / TEAM - 1) / (SIGMA_BLOCK / TEAM);
     nblk = std::min(nblk, std::max<int64_t>(max_blk, 1));
     nblk = (nblk + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
     XcdRows ranges;
@@ -222,65 +232,182 @@ void launch_sigma_u(const Ctx &c, const T *val, const T *diag, const T *X, int l
 }
 
 template <typename T, int K, int TEAM>
-void launch_sigma(const Ctx &c, const T *val, const T *diag, const T *X, int ldx, T *S, int lds,
-                  hipStream_t s) {
-    const int unr = env_int("HINQS_SIGMA_UNR", 2);
-    if (unr <= 2) launch_sigma_u<T, K, TEAM, 2>(c, val, diag, X, ldx, S, lds, s);
-    else if (unr <= 4) launch_sigma_u<T, K, TEAM, 4>(c, val, diag, X, ldx, S, lds, s);
-    else launch_sigma_u<T, K, TEAM, 8>(c, val, diag, X, ldx, S, lds, s);
+void launch_sigma(const Ctx &c, const SigmaCfg &cfg, const T *val, const T *diag, const T *X, int ldx,
+                  T *S, int lds, hipStream_t s) {
+    if (cfg.unr <= 2) launch_sigma_u<T, K, TEAM, 2>(c, cfg, val, diag, X, ldx, S, lds, s);
+    else if (cfg.unr <= 4) launch_sigma_u<T, K, TEAM, 4>(c, cfg, val, diag, X, ldx, S, lds, s);
+    else launch_sigma_u<T, K, TEAM, 8>(c, cfg, val, diag, X, ldx, S, lds, s);
 }
 
 template <typename T, int K>
-void dispatch_team(const Ctx &c, const T *val, const T *diag, const T *X, int ldx, T *S, int lds,
-                   hipStream_t s) {
-    // team size: lanes per coupling times couplings per step, sized to the mean row length
-    constexpr int VW = Vec16<T>::n;
-    constexpr int LPN = (K >= VW) ? K / VW : 1;
-    const double avg = c.ndet > 0 ? (double)c.nnz / (double)c.ndet : 0.0;
-    int team = env_int("HINQS_SIGMA_TEAM", 0);
-    if (team == 0) {
-        // about four unrolled steps per mean row
-        const double want = avg / 8.0 * LPN;
-        team = want <= 8 ? 8 : want <= 16 ? 16 : want <= 32 ? 32 : 64;
-    }
-    if (team < LPN) team = LPN;
+void dispatch_team(const Ctx &c, const SigmaCfg &cfg, const T *val, const T *diag, const T *X, int ldx,
+                   T *S, int lds, hipStream_t s) {
+    constexpr int LPN = lanes_per_coupling<T, K>();
+    const int team = std::max(cfg.team, LPN);
     switch (team) {
-        case 1: if constexpr (LPN <= 1) { launch_sigma<T, K, 1>(c, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
-        case 2: if constexpr (LPN <= 2) { launch_sigma<T, K, 2>(c, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
-        case 4: if constexpr (LPN <= 4) { launch_sigma<T, K, 4>(c, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
-        case 8: if constexpr (LPN <= 8) { launch_sigma<T, K, 8>(c, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
-        case 16: launch_sigma<T, K, 16>(c, val, diag, X, ldx, S, lds, s); break;
-        case 32: launch_sigma<T, K, 32>(c, val, diag, X, ldx, S, lds, s); break;
-        default: launch_sigma<T, K, 64>(c, val, diag, X, ldx, S, lds, s); break;
+        case 1: if constexpr (LPN <= 1) { launch_sigma<T, K, 1>(c, cfg, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
+        case 2: if constexpr (LPN <= 2) { launch_sigma<T, K, 2>(c, cfg, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
+        case 4: if constexpr (LPN <= 4) { launch_sigma<T, K, 4>(c, cfg, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
+        case 8: if constexpr (LPN <= 8) { launch_sigma<T, K, 8>(c, cfg, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
+        case 16: launch_sigma<T, K, 16>(c, cfg, val, diag, X, ldx, S, lds, s); break;
+        case 32: launch_sigma<T, K, 32>(c, cfg, val, diag, X, ldx, S, lds, s); break;
+        default: launch_sigma<T, K, 64>(c, cfg, val, diag, X, ldx, S, lds, s); break;
     }
 }
 
 template <typename T>
-void dispatch_k(const Ctx &c, int k, const T *val, const T *diag, const T *X, int ldx, T *S, int lds,
-                hipStream_t s) {
+void dispatch_k(const Ctx &c, int k, const SigmaCfg &cfg, const T *val, const T *diag, const T *X, int ldx,
+                T *S, int lds, hipStream_t s) {
     switch (k) {
-        case 1: dispatch_team<T, 1>(c, val, diag, X, ldx, S, lds, s); break;
-        case 2: dispatch_team<T, 2>(c, val, diag, X, ldx, S, lds, s); break;
-        case 4: dispatch_team<T, 4>(c, val, diag, X, ldx, S, lds, s); break;
-        case 8: dispatch_team<T, 8>(c, val, diag, X, ldx, S, lds, s); break;
-        case 16: dispatch_team<T, 16>(c, val, diag, X, ldx, S, lds, s); break;
+        case 1: dispatch_team<T, 1>(c, cfg, val, diag, X, ldx, S, lds, s); break;
+        case 2: dispatch_team<T, 2>(c, cfg, val, diag, X, ldx, S, lds, s); break;
+        case 4: dispatch_team<T, 4>(c, cfg, val, diag, X, ldx, S, lds, s); break;
+        case 8: dispatch_team<T, 8>(c, cfg, val, diag, X, ldx, S, lds, s); break;
+        case 16: dispatch_team<T, 16>(c, cfg, val, diag, X, ldx, S, lds, s); break;
         default: throw Error(HINQS_E_UNSUPPORTED, "sigma block size must be 1, 2, 4, 8 or 16");
     }
 }
 
+// Default shape before tuning: team sized to about four unrolled steps per mean row.
+SigmaCfg default_cfg(const Ctx &c, int k, int precision) {
+    const int vw = precision == HINQS_FP64 ? 2 : 4;
+    const int lpn = k >= vw ? k / vw : 1;
+    const double avg = c.ndet > 0 ? (double)c.nnz / (double)c.ndet : 0.0;
+    const double want = avg / 8.0 * lpn;
+    SigmaCfg g;
+    g.team = want <= 8 ? 8 : want <= 16 ? 16 : want <= 32 ? 32 : 64;
+    g.unr = 2;
+    g.occ = 4;
+    return g;
+}
+
+// Process-wide cache of tuned shapes keyed by (device arch, precision, k, problem-size bucket).
+std::mutex g_tune_mutex;
+std::map<std::string, SigmaCfg> g_tune_cache;
+
+std::string tune_key(const Ctx &c, int k, int precision) {
+    hipDeviceProp_t prop;
+    std::string arch = "gpu";
+    if (hipGetDeviceProperties(&prop, c.device) == hipSuccess) arch = prop.gcnArchName;
+    const int dbucket = c.ndet > 0 ? (int)std::lround(2.0 * std::log2((double)c.ndet)) : 0;
+    const int nbucket = c.ndet > 0 ? (int)std::lround((double)c.nnz / (double)c.ndet / 16.0) : 0;
+    return arch + "|p" + std::to_string(precision) + "|k" + std::to_string(k) + "|d" + std::to_string(dbucket) +
+           "|n" + std::to_string(nbucket);
+}
+
+void load_tune_file() {
+    static bool loaded = false;
+    if (loaded) return;
+    loaded = true;
+    const char *path = std::getenv("HINQS_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ifstream f(path);
+    std::string key;
+    SigmaCfg g;
+    while (f >> key >> g.team >> g.unr >> g.occ >> g.ms) g_tune_cache[key] = g;
+}
+
+void store_tune_file() {
+    const char *path = std::getenv("HINQS_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream f(path, std::ios::trunc);
+    for (const auto &kv : g_tune_cache)
+        f << kv.first << " " << kv.second.team << " " << kv.second.unr << " " << kv.second.occ << " "
+          << kv.second.ms << "\n";
+}
+
 }  // namespace
+
+SigmaCfg sigma_config(const Ctx &c, int k, int precision) {
+    SigmaCfg g = c.sigma_cfg[precision == HINQS_FP64 ? 0 : 1][kindex(k)];
+    if (g.team == 0) g = default_cfg(c, k, precision);
+    // explicit overrides for experiments
+    g.team = env_int("HINQS_SIGMA_TEAM", g.team);
+    g.unr = env_int("HINQS_SIGMA_UNR", g.unr);
+    g.occ = env_int("HINQS_SIGMA_OCC", g.occ);
+    return g;
+}
 
 // X, S in sorted order; k in {1,2,4,8,16}; leading dimensions keep 16-byte
 // alignment of every row (ldx, lds multiples of 16 / sizeof(T) when k >= that).
 void sigma_sorted(Ctx &c, int k, const void *X, int ldx, void *S, int lds, int precision,
                   hipStream_t s) {
     if (!c.have_elements) throw Error(HINQS_E_NOT_READY, "matrix elements are not built");
+    const SigmaCfg cfg = sigma_config(c, k, precision);
     if (precision == HINQS_FP64)
-        dispatch_k<double>(c, k, c.val.p, c.diag.p, (const double *)X, ldx, (double *)S, lds, s);
+        dispatch_k<double>(c, k, cfg, c.val.p, c.diag.p, (const double *)X, ldx, (double *)S, lds, s);
     else if (precision == HINQS_FP32)
-        dispatch_k<float>(c, k, c.val32.p, c.diag32.p, (const float *)X, ldx, (float *)S, lds, s);
+        dispatch_k<float>(c, k, cfg, c.val32.p, c.diag32.p, (const float *)X, ldx, (float *)S, lds, s);
     else
         throw Error(HINQS_E_INVALID_ARG, "precision must be HINQS_FP64 or HINQS_FP32");
+}
+
+SigmaCfg autotune_sigma(Ctx &c, int k, int precision) {
+    if (!c.have_elements) throw Error(HINQS_E_NOT_READY, "matrix elements are not built");
+    if (precision != HINQS_FP64 && precision != HINQS_FP32)
+        throw Error(HINQS_E_INVALID_ARG, "precision must be HINQS_FP64 or HINQS_FP32");
+    const int K = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
+    SigmaCfg &slot = c.sigma_cfg[precision == HINQS_FP64 ? 0 : 1][kindex(K)];
+    const std::string key = tune_key(c, K, precision);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        load_tune_file();
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            slot = it->second;
+            return slot;
+        }
+    }
+    hipStream_t s = c.stream;
+    const size_t esz = precision == HINQS_FP64 ? 8 : 4;
+    DBuf<char> X, S;
+    X.ensure((size_t)c.ndet * K * esz);
+    S.ensure((size_t)c.ndet * K * esz);
+    HQ_CHECK(hipMemsetAsync(X.p, 0, (size_t)c.ndet * K * esz, s));
+    hipEvent_t e0, e1;
+    HQ_CHECK(hipEventCreate(&e0));
+    HQ_CHECK(hipEventCreate(&e1));
+    const int vw = precision == HINQS_FP64 ? 2 : 4;
+    const int lpn = K >= vw ? K / vw : 1;
+    SigmaCfg best;
+    best.ms = 1e30;
+    const int teams[] = {16, 32, 64};
+    const int unrs[] = {2, 4};
+    const int occs[] = {2, 4, 8};
+    for (int team : teams) {
+        if (team < 4 * lpn) continue;
+        for (int unr : unrs)
+            for (int occ : occs) {
+                SigmaCfg g;
+                g.team = team;
+                g.unr = unr;
+                g.occ = occ;
+                auto run = [&]() {
+                    if (precision == HINQS_FP64)
+                        dispatch_k<double>(c, K, g, c.val.p, c.diag.p, (const double *)X.p, K, (double *)S.p, K, s);
+                    else
+                        dispatch_k<float>(c, K, g, c.val32.p, c.diag32.p, (const float *)X.p, K, (float *)S.p, K, s);
+                };
+                run();
+                HQ_CHECK(hipEventRecord(e0, s));
+                for (int r = 0; r < 3; ++r) run();
+                HQ_CHECK(hipEventRecord(e1, s));
+                HQ_CHECK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HQ_CHECK(hipEventElapsedTime(&ms, e0, e1));
+                g.ms = ms / 3.0;
+                if (g.ms < best.ms) best = g;
+            }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    slot = best;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        g_tune_cache[key] = best;
+        store_tune_file();
+    }
+    return best;
 }
 
 }  // namespace hinqs

@@ -306,3 +306,36 @@ def test_error_paths():
     with pytest.raises(hq.HinqsError) as ei:
         s.sigma(torch.zeros((len(a), 17), dtype=torch.float64, device="cuda"))
     assert ei.value.name == "UNSUPPORTED"
+
+
+@pytest.mark.parametrize("team,unr,occ", [(16, 2, 2), (32, 4, 8), (64, 2, 4), (64, 4, 2), (8, 2, 4)])
+def test_sigma_every_launch_shape(team, unr, occ, monkeypatch):
+    """Every launch shape the tuner may pick gives the same products (to the bar)."""
+    ints, a, b, cfg = W.config_inputs(1, ndet=5000)
+    log(f"sigma launch shape team={team} unr={unr} occ={occ}")
+    monkeypatch.setenv("HINQS_SIGMA_TEAM", str(team))
+    monkeypatch.setenv("HINQS_SIGMA_UNR", str(unr))
+    monkeypatch.setenv("HINQS_SIGMA_OCC", str(occ))
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    o = oracle_for(ints, a, b, cfg.na, cfg.nb)
+    for k in (1, 8, 16):
+        X = W.random_block(len(a), k, 31 + k)
+        _check_sigma(s, o, X, np.arange(len(a)), 1e-12)
+    X = W.random_block(len(a), 8, 40)
+    _check_sigma(s, o, X, np.arange(len(a)), 2e-6, dtype=torch.float32)
+
+
+def test_autotune_then_solve():
+    ints, a, b, cfg = W.config_inputs(1, ndet=8000)
+    log("autotune cas10 8000 dets, then solve with the tuned shape")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    o = oracle_for(ints, a, b, cfg.na, cfg.nb)
+    shape, ms = s.autotune(8, hq.HINQS_FP64)
+    assert shape[0] in (16, 32, 64) and shape[1] in (2, 4) and shape[2] in (2, 4, 8) and ms > 0
+    shape2, _ = s.autotune(8, hq.HINQS_FP64)   # cached
+    assert shape2 == shape
+    X = W.random_block(len(a), 8, 41)
+    _check_sigma(s, o, X, np.arange(len(a)), 1e-12)
+    e, c, st = s.lowest_eigenpair(tol=1e-9, autotune=True, mixed=True)
+    e_ref, _ = o.lowest_eigenpair()
+    assert abs(e - e_ref) <= 1e-8
