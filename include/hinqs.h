@@ -62,6 +62,7 @@ extern "C" {
 /* flags */
 #define HINQS_SORTED_ORDER 1   /* vectors are in the library's internal sorted order */
 #define HINQS_AUTOTUNE     2   /* hinqs_opts.flags: tune the sigma launch shape before solving */
+#define HINQS_NO_GRAPH     4   /* hinqs_opts.flags, batched solves: launch each kernel directly */
 
 /* excitation classes stored in a coupling descriptor (bits 0..2) */
 #define HINQS_EXC_1A   1   /* single, alpha */
@@ -106,6 +107,20 @@ typedef struct hinqs_info {
     double  ms_connect;        /* last set_determinants: coupling enumeration */
     double  ms_elements;       /* last element build (Slater-Condon) */
 } hinqs_info;
+
+typedef struct hinqs_batch_stats {
+    int     instances;
+    int     converged;         /* instances whose lowest root reached tol */
+    int     iterations;        /* batched iterations (one graph launch each) */
+    int     graphs;            /* graphs captured (one per subspace size); 0 with HINQS_NO_GRAPH */
+    double  ms_total;          /* wall time of the call */
+    double  ms_setup;          /* merge, buffers, initial block, graph capture */
+    double  ms_iterations;     /* the iteration loop without capture */
+    double  max_residual;      /* largest final ||r||_2 of a lowest root */
+    int64_t ndet;              /* determinants over all instances */
+    int64_t nnz;               /* stored couplings over all instances */
+    int     sigma_team, sigma_unroll, sigma_occupancy;  /* sigma launch shape used */
+} hinqs_batch_stats;
 
 /* Fill *opts with the defaults listed above. */
 void hinqs_opts_default(hinqs_opts *opts);
@@ -262,6 +277,49 @@ int hinqs_autotune(hinqs_ctx *ctx, int k, int precision, int *shape, double *ms)
 
 /* Sizes and timings of the current state. */
 int hinqs_get_info(hinqs_ctx *ctx, hinqs_info *info);
+
+/*
+ * Batched instances.  A context also holds a list of independent instances
+ * (for example the points of a bond-length scan: each its own norb, electron
+ * counts, integrals and determinant set, as for hinqs_set_integrals and
+ * hinqs_set_determinants), solved together for their lowest eigenpairs
+ * (paper Sec. 2.2, Step 3, once per instance).  The batch does not touch
+ * the context's single determinant set.
+ *
+ * hinqs_batch_clear drops every instance.
+ *
+ * hinqs_batch_add copies one instance from host memory (same arguments and
+ * validation as hinqs_set_integrals + hinqs_set_determinants, errors
+ * likewise) and builds its couplings and matrix elements.  *index (may be
+ * NULL) receives its position in the batch.
+ *
+ * hinqs_batch_info: *ninst instances; offsets (host, ninst + 1, may be NULL)
+ * receives the first coefficient of each instance in the concatenated
+ * vector (offsets[ninst] = total determinants); *nnz (may be NULL) the
+ * stored couplings over all instances.
+ *
+ * hinqs_batch_lowest_eigenpair solves all instances with FP64 block Davidson
+ * (opts as for hinqs_lowest_eigenpair; precision must be HINQS_SOLVE_FP64;
+ * max_space is capped at 64 and rounded down to a multiple of block, and
+ * must be at least 3 * block; every instance needs at least max_space
+ * determinants).  All instances advance together and each iteration is one
+ * replay of a captured hipGraph (HINQS_NO_GRAPH: plain launches, same
+ * arithmetic); converged instances are skipped from then on.  Outputs:
+ * energies (host, ninst), coeffs (device, total determinants; instance i at
+ * offsets[i], in its own caller order unless HINQS_SORTED_ORDER), status
+ * (host, ninst, may be NULL: 0 or HINQS_E_NOT_CONVERGED), iterations (host,
+ * ninst, may be NULL), stats (may be NULL).  Returns NOT_CONVERGED when any
+ * instance missed the tolerance (outputs hold the best estimates).
+ * Errors: NOT_READY (empty batch), UNSUPPORTED, INVALID_ARG, OOM, HIP.
+ */
+int hinqs_batch_clear(hinqs_ctx *ctx);
+int hinqs_batch_add(hinqs_ctx *ctx, int norb, const double *h, const double *eri, double e_core,
+                    int64_t ndet, const uint64_t *alpha, const uint64_t *beta, int nalpha, int nbeta,
+                    int *index);
+int hinqs_batch_info(hinqs_ctx *ctx, int *ninst, int64_t *offsets, int64_t *nnz);
+int hinqs_batch_lowest_eigenpair(hinqs_ctx *ctx, const hinqs_opts *opts, double *energies,
+                                 double *coeffs, int *status, int *iterations,
+                                 hinqs_batch_stats *stats);
 
 /*
  * Host-only helper (no device work): descriptor of the pair x_i <- x_j as

@@ -34,6 +34,7 @@ HINQS_FP64, HINQS_FP32 = 0, 1
 SOLVE_FP64, SOLVE_MIXED = 0, 1
 SORTED_ORDER = 1
 AUTOTUNE = 2
+NO_GRAPH = 4
 EXC_1A, EXC_1B, EXC_2AA, EXC_2BB, EXC_2AB = 1, 2, 3, 4, 5
 
 EXPORTED = ["hinqs_opts_default", "hinqs_create", "hinqs_destroy", "hinqs_last_error",
@@ -41,7 +42,8 @@ EXPORTED = ["hinqs_opts_default", "hinqs_create", "hinqs_destroy", "hinqs_last_e
             "hinqs_lowest_eigenpair", "hinqs_rdm12", "hinqs_integral_grad", "hinqs_diag",
             "hinqs_connectivity", "hinqs_permutation", "hinqs_get_info",
             "hinqs_pair_descriptor", "hinqs_gram", "hinqs_set_determinants_device",
-            "hinqs_autotune"]
+            "hinqs_autotune", "hinqs_batch_clear", "hinqs_batch_add", "hinqs_batch_info",
+            "hinqs_batch_lowest_eigenpair"]
 
 
 class HinqsError(RuntimeError):
@@ -75,6 +77,17 @@ class Info(ctypes.Structure):
                 ("n_alpha_strings", ctypes.c_int32), ("n_beta_strings", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64), ("ms_sort", ctypes.c_double),
                 ("ms_connect", ctypes.c_double), ("ms_elements", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("instances", ctypes.c_int), ("converged", ctypes.c_int), ("iterations", ctypes.c_int),
+                ("graphs", ctypes.c_int), ("ms_total", ctypes.c_double), ("ms_setup", ctypes.c_double),
+                ("ms_iterations", ctypes.c_double), ("max_residual", ctypes.c_double),
+                ("ndet", ctypes.c_int64), ("nnz", ctypes.c_int64), ("sigma_team", ctypes.c_int),
+                ("sigma_unroll", ctypes.c_int), ("sigma_occupancy", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -114,6 +127,10 @@ def load_library() -> ctypes.CDLL:
             "hinqs_pair_descriptor": (ctypes.c_uint32, [ctypes.c_uint64] * 4),
             "hinqs_gram": (i32, [P, i64, P, i32, i32, P, i32, i32, P]),
             "hinqs_autotune": (i32, [P, i32, i32, P, P]),
+            "hinqs_batch_clear": (i32, [P]),
+            "hinqs_batch_add": (i32, [P, i32, P, P, dbl, i64, P, P, i32, i32, P]),
+            "hinqs_batch_info": (i32, [P, P, P, P]),
+            "hinqs_batch_lowest_eigenpair": (i32, [P, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -330,6 +347,69 @@ class Hinqs:
         self._check(self._lib.hinqs_gram(self._h, n, self._ptr(A), ma, ma, self._ptr(B), nb, nb,
                                          self._ptr(G)))
         return G
+
+    # ------------------------------------------------------ batched instances
+    def batch_clear(self):
+        self._check(self._lib.hinqs_batch_clear(self._h))
+
+    def batch_add(self, h, eri, e_core, alpha, beta, nalpha: int, nbeta: int) -> int:
+        """Add one independent instance (host inputs); returns its index."""
+        h = _host_f64(h)
+        eri = _host_f64(eri)
+        norb = h.shape[0]
+        if h.shape != (norb, norb) or eri.shape != (norb,) * 4:
+            raise ValueError("h must be (n, n) and eri (n, n, n, n)")
+        a = _host_u64(alpha)
+        b = _host_u64(beta)
+        if a.shape != b.shape or a.ndim != 1:
+            raise ValueError("alpha and beta must be 1-D and equally long")
+        idx = ctypes.c_int(-1)
+        self._check(self._lib.hinqs_batch_add(
+            self._h, norb, h.ctypes.data_as(ctypes.c_void_p), eri.ctypes.data_as(ctypes.c_void_p),
+            float(e_core), len(a), a.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p),
+            nalpha, nbeta, ctypes.byref(idx)))
+        return idx.value
+
+    def batch_info(self):
+        """(number of instances, coefficient offsets (n + 1), total couplings)."""
+        n = ctypes.c_int(0)
+        self._check(self._lib.hinqs_batch_info(self._h, ctypes.byref(n), None, None))
+        off = np.zeros(n.value + 1, dtype=np.int64)
+        nnz = ctypes.c_int64(0)
+        self._check(self._lib.hinqs_batch_info(self._h, ctypes.byref(n), off.ctypes.data_as(ctypes.c_void_p),
+                                               ctypes.byref(nnz)))
+        return n.value, off, nnz.value
+
+    def batch_lowest_eigenpair(self, *, block=8, max_space=None, max_iter=200, tol=1e-8, precond_floor=1e-8,
+                               sorted_order=False, autotune=False, graph=True, raise_on_not_converged=True):
+        """Lowest eigenpair of every batched instance.
+
+        Returns (energies (n,), coefficient tensor (total determinants,) with instance i
+        at offsets[i]:offsets[i+1], dict with offsets, status, iterations and stats)."""
+        torch = _torch()
+        n, off, _ = self.batch_info()
+        o = Opts()
+        self._lib.hinqs_opts_default(ctypes.byref(o))
+        o.block = block
+        o.max_space = max_space if max_space is not None else 6 * block
+        o.max_iter = max_iter
+        o.tol = tol
+        o.precision = SOLVE_FP64
+        o.precond_floor = precond_floor
+        o.flags = ((SORTED_ORDER if sorted_order else 0) | (AUTOTUNE if autotune else 0)
+                   | (0 if graph else NO_GRAPH))
+        e = np.zeros(max(n, 1), dtype=np.float64)
+        status = np.zeros(max(n, 1), dtype=np.int32)
+        iters = np.zeros(max(n, 1), dtype=np.int32)
+        c = torch.empty(int(off[-1]) if n else 1, dtype=torch.float64, device=self.device)
+        st = BatchStats()
+        rc = self._lib.hinqs_batch_lowest_eigenpair(
+            self._h, ctypes.byref(o), e.ctypes.data_as(ctypes.c_void_p), self._ptr(c),
+            status.ctypes.data_as(ctypes.c_void_p), iters.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st))
+        if not (rc == -7 and not raise_on_not_converged):
+            self._check(rc)
+        return e[:n], c, {"offsets": off, "status": status[:n], "iterations": iters[:n],
+                          "stats": st.as_dict(), "converged": rc == HINQS_OK}
 
     def autotune(self, k=8, precision=HINQS_FP64):
         """Tune the block-sigma launch shape for blocks of k vectors; returns

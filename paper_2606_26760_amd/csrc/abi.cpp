@@ -269,6 +269,52 @@ int hinqs_gram(hinqs_ctx *ctx, int64_t nrows, const double *A, int lda, int ma, 
     });
 }
 
+int hinqs_batch_clear(hinqs_ctx *ctx) {
+    return guarded(ctx, [&](Ctx &c) {
+        batch_clear(c);
+        return HINQS_OK;
+    });
+}
+
+int hinqs_batch_add(hinqs_ctx *ctx, int norb, const double *h, const double *eri, double e_core, int64_t ndet,
+                    const uint64_t *alpha, const uint64_t *beta, int nalpha, int nbeta, int *index) {
+    return guarded(ctx, [&](Ctx &c) {
+        if (!h || !eri || !alpha || !beta) throw Error(HINQS_E_INVALID_ARG, "null input pointer");
+        if (norb < 1) throw Error(HINQS_E_INVALID_ARG, "norb must be >= 1");
+        if (norb > 32) throw Error(HINQS_E_UNSUPPORTED, "norb > 32 is not supported");
+        if (ndet < 1 || ndet >= ((int64_t)1 << 31) - 1)
+            throw Error(HINQS_E_INVALID_ARG, "ndet must be in [1, 2^31 - 2]");
+        if (nalpha < 0 || nbeta < 0 || nalpha > norb || nbeta > norb)
+            throw Error(HINQS_E_INVALID_ARG, "electron counts out of range");
+        const int i = batch_add(c, norb, h, eri, e_core, ndet, alpha, beta, nalpha, nbeta);
+        if (index) *index = i;
+        return HINQS_OK;
+    });
+}
+
+int hinqs_batch_info(hinqs_ctx *ctx, int *ninst, int64_t *offsets, int64_t *nnz) {
+    return guarded(ctx, [&](Ctx &c) {
+        batch_info(c, ninst, offsets, nnz);
+        return HINQS_OK;
+    });
+}
+
+int hinqs_batch_lowest_eigenpair(hinqs_ctx *ctx, const hinqs_opts *opts, double *energies, double *coeffs,
+                                 int *status, int *iterations, hinqs_batch_stats *stats) {
+    return guarded(ctx, [&](Ctx &c) {
+        if (!energies || !coeffs) throw Error(HINQS_E_INVALID_ARG, "null output pointer");
+        hinqs_opts o;
+        hinqs_opts_default(&o);
+        if (opts) o = *opts;
+        if (!(o.tol > 0) || !(o.precond_floor > 0) || o.max_iter < 1)
+            throw Error(HINQS_E_INVALID_ARG, "tol, precond_floor and max_iter must be positive");
+        if (o.precision != HINQS_SOLVE_FP64) throw Error(HINQS_E_UNSUPPORTED, "batched solves run in FP64");
+        int rc = batch_solve(c, o, energies, coeffs, status, iterations, stats);
+        if (rc == HINQS_E_NOT_CONVERGED) c.err = "some instances did not reach the tolerance";
+        return rc;
+    });
+}
+
 int hinqs_autotune(hinqs_ctx *ctx, int k, int precision, int *shape, double *ms) {
     return guarded(ctx, [&](Ctx &c) {
         require_dets(c);

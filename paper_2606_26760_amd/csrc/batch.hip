@@ -1,0 +1,1249 @@
+// Batched lowest-eigenpair solves of many independent instances: a family of
+// problems such as the points of a potential-energy scan, each with its own
+// orbital count, electron count, integrals and determinant set.  The paper
+// (Sec. 2.2, Step 3) solves one instance by Davidson; its outlook names bond
+// scans as the next use.  Every instance is solved by the same block Davidson
+// method as the single-instance path (FP64, GD+k restart, CGS2 plus symmetric
+// orthonormalization), but all of them advance together.
+//
+// Layout.  The instances are concatenated into one block-diagonal coupling
+// matrix: instance b owns global rows inst_row[b] .. inst_row[b+1] (in its own
+// sorted order) and its couplings point only inside that range, so one launch
+// of the persistent sigma kernel applies every instance's H_B at once, with
+// the coupling-balanced XCD row ranges recomputed on the device from the
+// instances still running; rows of finished instances are skipped.  Dense
+// tall-skinny work (Gram products, basis updates, Ritz vectors) runs over a
+// chunk list: a chunk is a run of at most CH rows of one instance and one
+// workgroup handles one chunk, so a single launch covers all instances however
+// uneven their sizes.  The small dense problems (Rayleigh-Ritz eigenproblem,
+// restart basis, block orthonormalization) run on the device, one workgroup
+// per instance, so an iteration needs no host round trip.
+//
+// Schedule.  All instances use the same subspace size m at every iteration
+// (K, 2K, ..., m_max, then a restart to 2K), so the launches of an iteration
+// depend only on m: each distinct m is captured once as a hipGraph and
+// replayed.  Converged instances raise a flag that every kernel checks; the
+// host reads one counter per iteration to learn when all have finished.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <memory>
+#include <type_traits>
+#include <vector>
+
+#include "common.hpp"
+
+namespace hinqs {
+
+struct BatchState {
+    struct Meta {
+        int norb, na, nb;
+        int64_t ndet, nnz;
+    };
+    std::vector<Meta> meta;
+    std::vector<std::unique_ptr<Ctx>> pending;  // built, not yet merged into g
+    int nmerged = 0;                             // instances already merged into g
+    Ctx g;                                       // block-diagonal couplings of the merged instances
+    DBuf<int32_t> perm;                          // global sorted row -> caller index inside its instance
+    DBuf<int32_t> row_inst;                      // global row -> instance
+    DBuf<int64_t> inst_row;                      // row offsets (ninst + 1), device
+    std::vector<int64_t> row_off{0}, nz_off{0};  // host copies of the row / coupling offsets
+};
+
+namespace {
+
+constexpr int MS = 64;             // largest subspace
+constexpr int KB = 16;             // largest block; leading dimension of per-instance K-wide arrays
+constexpr int PSTRIDE = MS * KB;   // doubles per chunk of a Gram partial
+constexpr int RSTRIDE = KB;        // doubles per chunk of a residual partial
+constexpr int NT = 256;            // threads of the per-instance kernels
+constexpr int GRAM_UNROLL_B = 4;
+
+struct Chunk {
+    int64_t r0;
+    int32_t n;
+    int32_t inst;
+};
+
+// Per-instance solver state in device memory (passed by value).
+struct BDev {
+    int nb;
+    const int32_t *inst_chunk;  // chunks of instance b: inst_chunk[b] .. inst_chunk[b+1]
+    int32_t *done;              // 0 running, 1 converged, 2 no new direction
+    int32_t *iters, *mfin, *valid;  // valid: [b][MS] basis columns in use
+    double *G;                  // [b][MS][MS] V^T H V
+    double *Y;                  // [b][MS][KB] Ritz coefficients of the current basis
+    double *theta;              // [b][KB]
+    double *Q;                  // [b][MS][2K] restart transform (leading dimension 2K)
+    double *C;                  // [b][MS][KB] projection coefficients
+    double *Z;                  // [b][KB][KB] block orthonormalization transform
+    double *scl;                // [b][KB] column scales of the new block
+    double *energy, *resid;     // [b]
+};
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Sum over a workgroup of NT threads; every thread receives the same value.
+__device__ double block_sum(double v, double *red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
+    return s;
+}
+
+// Sum over one wave, broadcast from lane 0 so every lane holds the same value.
+__device__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return __shfl(v, 0);
+}
+
+// Parallel cyclic Jacobi eigensolver for the symmetric n x n matrix A (LDS,
+// leading dimension LD, n <= 64).  Rotations follow a round-robin pairing:
+// each round pairs every index once, the n/2 disjoint rotations are computed
+// from the current matrix and applied together (columns, then rows).  Sweeps
+// stop when the off-diagonal mass falls below 1e-32 of the Frobenius norm.
+// On return A's diagonal holds the eigenvalues and row j of ZT the
+// eigenvector belonging to A[j][j].
+template <int LD>
+__device__ void block_jacobi(int n, double *A, double *ZT, int *pp, int *pq, double *pc, double *ps,
+                             double *red) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < n * n; e += NT) {
+        const int i = e / n, j = e % n;
+        ZT[i * LD + j] = i == j ? 1.0 : 0.0;
+    }
+    double f = 0.0;
+    for (int e = tid; e < n * n; e += NT) {
+        const double x = A[(e / n) * LD + e % n];
+        f += x * x;
+    }
+    const double fro = block_sum(f, red);
+    if (n < 2) return;
+    const int ne = n + (n & 1), np = ne / 2, nr = ne - 1;
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double o = 0.0;
+        for (int e = tid; e < n * n; e += NT) {
+            const int i = e / n, j = e % n;
+            if (i < j) o += A[i * LD + j] * A[i * LD + j];
+        }
+        const double off = block_sum(o, red);
+        if (off == 0.0 || off <= 1e-32 * fro) break;
+        for (int r = 0; r < nr; ++r) {
+            if (tid < np) {
+                int a, b;
+                if (tid == 0) {
+                    a = r;
+                    b = ne - 1;
+                } else {
+                    a = (r + tid) % nr;
+                    b = (r - tid + nr) % nr;
+                }
+                const int p = min(a, b), q = max(a, b);
+                double c = 1.0, s = 0.0;
+                if (q < n) {
+                    const double apq = A[p * LD + q];
+                    if (apq != 0.0) {
+                        const double th = (A[q * LD + q] - A[p * LD + p]) / (2.0 * apq);
+                        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        s = t * c;
+                    }
+                }
+                pp[tid] = p;
+                pq[tid] = q < n ? q : -1;
+                pc[tid] = c;
+                ps[tid] = s;
+            }
+            __syncthreads();
+            // columns p, q (pairs vary fastest so neighbouring threads hit different banks)
+            for (int e = tid; e < np * n; e += NT) {
+                const int k = e % np, j = e / np;
+                const int p = pp[k], q = pq[k];
+                const double s = ps[k];
+                if (q < 0 || s == 0.0) continue;
+                const double c = pc[k];
+                const double ajp = A[j * LD + p], ajq = A[j * LD + q];
+                A[j * LD + p] = c * ajp - s * ajq;
+                A[j * LD + q] = s * ajp + c * ajq;
+            }
+            __syncthreads();
+            // rows p, q and the eigenvector rows
+            for (int e = tid; e < np * n; e += NT) {
+                const int k = e / n, j = e % n;
+                const int p = pp[k], q = pq[k];
+                const double s = ps[k];
+                if (q < 0 || s == 0.0) continue;
+                const double c = pc[k];
+                const double apj = A[p * LD + j], aqj = A[q * LD + j];
+                A[p * LD + j] = c * apj - s * aqj;
+                A[q * LD + j] = s * apj + c * aqj;
+                const double zp = ZT[p * LD + j], zq = ZT[q * LD + j];
+                ZT[p * LD + j] = c * zp - s * zq;
+                ZT[q * LD + j] = s * zp + c * zq;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// --------------------------------------------------------- chunked dense kernels
+
+// partial[chunk][a * nb + b] = sum over the chunk's rows of A(i, a) B(i, b),
+// a < ma <= 16 MT, b < nb <= 16, with FP64 MFMA (16x16x4): lane l supplies
+// A_mat[l%16][l/16] and B_mat[l/16][l%16] and receives D[l/16 + 4r][l%16].
+// The four waves split the chunk's rows.
+template <int MT>
+__global__ __launch_bounds__(256) void k_bgram(const Chunk *__restrict__ chunks, const int32_t *__restrict__ done,
+                                               Mat A, int ma, Mat B, int nb, double *__restrict__ partial) {
+    const Chunk ch = chunks[blockIdx.x];
+    if (done[ch.inst]) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int per = ((ch.n + 3) / 4 + 3) / 4 * 4;  // rows per wave, a multiple of 4
+    const int64_t end = ch.r0 + ch.n;
+    const int64_t r0 = ch.r0 + (int64_t)wave * per;
+    const int64_t r1 = min(end, r0 + per);
+    const int col = lane & 15, kk = lane >> 4;
+    dbl4 acc[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const bool bok = col < nb;
+    for (int64_t i = r0; i < r1; i += 4 * GRAM_UNROLL_B) {
+        double bv[GRAM_UNROLL_B], av[GRAM_UNROLL_B][MT];
+#pragma unroll
+        for (int u = 0; u < GRAM_UNROLL_B; ++u) {
+            const int64_t row = i + 4 * u + kk;
+            const bool rok = row < r1;
+            bv[u] = (rok && bok) ? *B.at(row, col) : 0.0;
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
+                const int a = t * 16 + col;
+                av[u][t] = (rok && a < ma) ? *A.at(row, a) : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GRAM_UNROLL_B; ++u)
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][t], bv[u], acc[t], 0, 0, 0);
+    }
+    __shared__ double red[4][MT][64][4];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[wave][t][lane][r] = acc[t][r];
+    __syncthreads();
+    for (int e = threadIdx.x; e < MT * 256; e += 256) {
+        const int t = e / 256, rem = e % 256, ln = rem / 4, r = rem % 4;
+        const double s = red[0][t][ln][r] + red[1][t][ln][r] + red[2][t][ln][r] + red[3][t][ln][r];
+        const int a = t * 16 + (ln >> 4) + 4 * r;
+        const int b = ln & 15;
+        if (a < ma && b < nb) partial[(int64_t)blockIdx.x * PSTRIDE + a * nb + b] = s;
+    }
+}
+
+// Out(i, c) = beta Out(i, c) + alpha sum_{j<m} A(i, j) B_inst[j][c] for the
+// rows of each chunk, with B_inst = Bs + inst * bstride (leading dimension
+// ldb).  A tile's A rows are all read (across a barrier) before the tile is
+// written, so Out may alias A.
+template <int NC>
+__global__ __launch_bounds__(256) void k_btsmm(const Chunk *__restrict__ chunks, const int32_t *__restrict__ done,
+                                               int m, Mat A, const double *__restrict__ Bs, int bstride, int ldb,
+                                               int nc, double alpha, double beta, Mat Out) {
+    const Chunk ch = chunks[blockIdx.x];
+    if (done[ch.inst]) return;
+    constexpr int ROWS = 256 / NC;
+    __shared__ double sA[ROWS * 16];
+    __shared__ double sB[MS * NC];
+    const double *B = Bs + (int64_t)ch.inst * bstride;
+    for (int t = threadIdx.x; t < m * NC; t += 256) {
+        const int j = t / NC, cc = t % NC;
+        sB[t] = cc < nc ? B[j * ldb + cc] : 0.0;
+    }
+    const int r = threadIdx.x / NC, c = threadIdx.x % NC;
+    const int kb = A.kb;
+    const int64_t end = ch.r0 + ch.n;
+    for (int64_t i0 = ch.r0; i0 < end; i0 += ROWS) {
+        double acc = 0.0;
+        for (int j0 = 0; j0 < m; j0 += kb) {
+            const int jn = min(kb, m - j0);
+            __syncthreads();
+            for (int f = threadIdx.x; f < ROWS * kb; f += 256) {
+                const int rr = f / kb, j = f % kb;
+                const int64_t row = i0 + rr;
+                sA[rr * 16 + j] = (row < end && j < jn) ? *A.at(row, j0 + j) : 0.0;
+            }
+            __syncthreads();
+            for (int j = 0; j < jn; ++j) acc += sA[r * 16 + j] * sB[(j0 + j) * NC + c];
+        }
+        __syncthreads();  // every read of this tile's A rows is done
+        const int64_t row = i0 + r;
+        if (row < end && c < nc) {
+            double *o = Out.at(row, c);
+            *o = (beta == 0.0 ? 0.0 : beta * *o) + alpha * acc;
+        }
+    }
+}
+
+// Ritz vectors, residuals and preconditioned corrections of every root:
+//   r_c = W y_c - theta_c V y_c,  T[i][c] = r_c[i] / clamp(theta_c - H_ii)
+// with per-chunk partial sums of r_c^2.
+template <int KK>
+__global__ __launch_bounds__(256) void k_britz(const Chunk *__restrict__ chunks, BDev st, int m, Mat V, Mat W,
+                                               const double *__restrict__ diag, double floor_,
+                                               double *__restrict__ T, double *__restrict__ rpart) {
+    const Chunk ch = chunks[blockIdx.x];
+    if (st.done[ch.inst]) return;
+    constexpr int ROWS = 256 / KK;
+    __shared__ double sV[ROWS * KK];
+    __shared__ double sW[ROWS * KK];
+    __shared__ double sY[MS * KK];
+    __shared__ double red[256];
+    const double *Yb = st.Y + (int64_t)ch.inst * MS * KB;
+    for (int t = threadIdx.x; t < m * KK; t += 256) sY[t] = Yb[(t / KK) * KB + t % KK];
+    const int r = threadIdx.x / KK, c = threadIdx.x % KK;
+    const double th = st.theta[ch.inst * KB + c];
+    const int64_t end = ch.r0 + ch.n;
+    double nrm = 0.0;
+    for (int64_t i0 = ch.r0; i0 < end; i0 += ROWS) {
+        double x = 0.0, w = 0.0;
+        const int64_t row = i0 + r;
+        const bool ok = row < end;
+        for (int j0 = 0; j0 < m; j0 += KK) {
+            __syncthreads();
+            sV[threadIdx.x] = ok ? *V.at(row, j0 + c) : 0.0;
+            sW[threadIdx.x] = ok ? *W.at(row, j0 + c) : 0.0;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < KK; ++j) {
+                const double y = sY[(j0 + j) * KK + c];
+                x += sV[r * KK + j] * y;
+                w += sW[r * KK + j] * y;
+            }
+        }
+        if (ok) {
+            const double res = w - th * x;
+            nrm += res * res;
+            double den = th - diag[row];
+            if (fabs(den) < floor_) den = den < 0.0 ? -floor_ : floor_;
+            T[row * KK + c] = res / den;
+        }
+    }
+    __syncthreads();
+    red[threadIdx.x] = nrm;
+    __syncthreads();
+    if (threadIdx.x < KK) {
+        double s = 0.0;
+        for (int q = 0; q < ROWS; ++q) s += red[q * KK + threadIdx.x];
+        rpart[(int64_t)blockIdx.x * RSTRIDE + threadIdx.x] = s;
+    }
+}
+
+// ------------------------------------------------------- per-instance kernels
+
+// Sum of the chunk partials of instance b, element e (fixed order).
+__device__ inline double chunk_sum(const double *__restrict__ part, int stride, int c0, int c1, int e) {
+    double s = 0.0;
+    for (int ch = c0; ch < c1; ++ch) s += part[(int64_t)ch * stride + e];
+    return s;
+}
+
+constexpr int RR_LD = MS + 1;
+constexpr size_t RR_LDS_BYTES = sizeof(double) * (2 * MS * RR_LD + 2 * MS * KB + 2 * KB * KB + KB + NT / 64 + MS) +
+                                sizeof(int) * (2 * MS + 2 * MS);
+
+// Rayleigh-Ritz of instance b at subspace size m: the last K columns of
+// G = V^T W arrive as chunk partials (gpart) and are folded into G; the valid
+// columns are diagonalized; theta and Y receive the lowest K Ritz pairs.
+// restart (m == m_max): the basis is replaced by an orthonormal basis Q of
+// the current and the previous Ritz vectors (GD+k); Q (for the tall update),
+// Q^T G Q, Q^T Y and the validity of the new columns are written.
+template <int KK>
+__global__ __launch_bounds__(NT) void k_brr(BDev st, int m, int restart, const double *__restrict__ gpart) {
+    const int b = blockIdx.x;
+    if (st.done[b]) return;
+    extern __shared__ double lds[];
+    double *A = lds;                       // MS x RR_LD
+    double *ZT = A + MS * RR_LD;           // MS x RR_LD
+    double *gn = ZT + MS * RR_LD;          // MS x KK: new columns, rows 0..m-1
+    double *Yn = gn + MS * KB;             // MS x KK
+    double *Y2 = Yn + MS * KB;             // 2KK x KK
+    double *th = Y2 + 2 * KB * KB;         // KK
+    double *red = th + KB;                 // NT/64
+    double *pc = red + NT / 64;            // MS/2
+    double *ps = pc + MS / 2;              // MS/2
+    int *pp = (int *)(ps + MS / 2);        // MS/2
+    int *pq = pp + MS / 2;                 // MS/2
+    int *vidx = pq + MS / 2;               // MS
+    int *misc = vidx + MS;                 // [0] nv, [1] kept mask
+    const int tid = threadIdx.x;
+    const int base = m - KK;
+    const int c0 = st.inst_chunk[b], c1 = st.inst_chunk[b + 1];
+    for (int e = tid; e < m * KK; e += NT) gn[e] = chunk_sum(gpart, PSTRIDE, c0, c1, e);
+    if (tid == 0) {
+        int n = 0;
+        for (int j = 0; j < m; ++j)
+            if (st.valid[b * MS + j]) vidx[n++] = j;
+        misc[0] = n;
+    }
+    __syncthreads();
+    const int nv = misc[0];
+    double *Gb = st.G + (int64_t)b * MS * MS;
+    // element (r, c) of the current G: old block from memory, new columns from gn
+    auto gval = [&](int r, int c) -> double {
+        if (r < base && c < base) return Gb[r * MS + c];
+        if (r < base) return gn[r * KK + (c - base)];
+        if (c < base) return gn[c * KK + (r - base)];
+        return 0.5 * (gn[r * KK + (c - base)] + gn[c * KK + (r - base)]);
+    };
+    for (int e = tid; e < nv * nv; e += NT) {
+        const int i = e / nv, j = e % nv;
+        A[i * RR_LD + j] = gval(vidx[i], vidx[j]);
+    }
+    __syncthreads();
+    block_jacobi<RR_LD>(nv, A, ZT, pp, pq, pc, ps, red);
+    __syncthreads();
+    for (int e = tid; e < MS * KK; e += NT) Yn[e] = 0.0;
+    if (tid < KK) th[tid] = 0.0;
+    __syncthreads();
+    // lowest KK eigenpairs in ascending order (ties: lower index first)
+    for (int j = tid; j < nv; j += NT) {
+        const double d = A[j * RR_LD + j];
+        int rank = 0;
+        for (int i = 0; i < nv; ++i) {
+            const double x = A[i * RR_LD + i];
+            rank += (x < d || (x == d && i < j)) ? 1 : 0;
+        }
+        if (rank < KK) {
+            th[rank] = d;
+            for (int i = 0; i < nv; ++i) Yn[vidx[i] * KK + rank] = ZT[j * RR_LD + i];
+        }
+    }
+    __syncthreads();
+    double *Yb = st.Y + (int64_t)b * MS * KB;
+    if (tid < KB) st.theta[b * KB + tid] = tid < KK ? th[tid] : 0.0;
+    if (!restart) {
+        for (int e = tid; e < MS * KB; e += NT) {
+            const int a = e / KB, q = e % KB;
+            Yb[e] = (a < m && q < KK) ? Yn[a * KK + q] : 0.0;
+        }
+        for (int e = tid; e < m * KK; e += NT) {
+            const int r = e / KK, c = base + e % KK;
+            const double v = gval(r, c);
+            Gb[r * MS + c] = v;
+            if (r < base) Gb[c * MS + r] = v;
+        }
+        return;
+    }
+    // ---- GD+k restart
+    constexpr int Q2 = 2 * KK;
+    double *Qs = A;            // m x Q2
+    double *GQ = A + MS * Q2;  // m x Q2
+    double *Gs = ZT;           // m x m, leading dimension RR_LD
+    for (int e = tid; e < m * m; e += NT) {
+        const int r = e / m, c = e % m;
+        Gs[r * RR_LD + c] = gval(r, c);
+    }
+    if (tid < 64) {  // modified Gram-Schmidt, twice, by wave 0; lane a owns row a
+        const int a = tid;
+        unsigned kept = 0u;
+        for (int c = 0; c < Q2; ++c) {
+            double v = 0.0;
+            if (a < m) v = c < KK ? Yn[a * KK + c] : Yb[a * KB + (c - KK)];
+            const double n0 = sqrt(wave_sum(v * v));
+            bool keep = n0 > 0.0;
+            if (keep) {
+                for (int pass = 0; pass < 2; ++pass)
+                    for (int u = 0; u < c; ++u) {
+                        if (!((kept >> u) & 1u)) continue;
+                        const double qu = a < m ? Qs[a * Q2 + u] : 0.0;
+                        const double d = wave_sum(qu * v);
+                        v -= d * qu;
+                    }
+                const double n1 = sqrt(wave_sum(v * v));
+                keep = n1 > 1e-8 * n0;
+                if (keep) v /= n1;
+            }
+            if (a < m) Qs[a * Q2 + c] = keep ? v : 0.0;
+            if (keep) kept |= 1u << c;
+        }
+        if (a == 0) misc[1] = (int)kept;
+    }
+    __syncthreads();
+    const unsigned kept = (unsigned)misc[1];
+    for (int e = tid; e < Q2 * KK; e += NT) {  // Ritz coefficients in the new basis
+        const int i = e / KK, q = e % KK;
+        double s = 0.0;
+        for (int a = 0; a < m; ++a) s += Qs[a * Q2 + i] * Yn[a * KK + q];
+        Y2[e] = s;
+    }
+    for (int e = tid; e < m * Q2; e += NT) {
+        const int r = e / Q2, j = e % Q2;
+        double s = 0.0;
+        for (int c = 0; c < m; ++c) s += Gs[r * RR_LD + c] * Qs[c * Q2 + j];
+        GQ[e] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < Q2 * Q2; e += NT) {
+        const int i = e / Q2, j = e % Q2;
+        double s1 = 0.0, s2 = 0.0;
+        for (int a = 0; a < m; ++a) {
+            s1 += Qs[a * Q2 + i] * GQ[a * Q2 + j];
+            s2 += Qs[a * Q2 + j] * GQ[a * Q2 + i];
+        }
+        Gb[i * MS + j] = 0.5 * (s1 + s2);
+    }
+    double *Qb = st.Q + (int64_t)b * MS * 2 * KB;
+    for (int e = tid; e < m * Q2; e += NT) Qb[e] = Qs[e];
+    for (int c = tid; c < MS; c += NT) st.valid[b * MS + c] = (c < Q2 && ((kept >> c) & 1u)) ? 1 : 0;
+    for (int e = tid; e < MS * KB; e += NT) {
+        const int a = e / KB, q = e % KB;
+        Yb[e] = (a < Q2 && q < KK) ? Y2[a * KK + q] : 0.0;
+    }
+}
+
+// After the Ritz step and the first Gram product [V T]^T T: residual norms,
+// convergence of the lowest root, the projection coefficients C = V^T T and
+// the unit scales of the corrections that are kept (roots with ||r|| > tol).
+template <int KK>
+__global__ __launch_bounds__(NT) void k_bpost_first(BDev st, int m, double tol, const double *__restrict__ rpart,
+                                                    const double *__restrict__ gpart) {
+    const int b = blockIdx.x;
+    if (st.done[b]) return;
+    __shared__ double rn2[KK];
+    __shared__ double g1[MS * KK];
+    const int tid = threadIdx.x;
+    const int c0 = st.inst_chunk[b], c1 = st.inst_chunk[b + 1];
+    if (tid < KK) rn2[tid] = chunk_sum(rpart, RSTRIDE, c0, c1, tid);
+    for (int e = tid; e < (m + KK) * KK; e += NT) g1[e] = chunk_sum(gpart, PSTRIDE, c0, c1, e);
+    __syncthreads();
+    const double r0 = sqrt(fmax(0.0, rn2[0]));
+    if (tid == 0) {
+        st.iters[b] += 1;
+        st.resid[b] = r0;
+        if (r0 <= tol) {
+            st.done[b] = 1;
+            st.energy[b] = st.theta[b * KB];
+            st.mfin[b] = m;
+        }
+    }
+    if (r0 <= tol) return;
+    if (tid < KK) {
+        const double rq = sqrt(fmax(0.0, rn2[tid]));
+        const double nq = g1[(m + tid) * KK + tid];
+        st.scl[b * KB + tid] = (rq > tol && nq > 0.0 && isfinite(nq)) ? 1.0 / sqrt(nq) : 0.0;
+    }
+    double *Cb = st.C + (int64_t)b * MS * KB;
+    for (int e = tid; e < m * KK; e += NT) Cb[(e / KK) * KB + e % KK] = g1[e];
+}
+
+// C = V^T T from the chunk partials.
+template <int KK>
+__global__ __launch_bounds__(NT) void k_bpost_proj(BDev st, int m, const double *__restrict__ gpart) {
+    const int b = blockIdx.x;
+    if (st.done[b]) return;
+    const int c0 = st.inst_chunk[b], c1 = st.inst_chunk[b + 1];
+    double *Cb = st.C + (int64_t)b * MS * KB;
+    for (int e = threadIdx.x; e < m * KK; e += NT) Cb[(e / KK) * KB + e % KK] = chunk_sum(gpart, PSTRIDE, c0, c1, e);
+}
+
+// Symmetric orthonormalization of the new block T from g = T^T T: with
+// S = diag(scl) in the first round (unit columns, dropped roots zero) and
+// S = I in the second, S g S = Z diag(w) Z^T and T <- T S Z_k w_k^(-1/2) over
+// the eigenvalues w_k > thresh, largest first.  No kept direction: the
+// instance stops (its current Ritz pair is the result).  The second round
+// marks the new basis columns valid.
+template <int KK>
+__global__ __launch_bounds__(NT) void k_bpost_orth(BDev st, int m, int round, double thresh,
+                                                   const double *__restrict__ gpart) {
+    const int b = blockIdx.x;
+    if (st.done[b]) return;
+    constexpr int LD = KK + 1;
+    __shared__ double A[KK * LD], ZT[KK * LD], sc[KK], red[NT / 64];
+    __shared__ double pc[KK], ps[KK];
+    __shared__ int pp[KK], pq[KK], nk_s;
+    const int tid = threadIdx.x;
+    const int c0 = st.inst_chunk[b], c1 = st.inst_chunk[b + 1];
+    if (tid < KK) sc[tid] = round == 0 ? st.scl[b * KB + tid] : 1.0;
+    for (int e = tid; e < KK * KK; e += NT) ZT[(e / KK) * LD + e % KK] = chunk_sum(gpart, PSTRIDE, c0, c1, e);
+    __syncthreads();
+    for (int e = tid; e < KK * KK; e += NT) {
+        const int i = e / KK, j = e % KK;
+        A[i * LD + j] = sc[i] * sc[j] * 0.5 * (ZT[i * LD + j] + ZT[j * LD + i]);
+    }
+    __syncthreads();
+    block_jacobi<LD>(KK, A, ZT, pp, pq, pc, ps, red);
+    __syncthreads();
+    double *Zb = st.Z + (int64_t)b * KB * KB;
+    for (int e = tid; e < KB * KB; e += NT) Zb[e] = 0.0;
+    if (tid == 0) {
+        int n = 0;
+        for (int j = 0; j < KK; ++j) {
+            const double w = A[j * LD + j];
+            n += (isfinite(w) && w > thresh) ? 1 : 0;
+        }
+        nk_s = n;
+    }
+    __syncthreads();
+    if (tid < KK) {
+        const int j = tid;
+        const double w = A[j * LD + j];
+        if (isfinite(w) && w > thresh) {
+            int rank = 0;
+            for (int i = 0; i < KK; ++i) {
+                const double x = A[i * LD + i];
+                if (isfinite(x) && x > thresh && (x > w || (x == w && i < j))) ++rank;
+            }
+            const double inv = 1.0 / sqrt(w);
+            for (int a = 0; a < KK; ++a) Zb[a * KB + rank] = sc[a] * ZT[j * LD + a] * inv;
+        }
+    }
+    const int nk = nk_s;
+    if (tid == 0 && nk == 0) {
+        st.done[b] = 2;
+        st.energy[b] = st.theta[b * KB];
+        st.mfin[b] = m;
+    }
+    if (round == 1 && tid < KK) st.valid[b * MS + m + tid] = tid < nk ? 1 : 0;
+}
+
+// Coupling-balanced XCD row ranges over the instances still running: range x
+// starts at the first row whose running-coupling prefix reaches x/8 of the
+// total.  One thread per bound.
+__global__ void k_bbalance(int nb, const int64_t *__restrict__ inst_row, const int64_t *__restrict__ rowptr,
+                           const int32_t *__restrict__ done, int64_t *__restrict__ ranges) {
+    const int x = threadIdx.x;
+    if (x > 8) return;
+    const int64_t N = inst_row[nb];
+    if (x == 0 || x == 8) {
+        ranges[x] = x == 0 ? 0 : N;
+        return;
+    }
+    int64_t tot = 0;
+    for (int b = 0; b < nb; ++b)
+        if (!done[b]) tot += rowptr[inst_row[b + 1]] - rowptr[inst_row[b]];
+    const int64_t t = tot / 8 * x + (tot % 8) * x / 8;
+    int64_t acc = 0;
+    for (int b = 0; b < nb; ++b) {
+        if (done[b]) continue;
+        const int64_t z0 = rowptr[inst_row[b]], nz = rowptr[inst_row[b + 1]] - z0;
+        if (acc + nz > t) {
+            int64_t lo = inst_row[b], hi = inst_row[b + 1];
+            const int64_t want = t - acc + z0;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) / 2;
+                if (rowptr[mid] < want) lo = mid + 1;
+                else hi = mid;
+            }
+            ranges[x] = lo;
+            return;
+        }
+        acc += nz;
+    }
+    ranges[x] = N;
+}
+
+__global__ void k_bcount(int nb, const int32_t *__restrict__ done, int32_t *__restrict__ out) {
+    __shared__ int red[256];
+    int n = 0;
+    for (int b = threadIdx.x; b < nb; b += 256) n += done[b] != 0 ? 1 : 0;
+    red[threadIdx.x] = n;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+__global__ void k_bvalid_init(int nb, int K, int32_t *valid) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (int64_t)nb * MS) valid[t] = (int)(t % MS) < K ? 1 : 0;
+}
+
+// Initial block of instance b: unit vectors at its K lowest diagonal elements
+// (lexicographic (value, row) order), written into V's first column block
+// (which is zero on entry).
+__global__ __launch_bounds__(256) void k_binit(int K, const int64_t *__restrict__ inst_row,
+                                               const double *__restrict__ diag, double *__restrict__ V0) {
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int64_t r0 = inst_row[b], r1 = inst_row[b + 1];
+    __shared__ int64_t chosen[KB];
+    __shared__ double sv[256];
+    __shared__ int64_t si[256];
+    for (int r = 0; r < K; ++r) {
+        double best = INFINITY;
+        int64_t bi = INT64_MAX;
+        for (int64_t i = r0 + tid; i < r1; i += 256) {
+            bool skip = false;
+            for (int e = 0; e < r; ++e) skip |= chosen[e] == i;
+            if (skip) continue;
+            const double v = diag[i];
+            if (v < best || (v == best && i < bi)) {
+                best = v;
+                bi = i;
+            }
+        }
+        sv[tid] = best;
+        si[tid] = bi;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s) {
+                const double v = sv[tid + s];
+                const int64_t j = si[tid + s];
+                if (v < sv[tid] || (v == sv[tid] && j < si[tid])) {
+                    sv[tid] = v;
+                    si[tid] = j;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) chosen[r] = si[0];
+        __syncthreads();
+    }
+    if (tid < K && chosen[tid] >= r0 && chosen[tid] < r1) V0[chosen[tid] * K + tid] = 1.0;
+}
+
+// Final vector of every instance: x = V y_0 over the instance's final
+// subspace, with per-chunk partials of ||x||^2 and of the largest |x_i|
+// (lowest row on ties).
+__global__ __launch_bounds__(256) void k_bfinal_x(const Chunk *__restrict__ chunks, BDev st, int m_last, Mat V,
+                                                  double *__restrict__ x, double *__restrict__ fpart,
+                                                  int64_t *__restrict__ ipart) {
+    const Chunk ch = chunks[blockIdx.x];
+    const int b = ch.inst, tid = threadIdx.x;
+    const int mu = st.done[b] ? st.mfin[b] : m_last;
+    __shared__ double sy[MS];
+    __shared__ double sv[256], sn[256];
+    __shared__ int64_t si[256];
+    for (int j = tid; j < mu; j += 256) sy[j] = st.Y[(int64_t)b * MS * KB + j * KB];
+    __syncthreads();
+    const int64_t end = ch.r0 + ch.n;
+    double n2 = 0.0, best = -1.0;
+    int64_t bi = INT64_MAX;
+    for (int64_t i = ch.r0 + tid; i < end; i += 256) {
+        double s = 0.0;
+        for (int j = 0; j < mu; ++j) s += *V.at(i, j) * sy[j];
+        x[i] = s;
+        n2 += s * s;
+        const double a = fabs(s);
+        if (a > best || (a == best && i < bi)) {
+            best = a;
+            bi = i;
+        }
+    }
+    sn[tid] = n2;
+    sv[tid] = best;
+    si[tid] = bi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            sn[tid] += sn[tid + s];
+            const double v = sv[tid + s];
+            const int64_t j = si[tid + s];
+            if (v > sv[tid] || (v == sv[tid] && j < si[tid])) {
+                sv[tid] = v;
+                si[tid] = j;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        fpart[blockIdx.x * 2] = sn[0];
+        fpart[blockIdx.x * 2 + 1] = sv[0];
+        ipart[blockIdx.x] = si[0];
+    }
+}
+
+// Per instance: norm and gauge of the final vector (largest component
+// positive), and the energy of instances that did not converge.
+__global__ void k_bfinal_red(BDev st, const double *__restrict__ fpart, const int64_t *__restrict__ ipart,
+                             const double *__restrict__ x, double *__restrict__ ss) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= st.nb) return;
+    double n2 = 0.0, best = -1.0;
+    int64_t bi = INT64_MAX;
+    for (int ch = st.inst_chunk[b]; ch < st.inst_chunk[b + 1]; ++ch) {
+        n2 += fpart[ch * 2];
+        const double v = fpart[ch * 2 + 1];
+        const int64_t j = ipart[ch];
+        if (v > best || (v == best && j < bi)) {
+            best = v;
+            bi = j;
+        }
+    }
+    ss[b * 2] = n2 > 0.0 ? 1.0 / sqrt(n2) : 1.0;
+    ss[b * 2 + 1] = (bi != INT64_MAX && x[bi] < 0.0) ? -1.0 : 1.0;
+    if (!st.done[b]) st.energy[b] = st.theta[b * KB];
+}
+
+__global__ void k_bscatter(int64_t N, const double *__restrict__ x, const int32_t *__restrict__ row_inst,
+                           const int64_t *__restrict__ inst_row, const int32_t *__restrict__ perm,
+                           const double *__restrict__ ss, int sorted, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int b = row_inst[i];
+    const int64_t r0 = inst_row[b];
+    const int64_t dst = r0 + (sorted ? (i - r0) : (int64_t)perm[i]);
+    out[dst] = x[i] * ss[b * 2] * ss[b * 2 + 1];
+}
+
+// ----------------------------------------------------------- concatenation
+
+__global__ void k_cat_rowptr(int64_t n, const int64_t *__restrict__ src, int64_t *__restrict__ dst, int64_t nz0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= n) dst[i] = src[i] + nz0;
+}
+
+__global__ void k_cat_col(int64_t n, const int32_t *__restrict__ src, int32_t *__restrict__ dst, int32_t row0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i] + row0;
+}
+
+__global__ void k_fill_i32(int64_t n, int32_t *__restrict__ dst, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = v;
+}
+
+// ------------------------------------------------------------- host side
+
+template <typename T>
+void copy_d2d(T *dst, const T *src, int64_t n, hipStream_t s) {
+    if (n > 0) HQ_CHECK(hipMemcpyAsync(dst, src, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+}
+
+// Merge the pending instances into the block-diagonal matrix.
+void batch_plan(Ctx &c, BatchState &B) {
+    if (B.pending.empty()) return;
+    hipStream_t s = c.stream;
+    const int nb = (int)B.meta.size();
+    const int64_t N0 = B.nmerged > 0 ? B.g.ndet : 0, Z0 = B.nmerged > 0 ? B.g.nnz : 0;
+    const int64_t N = B.row_off[nb], Z = B.nz_off[nb];
+    if (N >= ((int64_t)1 << 31) - 1) throw Error(HINQS_E_UNSUPPORTED, "a batch holds fewer than 2^31 determinants");
+    DBuf<int64_t> rowptr;
+    DBuf<int32_t> col, perm, row_inst;
+    DBuf<double> val, diag;
+    rowptr.ensure(N + 1);
+    col.ensure(std::max<int64_t>(Z, 1));
+    val.ensure(std::max<int64_t>(Z, 1));
+    diag.ensure(N);
+    perm.ensure(N);
+    row_inst.ensure(N);
+    if (N0 > 0) {
+        copy_d2d(rowptr.p, B.g.rowptr.p, N0 + 1, s);
+        copy_d2d(col.p, B.g.col.p, Z0, s);
+        copy_d2d(val.p, B.g.val.p, Z0, s);
+        copy_d2d(diag.p, B.g.diag.p, N0, s);
+        copy_d2d(perm.p, B.perm.p, N0, s);
+        copy_d2d(row_inst.p, B.row_inst.p, N0, s);
+    }
+    for (size_t j = 0; j < B.pending.size(); ++j) {
+        Ctx &p = *B.pending[j];
+        const int bi = B.nmerged + (int)j;
+        const int64_t r0 = B.row_off[bi], z0 = B.nz_off[bi];
+        hipLaunchKernelGGL(k_cat_rowptr, dim3(grid_for(p.ndet + 1, 256)), dim3(256), 0, s, p.ndet, p.rowptr.p,
+                           rowptr.p + r0, z0);
+        HQ_LAUNCH_CHECK();
+        if (p.nnz > 0) {
+            hipLaunchKernelGGL(k_cat_col, dim3(grid_for(p.nnz, 256)), dim3(256), 0, s, p.nnz, p.col.p, col.p + z0,
+                               (int32_t)r0);
+            HQ_LAUNCH_CHECK();
+            copy_d2d(val.p + z0, p.val.p, p.nnz, s);
+        }
+        copy_d2d(diag.p + r0, p.diag.p, p.ndet, s);
+        copy_d2d(perm.p + r0, p.perm.p, p.ndet, s);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(p.ndet, 256)), dim3(256), 0, s, p.ndet, row_inst.p + r0,
+                           (int32_t)bi);
+        HQ_LAUNCH_CHECK();
+    }
+    HQ_CHECK(hipStreamSynchronize(s));
+    B.g.rowptr.swap(rowptr);
+    B.g.col.swap(col);
+    B.g.val.swap(val);
+    B.g.diag.swap(diag);
+    B.perm.swap(perm);
+    B.row_inst.swap(row_inst);
+    B.g.device = c.device;
+    B.g.stream = c.stream;
+    B.g.ndet = N;
+    B.g.nnz = Z;
+    B.g.have_elements = true;
+    for (auto &row : B.g.sigma_cfg)
+        for (auto &cfg : row) cfg = SigmaCfg{};
+    compute_xcd_rows(B.g);
+    B.inst_row.ensure(nb + 1);
+    HQ_CHECK(hipMemcpyAsync(B.inst_row.p, B.row_off.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s));
+    HQ_CHECK(hipStreamSynchronize(s));
+    B.pending.clear();
+    B.nmerged = nb;
+}
+
+int env_or(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    return (v && *v) ? std::atoi(v) : dflt;
+}
+
+struct Resources {  // released on every exit path
+    hipStream_t bs = nullptr;
+    hipEvent_t ev = nullptr;
+    std::vector<hipGraphExec_t> ex;
+    bool capturing = false;
+    ~Resources() {
+        if (capturing && bs) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(bs, &g);
+            if (g) (void)hipGraphDestroy(g);
+        }
+        for (auto e : ex)
+            if (e) (void)hipGraphExecDestroy(e);
+        if (bs) (void)hipStreamSynchronize(bs);
+        if (ev) (void)hipEventDestroy(ev);
+        if (bs) (void)hipStreamDestroy(bs);
+    }
+};
+
+template <int KK>
+int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *energies, double *coeffs,
+                  int *status, int *iters_out, hinqs_batch_stats *stats,
+                  std::chrono::steady_clock::time_point t0) {
+    const int nb = (int)B.meta.size();
+    const int64_t N = B.g.ndet;
+    const int maxit = o.max_iter > 0 ? o.max_iter : 200;
+    const bool use_graph = !(o.flags & HINQS_NO_GRAPH);
+    const bool sorted = (o.flags & HINQS_SORTED_ORDER) != 0;
+    if (o.flags & HINQS_AUTOTUNE) autotune_sigma(B.g, KK, HINQS_FP64);
+    const SigmaCfg scfg = sigma_config(B.g, KK, HINQS_FP64);
+
+    // ---- chunk list: runs of at most CH rows of one instance
+    const int CH = std::max(64, env_or("HINQS_BATCH_CHUNK", 2048));
+    std::vector<Chunk> chunks;
+    std::vector<int32_t> inst_chunk(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) {
+        inst_chunk[b] = (int32_t)chunks.size();
+        for (int64_t r = B.row_off[b]; r < B.row_off[b + 1]; r += CH)
+            chunks.push_back(Chunk{r, (int32_t)std::min<int64_t>(CH, B.row_off[b + 1] - r), b});
+    }
+    inst_chunk[nb] = (int32_t)chunks.size();
+    const int nch = (int)chunks.size();
+
+    // buffers, all allocated before any capture (declared before R: R's
+    // destructor drains the stream before they are freed)
+    DBuf<double> Vb, Wb, gpart, gpart_u, rpart, state, xfin, fpart, ss;
+    DBuf<int32_t> istate, d_ndone, d_inst_chunk;
+    DBuf<int64_t> ranges, ipart;
+    DBuf<Chunk> d_chunks;
+    Resources R;
+    HQ_CHECK(hipStreamCreateWithFlags(&R.bs, hipStreamNonBlocking));
+    HQ_CHECK(hipEventCreateWithFlags(&R.ev, hipEventDisableTiming));
+    HQ_CHECK(hipEventRecord(R.ev, c.stream));  // work queued on the caller's stream comes first
+    HQ_CHECK(hipStreamWaitEvent(R.bs, R.ev, 0));
+    hipStream_t s = R.bs;
+
+    const int nblocks = mmax / KK;
+    const size_t bsz = (size_t)N * KK;
+    Vb.ensure(bsz * nblocks);
+    Wb.ensure(bsz * nblocks);
+    gpart.ensure((size_t)nch * PSTRIDE);
+    gpart_u.ensure((size_t)nch * PSTRIDE);
+    rpart.ensure((size_t)nch * RSTRIDE);
+    const size_t n_state = (size_t)nb * (MS * MS + MS * KB + KB + MS * 2 * KB + MS * KB + KB * KB + KB + 2);
+    state.ensure(n_state);
+    istate.ensure((size_t)nb * (3 + MS));
+    d_ndone.ensure(1);
+    ranges.ensure(9);
+    d_chunks.ensure(nch);
+    d_inst_chunk.ensure(nb + 1);
+    xfin.ensure(N);
+    fpart.ensure((size_t)nch * 2);
+    ipart.ensure(nch);
+    ss.ensure((size_t)nb * 2);
+    HQ_CHECK(hipMemcpyAsync(d_chunks.p, chunks.data(), sizeof(Chunk) * nch, hipMemcpyHostToDevice, s));
+    HQ_CHECK(hipMemcpyAsync(d_inst_chunk.p, inst_chunk.data(), sizeof(int32_t) * (nb + 1), hipMemcpyHostToDevice, s));
+    HQ_CHECK(hipMemsetAsync(Vb.p, 0, sizeof(double) * bsz * nblocks, s));
+    HQ_CHECK(hipMemsetAsync(Wb.p, 0, sizeof(double) * bsz * nblocks, s));
+    HQ_CHECK(hipMemsetAsync(state.p, 0, sizeof(double) * n_state, s));
+    HQ_CHECK(hipMemsetAsync(istate.p, 0, sizeof(int32_t) * nb * (3 + MS), s));
+    BDev st{};
+    st.nb = nb;
+    st.inst_chunk = d_inst_chunk.p;
+    st.done = istate.p;
+    st.iters = st.done + nb;
+    st.mfin = st.iters + nb;
+    st.valid = st.mfin + nb;  // nb * MS
+    {
+        double *p = state.p;
+        st.G = p;      p += (size_t)nb * MS * MS;
+        st.Y = p;      p += (size_t)nb * MS * KB;
+        st.theta = p;  p += (size_t)nb * KB;
+        st.Q = p;      p += (size_t)nb * MS * 2 * KB;
+        st.C = p;      p += (size_t)nb * MS * KB;
+        st.Z = p;      p += (size_t)nb * KB * KB;
+        st.scl = p;    p += (size_t)nb * KB;
+        st.energy = p; p += nb;
+        st.resid = p;  p += nb;
+    }
+    hipLaunchKernelGGL(k_bvalid_init, dim3(grid_for((int64_t)nb * MS, 256)), dim3(256), 0, s, nb, KK, st.valid);
+    HQ_LAUNCH_CHECK();
+    HQ_CHECK(hipFuncSetAttribute((const void *)k_brr<KK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)RR_LDS_BYTES));
+
+    const Mat V{Vb.p, KK, (int64_t)bsz}, W{Wb.p, KK, (int64_t)bsz};
+    SigmaMask mk;
+    mk.ranges = ranges.p;
+    mk.row_inst = B.row_inst.p;
+    mk.inst_row = B.inst_row.p;
+    mk.done = st.done;
+    const Chunk *dch = d_chunks.p;
+    const dim3 gch(nch), gin(nb), b256(256);
+
+    auto gram = [&](Mat A, int ma, Mat Bm, double *part) {
+        const int mt = (ma + 15) / 16;
+        switch (mt) {
+            case 1: hipLaunchKernelGGL(k_bgram<1>, gch, b256, 0, s, dch, st.done, A, ma, Bm, KK, part); break;
+            case 2: hipLaunchKernelGGL(k_bgram<2>, gch, b256, 0, s, dch, st.done, A, ma, Bm, KK, part); break;
+            case 3: hipLaunchKernelGGL(k_bgram<3>, gch, b256, 0, s, dch, st.done, A, ma, Bm, KK, part); break;
+            default: hipLaunchKernelGGL(k_bgram<4>, gch, b256, 0, s, dch, st.done, A, ma, Bm, KK, part); break;
+        }
+        HQ_LAUNCH_CHECK();
+    };
+    // Out = beta Out + alpha A[:, 0:m] B_inst (nc columns)
+    auto tsmm = [&](Mat A, int m, const double *Bs, int bstride, int ldb, auto ncc, double alpha, double beta,
+                    Mat Out) {
+        constexpr int NC = decltype(ncc)::value;
+        hipLaunchKernelGGL(k_btsmm<NC>, gch, b256, 0, s, dch, st.done, m, A, Bs, bstride, ldb, NC, alpha, beta,
+                           Out);
+        HQ_LAUNCH_CHECK();
+    };
+    using NK = std::integral_constant<int, KK>;
+    using N2K = std::integral_constant<int, 2 * KK>;
+    Ctx &g = B.g;
+    auto sigma = [&](const double *X, double *S) {
+        hipLaunchKernelGGL(k_bbalance, dim3(1), dim3(64), 0, s, nb, B.inst_row.p, g.rowptr.p, st.done, ranges.p);
+        HQ_LAUNCH_CHECK();
+        sigma_masked_fp64(g, KK, X, S, mk, s);
+    };
+
+    // ---- initial block (unit vectors at the lowest diagonal elements), its images and G
+    hipLaunchKernelGGL(k_binit, gin, b256, 0, s, KK, B.inst_row.p, g.diag.p, Vb.p);
+    HQ_LAUNCH_CHECK();
+    sigma(V.p, W.p);
+    gram(V, KK, W, gpart_u.p);
+
+    // ---- one iteration at subspace size m (m - KK columns old, KK new);
+    // returns the subspace size after the optional restart
+    const double tol = o.tol, floor_ = o.precond_floor;
+    auto phase = [&](int m) -> int {
+        const int restart = (m == mmax) ? 1 : 0;
+        const int mp = restart ? 2 * KK : m;
+        hipLaunchKernelGGL(k_brr<KK>, gin, dim3(NT), RR_LDS_BYTES, s, st, m, restart, (const double *)gpart_u.p);
+        HQ_LAUNCH_CHECK();
+        if (restart) {
+            tsmm(V, m, st.Q, MS * 2 * KB, 2 * KK, N2K{}, 1.0, 0.0, V);
+            tsmm(W, m, st.Q, MS * 2 * KB, 2 * KK, N2K{}, 1.0, 0.0, W);
+        }
+        const Mat T = V.cols(mp);
+        hipLaunchKernelGGL(k_britz<KK>, gch, b256, 0, s, dch, st, mp, V, W, (const double *)g.diag.p, floor_, T.p,
+                           rpart.p);
+        HQ_LAUNCH_CHECK();
+        // CGS2 against the basis, with T^T T from the first product
+        gram(V, mp + KK, T, gpart.p);
+        hipLaunchKernelGGL(k_bpost_first<KK>, gin, dim3(NT), 0, s, st, mp, tol, (const double *)rpart.p,
+                           (const double *)gpart.p);
+        HQ_LAUNCH_CHECK();
+        tsmm(V, mp, st.C, MS * KB, KB, NK{}, -1.0, 1.0, T);
+        gram(V, mp, T, gpart.p);
+        hipLaunchKernelGGL(k_bpost_proj<KK>, gin, dim3(NT), 0, s, st, mp, (const double *)gpart.p);
+        HQ_LAUNCH_CHECK();
+        tsmm(V, mp, st.C, MS * KB, KB, NK{}, -1.0, 1.0, T);
+        // symmetric orthonormalization within the block (unit columns first)
+        const Mat Tm{T.p, KK, (int64_t)bsz};
+        gram(Tm, KK, Tm, gpart.p);
+        hipLaunchKernelGGL(k_bpost_orth<KK>, gin, dim3(NT), 0, s, st, mp, 0, 1e-14, (const double *)gpart.p);
+        HQ_LAUNCH_CHECK();
+        tsmm(Tm, KK, st.Z, KB * KB, KB, NK{}, 1.0, 0.0, Tm);
+        // one more projection and orthonormalization remove what the scaling amplified
+        gram(V, mp, T, gpart.p);
+        hipLaunchKernelGGL(k_bpost_proj<KK>, gin, dim3(NT), 0, s, st, mp, (const double *)gpart.p);
+        HQ_LAUNCH_CHECK();
+        tsmm(V, mp, st.C, MS * KB, KB, NK{}, -1.0, 1.0, T);
+        gram(Tm, KK, Tm, gpart.p);
+        hipLaunchKernelGGL(k_bpost_orth<KK>, gin, dim3(NT), 0, s, st, mp, 1, 1e-4, (const double *)gpart.p);
+        HQ_LAUNCH_CHECK();
+        tsmm(Tm, KK, st.Z, KB * KB, KB, NK{}, 1.0, 0.0, Tm);
+        // images and the new columns of G
+        const Mat Wn = W.cols(mp);
+        sigma(T.p, Wn.p);
+        gram(V, mp + KK, Wn, gpart_u.p);
+        hipLaunchKernelGGL(k_bcount, dim3(1), b256, 0, s, nb, (const int32_t *)st.done, d_ndone.p);
+        HQ_LAUNCH_CHECK();
+        return mp;
+    };
+
+    HQ_CHECK(hipStreamSynchronize(s));
+    const auto t1 = std::chrono::steady_clock::now();
+    R.ex.assign(mmax / KK + 1, nullptr);
+    int m = KK, it = 0, m_last = KK, ngraphs = 0;
+    int32_t ndone = 0;
+    double ms_capture = 0.0;
+    while (it < maxit) {
+        int mp;
+        if (use_graph) {
+            hipGraphExec_t &ex = R.ex[m / KK];
+            if (!ex) {
+                const auto tc = std::chrono::steady_clock::now();
+                HQ_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                R.capturing = true;
+                phase(m);
+                hipGraph_t graph = nullptr;
+                R.capturing = false;
+                HQ_CHECK(hipStreamEndCapture(s, &graph));
+                const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                HQ_CHECK(e);
+                ++ngraphs;
+                ms_capture += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tc).count();
+            }
+            HQ_CHECK(hipGraphLaunch(ex, s));
+            mp = (m == mmax) ? 2 * KK : m;
+        } else {
+            mp = phase(m);
+        }
+        ++it;
+        m_last = mp;
+        HQ_CHECK(hipMemcpyAsync(&ndone, d_ndone.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HQ_CHECK(hipStreamSynchronize(s));
+        if (ndone >= nb) break;
+        m = mp + KK;
+    }
+    const auto t2 = std::chrono::steady_clock::now();
+
+    // ---- final vectors: x = V y_0, normalized, largest component positive, caller order
+    hipLaunchKernelGGL(k_bfinal_x, gch, b256, 0, s, dch, st, m_last, V, xfin.p, fpart.p, ipart.p);
+    HQ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_bfinal_red, dim3((nb + 63) / 64), dim3(64), 0, s, st, (const double *)fpart.p,
+                       (const int64_t *)ipart.p, (const double *)xfin.p, ss.p);
+    HQ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_bscatter, dim3(grid_for(N, 256)), b256, 0, s, N, (const double *)xfin.p,
+                       (const int32_t *)B.row_inst.p, (const int64_t *)B.inst_row.p, (const int32_t *)B.perm.p,
+                       (const double *)ss.p, sorted ? 1 : 0, coeffs);
+    HQ_LAUNCH_CHECK();
+    std::vector<double> e_h(nb), r_h(nb);
+    std::vector<int32_t> done_h(nb), it_h(nb);
+    HQ_CHECK(hipMemcpyAsync(e_h.data(), st.energy, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipMemcpyAsync(r_h.data(), st.resid, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipMemcpyAsync(done_h.data(), st.done, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipMemcpyAsync(it_h.data(), st.iters, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipStreamSynchronize(s));
+    HQ_CHECK(hipEventRecord(R.ev, s));  // the caller's stream sees the outputs
+    HQ_CHECK(hipStreamWaitEvent(c.stream, R.ev, 0));
+    int nconv = 0;
+    double maxres = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        energies[b] = e_h[b];
+        const bool ok = done_h[b] == 1;
+        nconv += ok ? 1 : 0;
+        if (status) status[b] = ok ? HINQS_OK : HINQS_E_NOT_CONVERGED;
+        if (iters_out) iters_out[b] = it_h[b];
+        maxres = std::max(maxres, r_h[b]);
+    }
+    if (stats) {
+        stats->instances = nb;
+        stats->converged = nconv;
+        stats->iterations = it;
+        stats->graphs = ngraphs;
+        stats->ms_setup = std::chrono::duration<double, std::milli>(t1 - t0).count() + ms_capture;
+        stats->ms_iterations = std::chrono::duration<double, std::milli>(t2 - t1).count() - ms_capture;
+        stats->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        stats->max_residual = maxres;
+        stats->ndet = N;
+        stats->nnz = g.nnz;
+        stats->sigma_team = scfg.team;
+        stats->sigma_unroll = scfg.unr;
+        stats->sigma_occupancy = scfg.occ;
+    }
+    return nconv == nb ? HINQS_OK : HINQS_E_NOT_CONVERGED;
+}
+
+}  // namespace
+
+void batch_clear(Ctx &c) { c.batch.reset(); }
+
+int batch_add(Ctx &c, int norb, const double *h, const double *eri, double ecore, int64_t ndet,
+              const uint64_t *alpha, const uint64_t *beta, int na, int nb) {
+    if (!c.batch) c.batch = std::make_shared<BatchState>();
+    BatchState &B = *c.batch;
+    if (B.row_off.back() + ndet >= ((int64_t)1 << 31) - 1)
+        throw Error(HINQS_E_UNSUPPORTED, "a batch holds fewer than 2^31 determinants");
+    auto p = std::make_unique<Ctx>();
+    p->device = c.device;
+    p->stream = c.stream;
+    build_integrals(*p, norb, h, eri, ecore);
+    build_determinants(*p, ndet, alpha, beta, na, nb, false);
+    build_connectivity(*p);
+    build_elements(*p);
+    HQ_CHECK(hipStreamSynchronize(c.stream));
+    // keep only what the merge needs
+    p->desc.release();
+    p->val32.release();
+    p->diag32.release();
+    p->d_eri32.release();
+    p->sa.release();
+    p->sb.release();
+    p->inv.release();
+    p->ua.release();
+    p->ub.release();
+    p->ga.release();
+    p->aidx.release();
+    p->bidx.release();
+    p->gb.release();
+    p->bperm.release();
+    p->bm_alpha.release();
+    p->alink_ptr.release();
+    p->alink.release();
+    p->alink_info.release();
+    p->work.release();
+    B.meta.push_back({norb, na, nb, p->ndet, p->nnz});
+    B.row_off.push_back(B.row_off.back() + p->ndet);
+    B.nz_off.push_back(B.nz_off.back() + p->nnz);
+    B.pending.push_back(std::move(p));
+    return (int)B.meta.size() - 1;
+}
+
+void batch_info(Ctx &c, int *ninst, int64_t *offsets, int64_t *nnz) {
+    const int nb = c.batch ? (int)c.batch->meta.size() : 0;
+    if (ninst) *ninst = nb;
+    if (offsets)
+        for (int b = 0; b <= nb; ++b) offsets[b] = c.batch ? c.batch->row_off[b] : 0;
+    if (nnz) *nnz = c.batch ? c.batch->nz_off[nb] : 0;
+}
+
+int batch_solve(Ctx &c, const hinqs_opts &o, double *energies, double *coeffs, int *status, int *iters_out,
+                hinqs_batch_stats *stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!c.batch || c.batch->meta.empty()) throw Error(HINQS_E_NOT_READY, "the batch holds no instance");
+    BatchState &B = *c.batch;
+    const int K = o.block;
+    if (K != 1 && K != 2 && K != 4 && K != 8 && K != 16)
+        throw Error(HINQS_E_UNSUPPORTED, "block size must be 1, 2, 4, 8 or 16");
+    int mmax = o.max_space > 0 ? o.max_space : 6 * K;
+    mmax = std::min(mmax, MS) / K * K;
+    if (mmax < 3 * K) throw Error(HINQS_E_UNSUPPORTED, "batched solves need 3 * block <= max_space <= 64");
+    const int nb = (int)B.meta.size();
+    for (int b = 0; b < nb; ++b)
+        if (B.meta[b].ndet < mmax)
+            throw Error(HINQS_E_UNSUPPORTED, "instance " + std::to_string(b) +
+                                                 " has fewer determinants than the subspace size; solve it alone");
+    batch_plan(c, B);
+    switch (K) {
+        case 1: return batch_solve_k<1>(c, B, o, mmax, energies, coeffs, status, iters_out, stats, t0);
+        case 2: return batch_solve_k<2>(c, B, o, mmax, energies, coeffs, status, iters_out, stats, t0);
+        case 4: return batch_solve_k<4>(c, B, o, mmax, energies, coeffs, status, iters_out, stats, t0);
+        case 8: return batch_solve_k<8>(c, B, o, mmax, energies, coeffs, status, iters_out, stats, t0);
+        default: return batch_solve_k<16>(c, B, o, mmax, energies, coeffs, status, iters_out, stats, t0);
+    }
+}
+
+}  // namespace hinqs

@@ -7,6 +7,8 @@
 
 #include <cstdint>
 #include <cstring>
+#include <memory>
+#include <utility>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -59,6 +61,10 @@ struct DBuf {
         n = count ? count : 1;
     }
     size_t bytes() const { return n * sizeof(T); }
+    void swap(DBuf &o) {
+        std::swap(p, o.p);
+        std::swap(n, o.n);
+    }
     operator T *() const { return p; }
 };
 
@@ -164,12 +170,37 @@ struct SigmaCfg {
     double ms = 0.0;  // measured time of one launch when chosen by the tuner
 };
 
+// Row mask of the sigma kernel for batched instances (rows of instance b are
+// inst_row[b] .. inst_row[b+1]); ranges holds 9 row bounds, one range per XCD.
+struct SigmaMask {
+    const int64_t *ranges = nullptr;
+    const int32_t *row_inst = nullptr;
+    const int64_t *inst_row = nullptr;
+    const int32_t *done = nullptr;
+};
+
+// Column-blocked tall matrix: element (i, j) at p[(j / kb) * bs + i * kb + j % kb].
+// A plain row-major array with leading dimension ld is {p, ld, 0} with j < ld.
+struct Mat {
+    double *p;
+    int kb;
+    int64_t bs;
+    __host__ __device__ double *at(int64_t i, int j) const {
+        return p + (int64_t)(j / kb) * bs + i * kb + (j % kb);
+    }
+    __host__ __device__ Mat cols(int c0) const {  // view from column c0 (c0 % kb == 0)
+        return Mat{p + (int64_t)(c0 / kb) * bs, kb, bs};
+    }
+};
+
 // ------------------------------------------------------------- context
 struct Timer {
     hipEvent_t a = nullptr, b = nullptr;
     Timer() { (void)hipEventCreate(&a); (void)hipEventCreate(&b); }
     ~Timer() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
 };
+
+struct BatchState;  // batched instances (batch.hip)
 
 struct Ctx {
     int device = 0;
@@ -225,6 +256,9 @@ struct Ctx {
     // workspace shared by calls
     DBuf<char> work;
 
+    // independent instances solved together (hinqs_batch_*)
+    std::shared_ptr<BatchState> batch;
+
     size_t device_bytes() const;
 };
 
@@ -253,6 +287,16 @@ void sigma_sorted(Ctx &c, int k, const void *X, int ldx, void *S, int lds, int p
 SigmaCfg autotune_sigma(Ctx &c, int k, int precision);
 // Shape the next sigma launch will use for (k, precision).
 SigmaCfg sigma_config(const Ctx &c, int k, int precision);
+// FP64 sigma over the rows that mk leaves live (X, S with leading dimension k).
+void sigma_masked_fp64(const Ctx &c, int k, const double *X, double *S, const SigmaMask &mk, hipStream_t s);
+
+// Batched instances (batch.hip)
+void batch_clear(Ctx &c);
+int batch_add(Ctx &c, int norb, const double *h, const double *eri, double ecore, int64_t ndet,
+              const uint64_t *alpha, const uint64_t *beta, int na, int nb);
+void batch_info(Ctx &c, int *ninst, int64_t *offsets, int64_t *nnz);
+int batch_solve(Ctx &c, const hinqs_opts &o, double *energies, double *coeffs, int *status, int *iters,
+                hinqs_batch_stats *st);
 
 // Davidson (davidson.hip)
 int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, double *coeffs,

@@ -39,20 +39,6 @@ namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// Column-blocked tall matrix: element (i, j) at p[(j / kb) * bs + i * kb + j % kb].
-// A plain row-major array with leading dimension ld is {p, ld, 0} with j < ld.
-struct Mat {
-    double *p;
-    int kb;
-    int64_t bs;
-    __host__ __device__ double *at(int64_t i, int j) const {
-        return p + (int64_t)(j / kb) * bs + i * kb + (j % kb);
-    }
-    __host__ __device__ Mat cols(int c0) const {  // view from column c0 (c0 % kb == 0)
-        return Mat{p + (int64_t)(c0 / kb) * bs, kb, bs};
-    }
-};
-
 constexpr int GRAM_BLOCK = 256;
 constexpr int GRAM_MAX_BLOCKS = 512;
 constexpr int GRAM_UNROLL = 4;

@@ -98,8 +98,11 @@ struct XcdRows {
     int64_t b[NUM_XCD + 1];
 };
 
-template <typename T, int K, int TEAM, int UNR>
-__global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges, int xcd_map,
+// MASK (batched instances): the XCD row ranges come from device memory and the
+// rows of finished instances are skipped; a team jumps over a finished
+// instance in one step, so the cost does not grow with its size.
+template <typename T, int K, int TEAM, int UNR, bool MASK>
+__global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges, SigmaMask mk, int xcd_map,
                                                        const int64_t *__restrict__ rowptr,
                                                        const int32_t *__restrict__ col,
                                                        const T *__restrict__ val,
@@ -118,16 +121,33 @@ __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges, int xcd_m
     const int64_t bix = xcd_map ? blockIdx.x / NUM_XCD : blockIdx.x % blocks_per_xcd;
     const int64_t team0 = bix * TPB + threadIdx.x / TEAM;
     const int64_t nteams = blocks_per_xcd * TPB;
-    const int64_t r0 = ranges.b[xcd];
-    const int64_t r1 = ranges.b[xcd + 1];
+    const int64_t r0 = MASK ? mk.ranges[xcd] : ranges.b[xcd];
+    const int64_t r1 = MASK ? mk.ranges[xcd + 1] : ranges.b[xcd + 1];
     const int sub = threadIdx.x % TEAM;
     const int q = sub % LPN, g = sub / LPN;
     const T *Xq = X + q * EPL;
-    int64_t row = r0 + team0;
+    // MASK: instance of the last row looked up (rows only increase)
+    int64_t inst_end = -1;
+    bool inst_done = false;
+    auto live_row = [&](int64_t rw) -> int64_t {
+        if constexpr (MASK) {
+            while (rw < r1) {
+                if (rw >= inst_end) {
+                    const int32_t b = mk.row_inst[rw];
+                    inst_end = mk.inst_row[b + 1];
+                    inst_done = mk.done[b] != 0;
+                }
+                if (!inst_done) break;
+                rw += (inst_end - rw + nteams - 1) / nteams * nteams;
+            }
+        }
+        return rw;
+    };
+    int64_t row = live_row(r0 + team0);
     if (row >= r1) return;  // uniform across the team
     int64_t beg = uniform_if<TEAM == 64>(rowptr[row]), end = uniform_if<TEAM == 64>(rowptr[row + 1]);
     for (;;) {
-        const int64_t nrow = row + nteams;
+        const int64_t nrow = live_row(row + nteams);
         // next row's bounds, in flight during this row (clamped, not predicated)
         const int64_t nrc = nrow < r1 ? nrow : row;
         const int64_t nbeg = rowptr[nrc], nend = rowptr[nrc + 1];
@@ -210,9 +230,9 @@ constexpr int lanes_per_coupling() {
     return (K >= Vec16<T>::n) ? K / Vec16<T>::n : 1;
 }
 
-template <typename T, int K, int TEAM, int UNR>
-void launch_sigma_u(const Ctx &c, const SigmaCfg &cfg, const T *val, const T *diag, const T *X, int ldx,
-                    T *S, int lds, hipStream_t s) {
+template <typename T, int K, int TEAM, int UNR, bool MASK>
+void launch_sigma_u(const Ctx &c, const SigmaCfg &cfg, const SigmaMask &mk, const T *val, const T *diag,
+                    const T *X, int ldx, T *S, int lds, hipStream_t s) {
     static int cus = 0;
     if (!cus) {
         cus = 256;
@@ -225,45 +245,47 @@ void launch_sigma_u(const Ctx &c, const SigmaCfg &cfg, const T *val, const T *di
     nblk = (nblk + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
     XcdRows ranges;
     for (int x = 0; x <= NUM_XCD; ++x) ranges.b[x] = c.xcd_rows[x];
-    hipLaunchKernelGGL((k_sigma<T, K, TEAM, UNR>), dim3((unsigned)nblk), dim3(SIGMA_BLOCK), 0, s,
-                       ranges, env_int("HINQS_SIGMA_XCDMAP", 1), c.rowptr.p, c.col.p, val, diag, X, ldx,
-                       S, lds);
+    hipLaunchKernelGGL((k_sigma<T, K, TEAM, UNR, MASK>), dim3((unsigned)nblk), dim3(SIGMA_BLOCK), 0, s,
+                       ranges, mk, env_int("HINQS_SIGMA_XCDMAP", 1), c.rowptr.p, c.col.p, val, diag, X,
+                       ldx, S, lds);
     HQ_LAUNCH_CHECK();
 }
 
-template <typename T, int K, int TEAM>
-void launch_sigma(const Ctx &c, const SigmaCfg &cfg, const T *val, const T *diag, const T *X, int ldx,
-                  T *S, int lds, hipStream_t s) {
-    if (cfg.unr <= 2) launch_sigma_u<T, K, TEAM, 2>(c, cfg, val, diag, X, ldx, S, lds, s);
-    else if (cfg.unr <= 4) launch_sigma_u<T, K, TEAM, 4>(c, cfg, val, diag, X, ldx, S, lds, s);
-    else launch_sigma_u<T, K, TEAM, 8>(c, cfg, val, diag, X, ldx, S, lds, s);
+template <typename T, int K, int TEAM, bool MASK>
+void launch_sigma(const Ctx &c, const SigmaCfg &cfg, const SigmaMask &mk, const T *val, const T *diag,
+                  const T *X, int ldx, T *S, int lds, hipStream_t s) {
+    if (cfg.unr <= 2) launch_sigma_u<T, K, TEAM, 2, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s);
+    else if (cfg.unr <= 4) launch_sigma_u<T, K, TEAM, 4, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s);
+    else launch_sigma_u<T, K, TEAM, 8, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s);
 }
 
-template <typename T, int K>
-void dispatch_team(const Ctx &c, const SigmaCfg &cfg, const T *val, const T *diag, const T *X, int ldx,
-                   T *S, int lds, hipStream_t s) {
+template <typename T, int K, bool MASK>
+void dispatch_team(const Ctx &c, const SigmaCfg &cfg, const SigmaMask &mk, const T *val, const T *diag,
+                   const T *X, int ldx, T *S, int lds, hipStream_t s) {
     constexpr int LPN = lanes_per_coupling<T, K>();
     const int team = std::max(cfg.team, LPN);
+#define HQ_TEAM(n) launch_sigma<T, K, n, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s)
     switch (team) {
-        case 1: if constexpr (LPN <= 1) { launch_sigma<T, K, 1>(c, cfg, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
-        case 2: if constexpr (LPN <= 2) { launch_sigma<T, K, 2>(c, cfg, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
-        case 4: if constexpr (LPN <= 4) { launch_sigma<T, K, 4>(c, cfg, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
-        case 8: if constexpr (LPN <= 8) { launch_sigma<T, K, 8>(c, cfg, val, diag, X, ldx, S, lds, s); break; } [[fallthrough]];
-        case 16: launch_sigma<T, K, 16>(c, cfg, val, diag, X, ldx, S, lds, s); break;
-        case 32: launch_sigma<T, K, 32>(c, cfg, val, diag, X, ldx, S, lds, s); break;
-        default: launch_sigma<T, K, 64>(c, cfg, val, diag, X, ldx, S, lds, s); break;
+        case 1: if constexpr (LPN <= 1) { HQ_TEAM(1); break; } [[fallthrough]];
+        case 2: if constexpr (LPN <= 2) { HQ_TEAM(2); break; } [[fallthrough]];
+        case 4: if constexpr (LPN <= 4) { HQ_TEAM(4); break; } [[fallthrough]];
+        case 8: if constexpr (LPN <= 8) { HQ_TEAM(8); break; } [[fallthrough]];
+        case 16: HQ_TEAM(16); break;
+        case 32: HQ_TEAM(32); break;
+        default: HQ_TEAM(64); break;
     }
+#undef HQ_TEAM
 }
 
-template <typename T>
+template <typename T, bool MASK = false>
 void dispatch_k(const Ctx &c, int k, const SigmaCfg &cfg, const T *val, const T *diag, const T *X, int ldx,
-                T *S, int lds, hipStream_t s) {
+                T *S, int lds, hipStream_t s, const SigmaMask &mk = SigmaMask{}) {
     switch (k) {
-        case 1: dispatch_team<T, 1>(c, cfg, val, diag, X, ldx, S, lds, s); break;
-        case 2: dispatch_team<T, 2>(c, cfg, val, diag, X, ldx, S, lds, s); break;
-        case 4: dispatch_team<T, 4>(c, cfg, val, diag, X, ldx, S, lds, s); break;
-        case 8: dispatch_team<T, 8>(c, cfg, val, diag, X, ldx, S, lds, s); break;
-        case 16: dispatch_team<T, 16>(c, cfg, val, diag, X, ldx, S, lds, s); break;
+        case 1: dispatch_team<T, 1, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s); break;
+        case 2: dispatch_team<T, 2, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s); break;
+        case 4: dispatch_team<T, 4, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s); break;
+        case 8: dispatch_team<T, 8, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s); break;
+        case 16: dispatch_team<T, 16, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s); break;
         default: throw Error(HINQS_E_UNSUPPORTED, "sigma block size must be 1, 2, 4, 8 or 16");
     }
 }
@@ -340,6 +362,12 @@ void sigma_sorted(Ctx &c, int k, const void *X, int ldx, void *S, int lds, int p
         dispatch_k<float>(c, k, cfg, c.val32.p, c.diag32.p, (const float *)X, ldx, (float *)S, lds, s);
     else
         throw Error(HINQS_E_INVALID_ARG, "precision must be HINQS_FP64 or HINQS_FP32");
+}
+
+void sigma_masked_fp64(const Ctx &c, int k, const double *X, double *S, const SigmaMask &mk, hipStream_t s) {
+    if (!c.have_elements) throw Error(HINQS_E_NOT_READY, "matrix elements are not built");
+    const SigmaCfg cfg = sigma_config(c, k, HINQS_FP64);
+    dispatch_k<double, true>(c, k, cfg, c.val.p, c.diag.p, X, k, S, k, s, mk);
 }
 
 SigmaCfg autotune_sigma(Ctx &c, int k, int precision) {
