@@ -8,10 +8,16 @@ uniform tail; synthetic integrals), starting from determinant strings already
 resident in HBM:
   set_integrals -> set_determinants (validate, sort, string tables, couplings,
   Slater-Condon elements) -> FP64 Davidson to 1e-8 -> mixed-precision
-  Davidson to 1e-8 -> 1-/2-RDM of the FP64 eigenvector.
+  Davidson to 1e-8 -> 1-/2-RDM of the FP64 eigenvector,
+followed by the batched solve of a bond-scan-like family of 64 uneven
+instances (norb 8..16, N = norb -+ 2, 1e3..3e5 determinants each, 3.45e6 in
+all; host inputs): build every instance, then one batched FP64 Davidson to
+1e-8 (one graph launch per iteration).  The same 64 instances solved one at a
+time are timed once outside the timed region for comparison.
 
 value = H.X elements applied by the sigma products of the step
-        ((nnz + ndet) * columns, summed over every block product) / step time.
+        ((nnz + ndet) * columns, summed over every block product of both
+        parts) / step time.
 The roofline object covers the FP64 sigma kernel: algorithmic bytes per launch
 (12 nnz + 16 k ndet + 16 ndet + 8) over its average launch time, taken from
 HIP events recorded around each launch on the library's stream.
@@ -75,6 +81,33 @@ def sigma_counter_run(hq, ints, alpha, beta, cfg, reps):
     print(json.dumps({"mode": "sigma", "ndet": len(alpha), "nnz": s.info()["nnz"], "launches": reps}))
 
 
+def batch_inputs(n=64):
+    import workloads as W
+    return [W.batch_instance(i) for i in range(n)]
+
+
+def sequential_batch(hq, insts, block, tol):
+    """The batch's instances solved one at a time with the plain FP64 solver."""
+    import torch
+    t_build = t_solve = 0.0
+    energies = []
+    for ints, a, b, spec in insts:
+        s = hq.Hinqs(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_integrals(ints.h, ints.eri, ints.e_core)
+        s.set_determinants(a, b, spec["na"], spec["nb"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e, _, _ = s.lowest_eigenpair(block=block, tol=tol)
+        torch.cuda.synchronize()
+        t_build += t1 - t0
+        t_solve += time.perf_counter() - t1
+        energies.append(e)
+        s.close()
+    return t_build, t_solve, energies
+
+
 def recorded_traffic():
     """HBM bytes per FP64 sigma launch from the committed counter summary, or None
     when the sigma kernel source has changed since the counters were taken."""
@@ -98,7 +131,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--ndet", type=int, default=None, help="override the determinant count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-batch", action="store_true", help="leave the batched instances out of the step")
+    ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--mode", choices=["step", "sigma"], default="step",
                     help="sigma: only repeated FP64 sigma launches plus a copy kernel of known "
                          "size (for hardware-counter runs)")
@@ -124,6 +158,8 @@ def main():
     b_d = torch.from_numpy(beta.view(np.int64).copy()).to(dev)
     solver = hq.Hinqs(0)
     stream = torch.cuda.current_stream(dev)
+    insts = None if args.no_batch else batch_inputs()
+    bsolver = None if args.no_batch else hq.Hinqs(0)
 
     def step():
         t = {}
@@ -131,15 +167,27 @@ def main():
         solver.set_integrals(ints.h, ints.eri, ints.e_core)
         solver.set_determinants(a_d, b_d, cfg.na, cfg.nb)
         t1 = time.perf_counter()
-        e64, c64, st64 = solver.lowest_eigenpair(tol=cfg.tol, block=cfg.k)
+        e64, c64, st64 = solver.lowest_eigenpair(tol=cfg.tol, block=cfg.k, autotune=True)
         t2 = time.perf_counter()
-        em, cm, stm = solver.lowest_eigenpair(tol=cfg.tol, block=cfg.k, mixed=True)
+        em, cm, stm = solver.lowest_eigenpair(tol=cfg.tol, block=cfg.k, mixed=True, autotune=True)
         t3 = time.perf_counter()
         d1, d2 = solver.rdm12(c64)
         stream.synchronize()
         t4 = time.perf_counter()
         t.update(build=t1 - t0, fp64=t2 - t1, mixed=t3 - t2, rdm=t4 - t3)
-        return t, (e64, st64), (em, stm)
+        bres = None
+        if insts is not None:
+            bsolver.batch_clear()
+            for bi, ba, bb, spec in insts:
+                bsolver.batch_add(bi.h, bi.eri, bi.e_core, ba, bb, spec["na"], spec["nb"])
+            stream.synchronize()
+            t5 = time.perf_counter()
+            be, _, binfo = bsolver.batch_lowest_eigenpair(tol=cfg.tol, block=cfg.k, autotune=True)
+            stream.synchronize()
+            t6 = time.perf_counter()
+            t.update(batch_build=t5 - t4, batch_solve=t6 - t5)
+            bres = (be, binfo)
+        return t, (e64, st64), (em, stm), bres
 
     for _ in range(args.warmup):
         step()
@@ -153,6 +201,8 @@ def main():
     nnz = info["nnz"]
     cols = sum(r[1][1]["sigma_columns"] + r[2][1]["sigma_columns"] for r in res)
     elements = (nnz + D) * cols
+    if insts is not None:
+        elements += sum(r[3][1]["stats"]["sigma_elements"] for r in res)
     value = elements / elapsed
     # FP64 sigma launches of the FP64 solves: one kernel per event pair
     ms_sig = sum(r[1][1]["ms_sigma"] for r in res)
@@ -177,8 +227,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"cas16_{D}: norb=16, 7a+7b electrons, {D} determinants sampled "
                                "with weight 0.35^rank + 5% uniform tail, random integrals "
-                               "(h_pp in [-15,1], 16 eri factors), Davidson block k=8, tol 1e-8",
-                   "ndet": D, "nnz": nnz, "block": k, "tol": cfg.tol},
+                               "(h_pp in [-15,1], 16 eri factors), Davidson block k=8, tol 1e-8"
+                               + ("" if insts is None else
+                                  "; then a 64-instance bond-scan batch (norb 8-16, 3.45e6 determinants)"),
+                   "ndet": D, "nnz": nnz, "block": k, "tol": cfg.tol,
+                   "batch_instances": 0 if insts is None else len(insts)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(),
                      "kernel": "k_sigma (FP64 block sigma, k=8)",
@@ -195,6 +248,23 @@ def main():
         "build_breakdown_ms": {"sort_tables": info["ms_sort"], "couplings": info["ms_connect"],
                                "elements": info["ms_elements"]},
     }
+    if insts is not None:
+        be, binfo = res[-1][3]
+        bst = binfo["stats"]
+        sb, ss, se = sequential_batch(hq, insts, cfg.k, cfg.tol)
+        ms_solve = med([r[0]["batch_solve"] for r in res]) * 1e3
+        out["batch"] = {
+            "workload": f"bond-scan batch: 64 instances, norb 8-16, N = norb -+ 2, 1e3-3e5 determinants "
+                        f"({bst['ndet']} in all), FP64 Davidson k={cfg.k} to {cfg.tol}",
+            "instances": bst["instances"], "ndet": bst["ndet"], "nnz": bst["nnz"],
+            "ms_build": med([r[0]["batch_build"] for r in res]) * 1e3, "ms_solve": ms_solve,
+            "iterations": bst["iterations"], "graphs": bst["graphs"],
+            "ms_per_iteration": bst["ms_iterations"] / max(1, bst["iterations"]),
+            "sigma_shape": [bst["sigma_team"], bst["sigma_unroll"], bst["sigma_occupancy"]],
+            "sequential_ms_build": sb * 1e3, "sequential_ms_solve": ss * 1e3,
+            "solve_speedup_vs_sequential": ss * 1e3 / ms_solve,
+            "max_abs_dE_vs_sequential": float(np.max(np.abs(np.asarray(se) - be))),
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ints, alpha, beta, cfg, args.cpu_seconds)
     print(json.dumps(out), flush=True)

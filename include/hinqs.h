@@ -120,6 +120,7 @@ typedef struct hinqs_batch_stats {
     int64_t ndet;              /* determinants over all instances */
     int64_t nnz;               /* stored couplings over all instances */
     int     sigma_team, sigma_unroll, sigma_occupancy;  /* sigma launch shape used */
+    double  sigma_elements;    /* H x products applied: sum over instances of (nnz + ndet) * block per sigma */
 } hinqs_batch_stats;
 
 /* Fill *opts with the defaults listed above. */

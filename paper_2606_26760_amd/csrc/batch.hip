@@ -1141,6 +1141,13 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     HQ_CHECK(hipStreamWaitEvent(c.stream, R.ev, 0));
     int nconv = 0;
     double maxres = 0.0;
+    double elements = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        // sigma products that carried instance b: the initial block plus one per
+        // iteration that did not end it
+        const int nsig = it_h[b] + ((done_h[b] == 1 || done_h[b] == 2) ? 0 : 1);
+        elements += (double)(B.meta[b].nnz + B.meta[b].ndet) * KK * nsig;
+    }
     for (int b = 0; b < nb; ++b) {
         energies[b] = e_h[b];
         const bool ok = done_h[b] == 1;
@@ -1163,6 +1170,7 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
         stats->sigma_team = scfg.team;
         stats->sigma_unroll = scfg.unr;
         stats->sigma_occupancy = scfg.occ;
+        stats->sigma_elements = elements;
     }
     return nconv == nb ? HINQS_OK : HINQS_E_NOT_CONVERGED;
 }
@@ -1184,27 +1192,7 @@ int batch_add(Ctx &c, int norb, const double *h, const double *eri, double ecore
     build_determinants(*p, ndet, alpha, beta, na, nb, false);
     build_connectivity(*p);
     build_elements(*p);
-    HQ_CHECK(hipStreamSynchronize(c.stream));
-    // keep only what the merge needs
-    p->desc.release();
-    p->val32.release();
-    p->diag32.release();
-    p->d_eri32.release();
-    p->sa.release();
-    p->sb.release();
-    p->inv.release();
-    p->ua.release();
-    p->ub.release();
-    p->ga.release();
-    p->aidx.release();
-    p->bidx.release();
-    p->gb.release();
-    p->bperm.release();
-    p->bm_alpha.release();
-    p->alink_ptr.release();
-    p->alink.release();
-    p->alink_info.release();
-    p->work.release();
+    // the instance's buffers are kept until the merge (one release per instance then)
     B.meta.push_back({norb, na, nb, p->ndet, p->nnz});
     B.row_off.push_back(B.row_off.back() + p->ndet);
     B.nz_off.push_back(B.nz_off.back() + p->nnz);
