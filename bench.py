@@ -69,6 +69,7 @@ def sigma_counter_run(hq, ints, alpha, beta, cfg, reps):
     s = hq.Hinqs(0)
     s.set_integrals(ints.h, ints.eri, ints.e_core)
     s.set_determinants(alpha, beta, cfg.na, cfg.nb)
+    shape, _ = s.autotune(cfg.k, hq.HINQS_FP64)  # the launch shape the step's FP64 solves use
     X = torch.randn(len(alpha), cfg.k, dtype=torch.float64, device="cuda")
     S = torch.empty_like(X)
     for _ in range(max(1, reps)):
@@ -78,7 +79,8 @@ def sigma_counter_run(hq, ints, alpha, beta, cfg, reps):
     for _ in range(3):
         torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
-    print(json.dumps({"mode": "sigma", "ndet": len(alpha), "nnz": s.info()["nnz"], "launches": reps}))
+    print(json.dumps({"mode": "sigma", "ndet": len(alpha), "nnz": s.info()["nnz"], "launches": reps,
+                      "shape": shape}))
 
 
 def batch_inputs(n=64):

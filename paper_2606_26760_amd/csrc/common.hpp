@@ -167,6 +167,7 @@ inline int neri_packed(int norb) { int m = npair(norb); return m * (m + 1) / 2; 
 // lane, resident workgroups per CU.
 struct SigmaCfg {
     int team = 0, unr = 0, occ = 0;
+    int pipe = 0;     // 0: one step of gathers in flight per team; 1: cross-row four-stage pipeline
     double ms = 0.0;  // measured time of one launch when chosen by the tuner
 };
 

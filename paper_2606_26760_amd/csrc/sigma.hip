@@ -16,6 +16,7 @@
 // the same X rows, and keeping them on one XCD keeps those X rows in its L2.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <fstream>
 #include <map>
@@ -218,6 +219,167 @@ __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges, SigmaMask
     }
 }
 
+// Cross-row pipelined variant.  A team walks its rows as one stream of steps
+// (UNR * TEAM / LPN couplings of one row per step; an empty row is one step
+// with none), and four register sets rotate through the stages of a step:
+//   stage t:  fetch (col, val) of step t+2;  gather the X rows of step t+1;
+//             accumulate step t-1 (and finish its row if it is the row's last)
+// so two steps of X gathers are in flight while a third is accumulated, with
+// no bubble at row boundaries.  Every step also fetches its row's diagonal
+// element and X row (used by the row's last step), so each stage issues the
+// same loads in the same order and the hardware's in-order load counter never
+// forces a wait on younger gathers.
+template <typename T, int K, int TEAM, int UNR, bool MASK>
+__global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma_xr(XcdRows ranges, SigmaMask mk, int xcd_map,
+                                                          const int64_t *__restrict__ rowptr,
+                                                          const int32_t *__restrict__ col,
+                                                          const T *__restrict__ val,
+                                                          const T *__restrict__ diag,
+                                                          const T *__restrict__ X, int ldx,
+                                                          T *__restrict__ S, int lds) {
+    constexpr int VW = Vec16<T>::n;
+    constexpr int LPN = (K >= VW) ? K / VW : 1;   // lanes per coupling
+    constexpr int EPL = K / LPN;                   // entries of X per lane
+    constexpr int NPT = TEAM / LPN;                // couplings per team per unrolled slot
+    constexpr int STEP = UNR * NPT;                // couplings per team step
+    constexpr int TPB = SIGMA_BLOCK / TEAM;        // teams per block
+    constexpr bool UNI = TEAM == 64;
+    static_assert(TEAM % LPN == 0 && TEAM <= 64, "team shape");
+    const int64_t blocks_per_xcd = gridDim.x / NUM_XCD;
+    const int xcd = xcd_map ? blockIdx.x % NUM_XCD : blockIdx.x / blocks_per_xcd;
+    const int64_t bix = xcd_map ? blockIdx.x / NUM_XCD : blockIdx.x % blocks_per_xcd;
+    const int64_t team0 = bix * TPB + threadIdx.x / TEAM;
+    const int64_t nteams = blocks_per_xcd * TPB;
+    const int64_t r0 = MASK ? mk.ranges[xcd] : ranges.b[xcd];
+    const int64_t r1 = MASK ? mk.ranges[xcd + 1] : ranges.b[xcd + 1];
+    const int sub = threadIdx.x % TEAM;
+    const int q = sub % LPN, g = sub / LPN;
+    const T *Xq = X + q * EPL;
+    int64_t inst_end = -1;
+    bool inst_done = false;
+    auto live_row = [&](int64_t rw) -> int64_t {
+        if constexpr (MASK) {
+            while (rw < r1) {
+                if (rw >= inst_end) {
+                    const int32_t b = mk.row_inst[rw];
+                    inst_end = mk.inst_row[b + 1];
+                    inst_done = mk.done[b] != 0;
+                }
+                if (!inst_done) break;
+                rw += (inst_end - rw + nteams - 1) / nteams * nteams;
+            }
+        }
+        return rw;
+    };
+    // step generator (the same on every lane of a team)
+    int64_t g_row = live_row(r0 + team0);
+    if (g_row >= r1) return;
+    const int64_t safe_row = g_row;  // an in-range row for clamped loads
+    int64_t g_eb = uniform_if<UNI>(rowptr[g_row]), g_end = uniform_if<UNI>(rowptr[g_row + 1]);
+    int64_t n_row = live_row(g_row + nteams);
+    int64_t n_beg, n_end;
+    {
+        const int64_t c = n_row < r1 ? n_row : safe_row;
+        n_beg = rowptr[c];
+        n_end = rowptr[c + 1];
+    }
+    struct Slot {
+        int32_t j[UNR];
+        T v[UNR];
+        bool ok[UNR];
+        T x[UNR][EPL];
+        T dx[EPL];
+        T dd;
+        int64_t row;
+        bool last, valid;
+    };
+    Slot s0, s1, s2, s3;
+    auto emit = [&](Slot &sl) {
+        sl.valid = g_row < r1;
+        sl.row = sl.valid ? g_row : safe_row;
+        sl.last = g_eb + STEP >= g_end;
+        const int64_t lastidx = g_end > 0 ? g_end - 1 : 0;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int64_t idx = g_eb + g + u * NPT;
+            sl.ok[u] = sl.valid && idx < g_end;
+            const int64_t idc = sl.ok[u] ? idx : lastidx;
+            sl.j[u] = __builtin_nontemporal_load(col + idc);
+            sl.v[u] = __builtin_nontemporal_load(val + idc);
+        }
+        if (sl.valid) {
+            g_eb += STEP;
+            if (g_eb >= g_end) {
+                g_row = n_row;
+                g_eb = uniform_if<UNI>(n_beg);
+                g_end = uniform_if<UNI>(n_end);
+                n_row = live_row(g_row + nteams);
+                const int64_t c = n_row < r1 ? n_row : safe_row;
+                n_beg = rowptr[c];
+                n_end = rowptr[c + 1];
+            }
+        }
+    };
+    auto gather = [&](Slot &sl) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int32_t jr = sl.ok[u] ? sl.j[u] : (int32_t)safe_row;
+            load_vec<T, EPL>(Xq + (int64_t)jr * ldx, sl.x[u]);
+        }
+        sl.dd = diag[sl.row];
+        load_vec<T, EPL>(Xq + sl.row * ldx, sl.dx);
+    };
+    T acc[EPL];
+#pragma unroll
+    for (int c = 0; c < EPL; ++c) acc[c] = T(0);
+    auto accumulate = [&](Slot &sl) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const T w = sl.ok[u] ? sl.v[u] : T(0);
+#pragma unroll
+            for (int c = 0; c < EPL; ++c) acc[c] += w * sl.x[u][c];
+        }
+        if (sl.last) {
+#pragma unroll
+            for (int off = LPN; off < TEAM; off <<= 1) {
+#pragma unroll
+                for (int c = 0; c < EPL; ++c) acc[c] += __shfl_xor(acc[c], off, TEAM);
+            }
+            if (g == 0) {
+                T o[EPL];
+#pragma unroll
+                for (int c = 0; c < EPL; ++c) o[c] = acc[c] + sl.dd * sl.dx[c];
+                store_vec<T, EPL>(S + sl.row * lds + q * EPL, o);
+            }
+#pragma unroll
+            for (int c = 0; c < EPL; ++c) acc[c] = T(0);
+        }
+    };
+    emit(s0);
+    emit(s1);
+    gather(s0);
+    emit(s2);
+    gather(s1);
+    for (;;) {
+        emit(s3);
+        gather(s2);
+        accumulate(s0);
+        if (!s1.valid) break;
+        emit(s0);
+        gather(s3);
+        accumulate(s1);
+        if (!s2.valid) break;
+        emit(s1);
+        gather(s0);
+        accumulate(s2);
+        if (!s3.valid) break;
+        emit(s2);
+        gather(s1);
+        accumulate(s3);
+        if (!s0.valid) break;
+    }
+}
+
 int env_int(const char *name, int dflt) {
     const char *v = std::getenv(name);
     return (v && *v) ? std::atoi(v) : dflt;
@@ -245,9 +407,13 @@ void launch_sigma_u(const Ctx &c, const SigmaCfg &cfg, const SigmaMask &mk, cons
     nblk = (nblk + NUM_XCD - 1) / NUM_XCD * NUM_XCD;
     XcdRows ranges;
     for (int x = 0; x <= NUM_XCD; ++x) ranges.b[x] = c.xcd_rows[x];
-    hipLaunchKernelGGL((k_sigma<T, K, TEAM, UNR, MASK>), dim3((unsigned)nblk), dim3(SIGMA_BLOCK), 0, s,
-                       ranges, mk, env_int("HINQS_SIGMA_XCDMAP", 1), c.rowptr.p, c.col.p, val, diag, X,
-                       ldx, S, lds);
+    const int xmap = env_int("HINQS_SIGMA_XCDMAP", 1);
+    if (cfg.pipe)
+        hipLaunchKernelGGL((k_sigma_xr<T, K, TEAM, UNR, MASK>), dim3((unsigned)nblk), dim3(SIGMA_BLOCK), 0, s,
+                           ranges, mk, xmap, c.rowptr.p, c.col.p, val, diag, X, ldx, S, lds);
+    else
+        hipLaunchKernelGGL((k_sigma<T, K, TEAM, UNR, MASK>), dim3((unsigned)nblk), dim3(SIGMA_BLOCK), 0, s,
+                           ranges, mk, xmap, c.rowptr.p, c.col.p, val, diag, X, ldx, S, lds);
     HQ_LAUNCH_CHECK();
 }
 
@@ -326,7 +492,7 @@ void load_tune_file() {
     std::ifstream f(path);
     std::string key;
     SigmaCfg g;
-    while (f >> key >> g.team >> g.unr >> g.occ >> g.ms) g_tune_cache[key] = g;
+    while (f >> key >> g.team >> g.unr >> g.occ >> g.pipe >> g.ms) g_tune_cache[key] = g;
 }
 
 void store_tune_file() {
@@ -335,7 +501,7 @@ void store_tune_file() {
     std::ofstream f(path, std::ios::trunc);
     for (const auto &kv : g_tune_cache)
         f << kv.first << " " << kv.second.team << " " << kv.second.unr << " " << kv.second.occ << " "
-          << kv.second.ms << "\n";
+          << kv.second.pipe << " " << kv.second.ms << "\n";
 }
 
 }  // namespace
@@ -347,6 +513,7 @@ SigmaCfg sigma_config(const Ctx &c, int k, int precision) {
     g.team = env_int("HINQS_SIGMA_TEAM", g.team);
     g.unr = env_int("HINQS_SIGMA_UNR", g.unr);
     g.occ = env_int("HINQS_SIGMA_OCC", g.occ);
+    g.pipe = env_int("HINQS_SIGMA_PIPE", g.pipe);
     return g;
 }
 
@@ -397,11 +564,13 @@ SigmaCfg autotune_sigma(Ctx &c, int k, int precision) {
     HQ_CHECK(hipEventCreate(&e1));
     const int vw = precision == HINQS_FP64 ? 2 : 4;
     const int lpn = K >= vw ? K / vw : 1;
+    const bool verbose = env_int("HINQS_VERBOSE", 0) != 0;
     SigmaCfg best;
     best.ms = 1e30;
     const int teams[] = {16, 32, 64};
     const int unrs[] = {2, 4};
     const int occs[] = {2, 4, 8};
+    for (int pipe = 0; pipe < 2; ++pipe)
     for (int team : teams) {
         if (team < 4 * lpn) continue;
         for (int unr : unrs)
@@ -410,6 +579,7 @@ SigmaCfg autotune_sigma(Ctx &c, int k, int precision) {
                 g.team = team;
                 g.unr = unr;
                 g.occ = occ;
+                g.pipe = pipe;
                 auto run = [&]() {
                     if (precision == HINQS_FP64)
                         dispatch_k<double>(c, K, g, c.val.p, c.diag.p, (const double *)X.p, K, (double *)S.p, K, s);
@@ -424,6 +594,9 @@ SigmaCfg autotune_sigma(Ctx &c, int k, int precision) {
                 float ms = 0.f;
                 HQ_CHECK(hipEventElapsedTime(&ms, e0, e1));
                 g.ms = ms / 3.0;
+                if (verbose)
+                    std::fprintf(stderr, "[hinqs] tune k=%d p=%d pipe %d team %d unr %d occ %d: %.4f ms\n", K,
+                                 precision, pipe, team, unr, occ, g.ms);
                 if (g.ms < best.ms) best = g;
             }
     }

@@ -308,14 +308,17 @@ def test_error_paths():
     assert ei.value.name == "UNSUPPORTED"
 
 
-@pytest.mark.parametrize("team,unr,occ", [(16, 2, 2), (32, 4, 8), (64, 2, 4), (64, 4, 2), (8, 2, 4)])
-def test_sigma_every_launch_shape(team, unr, occ, monkeypatch):
+@pytest.mark.parametrize("team,unr,occ,pipe", [(16, 2, 2, 0), (32, 4, 8, 0), (64, 2, 4, 0), (64, 4, 2, 0),
+                                                (8, 2, 4, 0), (64, 2, 4, 1), (32, 4, 2, 1), (16, 2, 8, 1),
+                                                (8, 4, 4, 1)])
+def test_sigma_every_launch_shape(team, unr, occ, pipe, monkeypatch):
     """Every launch shape the tuner may pick gives the same products (to the bar)."""
     ints, a, b, cfg = W.config_inputs(1, ndet=5000)
-    log(f"sigma launch shape team={team} unr={unr} occ={occ}")
+    log(f"sigma launch shape team={team} unr={unr} occ={occ} pipe={pipe}")
     monkeypatch.setenv("HINQS_SIGMA_TEAM", str(team))
     monkeypatch.setenv("HINQS_SIGMA_UNR", str(unr))
     monkeypatch.setenv("HINQS_SIGMA_OCC", str(occ))
+    monkeypatch.setenv("HINQS_SIGMA_PIPE", str(pipe))
     s = solver_for(ints, a, b, cfg.na, cfg.nb)
     o = oracle_for(ints, a, b, cfg.na, cfg.nb)
     for k in (1, 8, 16):
