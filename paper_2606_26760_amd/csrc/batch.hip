@@ -71,6 +71,7 @@ struct BDev {
     int nb;
     const int32_t *inst_chunk;  // chunks of instance b: inst_chunk[b] .. inst_chunk[b+1]
     int32_t *done;              // 0 running, 1 converged, 2 no new direction
+    int32_t *skip1;             // done, or the second orthonormalization round is not needed
     int32_t *iters, *mfin, *valid;  // valid: [b][MS] basis columns in use
     double *G;                  // [b][MS][MS] V^T H V
     double *Y;                  // [b][MS][KB] Ritz coefficients of the current basis
@@ -524,6 +525,7 @@ __global__ __launch_bounds__(NT) void k_bpost_first(BDev st, int m, double tol, 
     if (tid == 0) {
         st.iters[b] += 1;
         st.resid[b] = r0;
+        st.skip1[b] = r0 <= tol ? 1 : 0;
         if (r0 <= tol) {
             st.done[b] = 1;
             st.energy[b] = st.theta[b * KB];
@@ -542,9 +544,10 @@ __global__ __launch_bounds__(NT) void k_bpost_first(BDev st, int m, double tol, 
 
 // C = V^T T from the chunk partials.
 template <int KK>
-__global__ __launch_bounds__(NT) void k_bpost_proj(BDev st, int m, const double *__restrict__ gpart) {
+__global__ __launch_bounds__(NT) void k_bpost_proj(BDev st, const int32_t *__restrict__ gate, int m,
+                                                   const double *__restrict__ gpart) {
     const int b = blockIdx.x;
-    if (st.done[b]) return;
+    if (gate[b]) return;
     const int c0 = st.inst_chunk[b], c1 = st.inst_chunk[b + 1];
     double *Cb = st.C + (int64_t)b * MS * KB;
     for (int e = threadIdx.x; e < m * KK; e += NT) Cb[(e / KK) * KB + e % KK] = chunk_sum(gpart, PSTRIDE, c0, c1, e);
@@ -554,13 +557,15 @@ __global__ __launch_bounds__(NT) void k_bpost_proj(BDev st, int m, const double 
 // S = diag(scl) in the first round (unit columns, dropped roots zero) and
 // S = I in the second, S g S = Z diag(w) Z^T and T <- T S Z_k w_k^(-1/2) over
 // the eigenvalues w_k > thresh, largest first.  No kept direction: the
-// instance stops (its current Ritz pair is the result).  The second round
-// marks the new basis columns valid.
+// instance stops (its current Ritz pair is the result).  The new basis
+// columns are marked valid; the first round skips the second when every
+// kept eigenvalue is >= 1e-2 (the transform amplified what was left of
+// span(V) at most tenfold).
 template <int KK>
-__global__ __launch_bounds__(NT) void k_bpost_orth(BDev st, int m, int round, double thresh,
-                                                   const double *__restrict__ gpart) {
+__global__ __launch_bounds__(NT) void k_bpost_orth(BDev st, const int32_t *__restrict__ gate, int m, int round,
+                                                   double thresh, const double *__restrict__ gpart) {
     const int b = blockIdx.x;
-    if (st.done[b]) return;
+    if (gate[b]) return;
     constexpr int LD = KK + 1;
     __shared__ double A[KK * LD], ZT[KK * LD], sc[KK], red[NT / 64];
     __shared__ double pc[KK], ps[KK];
@@ -602,12 +607,22 @@ __global__ __launch_bounds__(NT) void k_bpost_orth(BDev st, int m, int round, do
         }
     }
     const int nk = nk_s;
-    if (tid == 0 && nk == 0) {
-        st.done[b] = 2;
-        st.energy[b] = st.theta[b * KB];
-        st.mfin[b] = m;
+    if (tid == 0) {
+        if (nk == 0) {
+            st.done[b] = 2;
+            st.energy[b] = st.theta[b * KB];
+            st.mfin[b] = m;
+        }
+        if (round == 0) {
+            double wmin = INFINITY;
+            for (int j = 0; j < KK; ++j) {
+                const double w = A[j * LD + j];
+                if (isfinite(w) && w > thresh) wmin = fmin(wmin, w);
+            }
+            st.skip1[b] = (nk == 0 || wmin >= 1e-2) ? 1 : 0;
+        }
     }
-    if (round == 1 && tid < KK) st.valid[b * MS + m + tid] = tid < nk ? 1 : 0;
+    if (tid < KK) st.valid[b * MS + m + tid] = tid < nk ? 1 : 0;
 }
 
 // Coupling-balanced XCD row ranges over the instances still running: range x
@@ -951,7 +966,7 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     rpart.ensure((size_t)nch * RSTRIDE);
     const size_t n_state = (size_t)nb * (MS * MS + MS * KB + KB + MS * 2 * KB + MS * KB + KB * KB + KB + 2);
     state.ensure(n_state);
-    istate.ensure((size_t)nb * (3 + MS));
+    istate.ensure((size_t)nb * (4 + MS));
     d_ndone.ensure(1);
     ranges.ensure(9);
     d_chunks.ensure(nch);
@@ -965,14 +980,15 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     HQ_CHECK(hipMemsetAsync(Vb.p, 0, sizeof(double) * bsz * nblocks, s));
     HQ_CHECK(hipMemsetAsync(Wb.p, 0, sizeof(double) * bsz * nblocks, s));
     HQ_CHECK(hipMemsetAsync(state.p, 0, sizeof(double) * n_state, s));
-    HQ_CHECK(hipMemsetAsync(istate.p, 0, sizeof(int32_t) * nb * (3 + MS), s));
+    HQ_CHECK(hipMemsetAsync(istate.p, 0, sizeof(int32_t) * nb * (4 + MS), s));
     BDev st{};
     st.nb = nb;
     st.inst_chunk = d_inst_chunk.p;
     st.done = istate.p;
     st.iters = st.done + nb;
     st.mfin = st.iters + nb;
-    st.valid = st.mfin + nb;  // nb * MS
+    st.skip1 = st.mfin + nb;
+    st.valid = st.skip1 + nb;  // nb * MS
     {
         double *p = state.p;
         st.G = p;      p += (size_t)nb * MS * MS;
@@ -999,21 +1015,21 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     const Chunk *dch = d_chunks.p;
     const dim3 gch(nch), gin(nb), b256(256);
 
-    auto gram = [&](Mat A, int ma, Mat Bm, double *part) {
+    auto gram = [&](Mat A, int ma, Mat Bm, double *part, const int32_t *gate) {
         const int mt = (ma + 15) / 16;
         switch (mt) {
-            case 1: hipLaunchKernelGGL(k_bgram<1>, gch, b256, 0, s, dch, st.done, A, ma, Bm, KK, part); break;
-            case 2: hipLaunchKernelGGL(k_bgram<2>, gch, b256, 0, s, dch, st.done, A, ma, Bm, KK, part); break;
-            case 3: hipLaunchKernelGGL(k_bgram<3>, gch, b256, 0, s, dch, st.done, A, ma, Bm, KK, part); break;
-            default: hipLaunchKernelGGL(k_bgram<4>, gch, b256, 0, s, dch, st.done, A, ma, Bm, KK, part); break;
+            case 1: hipLaunchKernelGGL(k_bgram<1>, gch, b256, 0, s, dch, gate, A, ma, Bm, KK, part); break;
+            case 2: hipLaunchKernelGGL(k_bgram<2>, gch, b256, 0, s, dch, gate, A, ma, Bm, KK, part); break;
+            case 3: hipLaunchKernelGGL(k_bgram<3>, gch, b256, 0, s, dch, gate, A, ma, Bm, KK, part); break;
+            default: hipLaunchKernelGGL(k_bgram<4>, gch, b256, 0, s, dch, gate, A, ma, Bm, KK, part); break;
         }
         HQ_LAUNCH_CHECK();
     };
     // Out = beta Out + alpha A[:, 0:m] B_inst (nc columns)
     auto tsmm = [&](Mat A, int m, const double *Bs, int bstride, int ldb, auto ncc, double alpha, double beta,
-                    Mat Out) {
+                    Mat Out, const int32_t *gate) {
         constexpr int NC = decltype(ncc)::value;
-        hipLaunchKernelGGL(k_btsmm<NC>, gch, b256, 0, s, dch, st.done, m, A, Bs, bstride, ldb, NC, alpha, beta,
+        hipLaunchKernelGGL(k_btsmm<NC>, gch, b256, 0, s, dch, gate, m, A, Bs, bstride, ldb, NC, alpha, beta,
                            Out);
         HQ_LAUNCH_CHECK();
     };
@@ -1030,7 +1046,8 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     hipLaunchKernelGGL(k_binit, gin, b256, 0, s, KK, B.inst_row.p, g.diag.p, Vb.p);
     HQ_LAUNCH_CHECK();
     sigma(V.p, W.p);
-    gram(V, KK, W, gpart_u.p);
+    const int32_t *dn = st.done, *g1 = st.skip1;
+    gram(V, KK, W, gpart_u.p, dn);
 
     // ---- one iteration at subspace size m (m - KK columns old, KK new);
     // returns the subspace size after the optional restart
@@ -1041,42 +1058,43 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
         hipLaunchKernelGGL(k_brr<KK>, gin, dim3(NT), RR_LDS_BYTES, s, st, m, restart, (const double *)gpart_u.p);
         HQ_LAUNCH_CHECK();
         if (restart) {
-            tsmm(V, m, st.Q, MS * 2 * KB, 2 * KK, N2K{}, 1.0, 0.0, V);
-            tsmm(W, m, st.Q, MS * 2 * KB, 2 * KK, N2K{}, 1.0, 0.0, W);
+            tsmm(V, m, st.Q, MS * 2 * KB, 2 * KK, N2K{}, 1.0, 0.0, V, dn);
+            tsmm(W, m, st.Q, MS * 2 * KB, 2 * KK, N2K{}, 1.0, 0.0, W, dn);
         }
         const Mat T = V.cols(mp);
         hipLaunchKernelGGL(k_britz<KK>, gch, b256, 0, s, dch, st, mp, V, W, (const double *)g.diag.p, floor_, T.p,
                            rpart.p);
         HQ_LAUNCH_CHECK();
         // CGS2 against the basis, with T^T T from the first product
-        gram(V, mp + KK, T, gpart.p);
+        gram(V, mp + KK, T, gpart.p, dn);
         hipLaunchKernelGGL(k_bpost_first<KK>, gin, dim3(NT), 0, s, st, mp, tol, (const double *)rpart.p,
                            (const double *)gpart.p);
         HQ_LAUNCH_CHECK();
-        tsmm(V, mp, st.C, MS * KB, KB, NK{}, -1.0, 1.0, T);
-        gram(V, mp, T, gpart.p);
-        hipLaunchKernelGGL(k_bpost_proj<KK>, gin, dim3(NT), 0, s, st, mp, (const double *)gpart.p);
+        tsmm(V, mp, st.C, MS * KB, KB, NK{}, -1.0, 1.0, T, dn);
+        gram(V, mp, T, gpart.p, dn);
+        hipLaunchKernelGGL(k_bpost_proj<KK>, gin, dim3(NT), 0, s, st, dn, mp, (const double *)gpart.p);
         HQ_LAUNCH_CHECK();
-        tsmm(V, mp, st.C, MS * KB, KB, NK{}, -1.0, 1.0, T);
+        tsmm(V, mp, st.C, MS * KB, KB, NK{}, -1.0, 1.0, T, dn);
         // symmetric orthonormalization within the block (unit columns first)
         const Mat Tm{T.p, KK, (int64_t)bsz};
-        gram(Tm, KK, Tm, gpart.p);
-        hipLaunchKernelGGL(k_bpost_orth<KK>, gin, dim3(NT), 0, s, st, mp, 0, 1e-14, (const double *)gpart.p);
+        gram(Tm, KK, Tm, gpart.p, dn);
+        hipLaunchKernelGGL(k_bpost_orth<KK>, gin, dim3(NT), 0, s, st, dn, mp, 0, 1e-14, (const double *)gpart.p);
         HQ_LAUNCH_CHECK();
-        tsmm(Tm, KK, st.Z, KB * KB, KB, NK{}, 1.0, 0.0, Tm);
-        // one more projection and orthonormalization remove what the scaling amplified
-        gram(V, mp, T, gpart.p);
-        hipLaunchKernelGGL(k_bpost_proj<KK>, gin, dim3(NT), 0, s, st, mp, (const double *)gpart.p);
+        tsmm(Tm, KK, st.Z, KB * KB, KB, NK{}, 1.0, 0.0, Tm, dn);
+        // when the transform amplified a small remainder: one more projection
+        // and orthonormalization (instances that do not need it are skipped)
+        gram(V, mp, T, gpart.p, g1);
+        hipLaunchKernelGGL(k_bpost_proj<KK>, gin, dim3(NT), 0, s, st, g1, mp, (const double *)gpart.p);
         HQ_LAUNCH_CHECK();
-        tsmm(V, mp, st.C, MS * KB, KB, NK{}, -1.0, 1.0, T);
-        gram(Tm, KK, Tm, gpart.p);
-        hipLaunchKernelGGL(k_bpost_orth<KK>, gin, dim3(NT), 0, s, st, mp, 1, 1e-4, (const double *)gpart.p);
+        tsmm(V, mp, st.C, MS * KB, KB, NK{}, -1.0, 1.0, T, g1);
+        gram(Tm, KK, Tm, gpart.p, g1);
+        hipLaunchKernelGGL(k_bpost_orth<KK>, gin, dim3(NT), 0, s, st, g1, mp, 1, 1e-4, (const double *)gpart.p);
         HQ_LAUNCH_CHECK();
-        tsmm(Tm, KK, st.Z, KB * KB, KB, NK{}, 1.0, 0.0, Tm);
+        tsmm(Tm, KK, st.Z, KB * KB, KB, NK{}, 1.0, 0.0, Tm, g1);
         // images and the new columns of G
         const Mat Wn = W.cols(mp);
         sigma(T.p, Wn.p);
-        gram(V, mp + KK, Wn, gpart_u.p);
+        gram(V, mp + KK, Wn, gpart_u.p, dn);
         hipLaunchKernelGGL(k_bcount, dim3(1), b256, 0, s, nb, (const int32_t *)st.done, d_ndone.p);
         HQ_LAUNCH_CHECK();
         return mp;

@@ -114,7 +114,8 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restric
 
 // Fused Ritz vector, residual, norm and diagonal preconditioner for KK roots:
 //   r_c = W y_c - theta_c V y_c,   T[:, c] = r_c / clamp(theta_c - H_ii)
-// partial[blk][c] = sum over the block's rows of r_c^2.  One column block of
+// partial[blk][c] = sum over the block's rows of r_c^2 and
+// partial[blk][KK + c] the same for T[:, c]^2.  One column block of
 // V and W (ROWS x KK, contiguous) is staged through LDS at a time; thread
 // (r, c) owns row r of the tile and root c.
 template <int KK>
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(256) void k_ritz(int64_t nrows, int m, Mat V, Mat W
     for (int t = threadIdx.x; t < m * KK; t += 256) sY[t] = Y[t];
     const int r = threadIdx.x / KK, c = threadIdx.x % KK;
     const double th = theta[c];
-    double nrm = 0.0;
+    double nrm = 0.0, tn = 0.0;
     for (int64_t i0 = (int64_t)blockIdx.x * ROWS; i0 < nrows; i0 += (int64_t)gridDim.x * ROWS) {
         double x = 0.0, w = 0.0;
         for (int j0 = 0; j0 < m; j0 += KK) {
@@ -160,6 +161,7 @@ __global__ __launch_bounds__(256) void k_ritz(int64_t nrows, int m, Mat V, Mat W
                 double den = th - diag[row];
                 if (fabs(den) < floor_) den = den < 0.0 ? -floor_ : floor_;
                 out = res / den;
+                tn += out * out;
             }
             T[row * KK + c] = out;
         }
@@ -167,10 +169,17 @@ __global__ __launch_bounds__(256) void k_ritz(int64_t nrows, int m, Mat V, Mat W
     __syncthreads();
     red[threadIdx.x] = nrm;
     __syncthreads();
-    if (threadIdx.x < KK) {
-        double s = 0.0;
+    double s = 0.0;
+    if (threadIdx.x < KK)
         for (int q = 0; q < ROWS; ++q) s += red[q * KK + threadIdx.x];
-        partial[(int64_t)blockIdx.x * KK + threadIdx.x] = s;
+    __syncthreads();
+    red[threadIdx.x] = tn;
+    __syncthreads();
+    if (threadIdx.x < KK) {
+        double t = 0.0;
+        for (int q = 0; q < ROWS; ++q) t += red[q * KK + threadIdx.x];
+        partial[(int64_t)blockIdx.x * 2 * KK + threadIdx.x] = s;
+        partial[(int64_t)blockIdx.x * 2 * KK + KK + threadIdx.x] = t;
     }
 }
 
@@ -582,41 +591,50 @@ struct Solver {
         sigma_columns += nc;
     }
 
-    // Orthonormalize T[:, 0:n] against V[:, 0:m] and within itself; returns the
-    // number of kept directions, left in T[:, 0:kept] (other columns zeroed).
-    // Columns are first scaled to unit norm, so the thresholds are relative: a
-    // direction is dropped when less than 1e-7 of it lies outside span(V) and
-    // the other new directions.
-    int orthonormalize(int m, int n) {
-        double *C = scratch_a();   // m x n
+    // Orthonormalize the columns of T against V[:, 0:m] and within T; returns
+    // the number of kept directions, left in T[:, 0:kept] (other columns
+    // zeroed).  scale[q] (host, K entries) is 1/||T[:, q]|| for the columns to
+    // keep and 0 for those to discard; nullptr = the first n columns, scales
+    // from T^T T.  Scaling to unit columns is folded into the first transform,
+    // so the drop thresholds are relative: a direction is dropped when less
+    // than 1e-7 of it lies outside span(V) and the other new directions.
+    //   round 0: two projection passes (CGS2), then symmetric
+    //            orthonormalization of S T^T T S (eigenvalues > 1e-14 kept);
+    //   round 1: only when round 0 kept an eigenvalue below 1e-2 (its inverse
+    //            square root amplified what was left of span(V)): one more
+    //            projection pass and orthonormalization (eigenvalues > 1e-4).
+    int orthonormalize(int m, int n, const double *scale) {
+        double *C = scratch_a();   // m x K
         double *Zd = scratch_b();  // K x K
-        int kept = 0;
-        {
+        std::vector<double> sc(K, 0.0);
+        if (scale) {
+            for (int q = 0; q < K; ++q) sc[q] = scale[q];
+        } else {
             std::vector<double> g = gram_host(Tm, n, Tm, n);
-            std::vector<int> nz;
             for (int q = 0; q < n; ++q) {
-                double d = g[(size_t)q * n + q];
-                if (std::isfinite(d) && d > 0.0) nz.push_back(q);
+                const double d = g[(size_t)q * n + q];
+                if (std::isfinite(d) && d > 0.0) sc[q] = 1.0 / std::sqrt(d);
             }
-            kept = (int)nz.size();
-            if (kept == 0) return 0;
-            std::vector<double> Dg((size_t)K * K, 0.0);
-            for (int q = 0; q < kept; ++q)
-                Dg[(size_t)nz[q] * K + q] = 1.0 / std::sqrt(g[(size_t)nz[q] * n + nz[q]]);
-            upload_small(Dg, Zd);
-            tsmm(Tm, K, Zd, K, 1.0, 0.0, Tm);
         }
+        int cols = 0;  // columns that may hold a direction
+        for (int q = 0; q < K; ++q)
+            if (sc[q] > 0.0) cols = q + 1;
+        if (cols == 0) return 0;
+        int kept = cols;
+        double wmin = 0.0;
         for (int round = 0; round < 2; ++round) {
+            if (round == 1 && wmin >= 1e-2) break;
             if (m > 0) {
-                for (int pass = 0; pass < 2; ++pass) {
+                for (int pass = 0; pass < (round == 0 ? 2 : 1); ++pass) {
                     gram(V, m, Tm, kept, C);
                     tsmm(V, m, C, kept, -1.0, 1.0, Tm);
                 }
             }
             std::vector<double> g = gram_host(Tm, kept, Tm, kept);
             for (int a = 0; a < kept; ++a)
-                for (int b = a + 1; b < kept; ++b) {
-                    double v = 0.5 * (g[(size_t)a * kept + b] + g[(size_t)b * kept + a]);
+                for (int b = a; b < kept; ++b) {
+                    const double sa = round == 0 ? sc[a] : 1.0, sb = round == 0 ? sc[b] : 1.0;
+                    const double v = sa * sb * 0.5 * (g[(size_t)a * kept + b] + g[(size_t)b * kept + a]);
                     g[(size_t)a * kept + b] = g[(size_t)b * kept + a] = v;
                 }
             std::vector<double> w, Z;
@@ -627,12 +645,14 @@ struct Solver {
                 if (std::isfinite(w[j]) && w[j] > thresh) keep.push_back(j);
             const int nk = (int)keep.size();
             if (nk == 0) return 0;
+            wmin = w[keep.back()];
             // K x K transform: rows >= kept and columns >= nk are zero, so the
             // unused columns of T are cleared as well
             std::vector<double> Zk((size_t)K * K, 0.0);
             for (int a = 0; a < kept; ++a)
                 for (int q = 0; q < nk; ++q)
-                    Zk[(size_t)a * K + q] = Z[(size_t)a * kept + keep[q]] / std::sqrt(w[keep[q]]);
+                    Zk[(size_t)a * K + q] =
+                        (round == 0 ? sc[a] : 1.0) * Z[(size_t)a * kept + keep[q]] / std::sqrt(w[keep[q]]);
             upload_small(Zk, Zd);
             tsmm(Tm, K, Zd, K, 1.0, 0.0, Tm);
             kept = nk;
@@ -736,7 +756,7 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
                            S.guess_idx.p);
         HQ_LAUNCH_CHECK();
     }
-    int m = S.orthonormalize(0, n0 + nunit);
+    int m = S.orthonormalize(0, n0 + nunit, nullptr);
     if (m == 0) throw Error(HINQS_E_INVALID_ARG, "initial guess is zero");
     S.apply_h(S.T.p, m, fp32);
     S.put_columns(S.T.p, m, S.V, 0);
@@ -822,11 +842,13 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
             case 8: launch_ritz<8>(S, m, Yd, thd, o.precond_floor, nroots_eff, grid); break;
             default: launch_ritz<16>(S, m, Yd, thd, o.precond_floor, nroots_eff, grid); break;
         }
-        hipLaunchKernelGGL(k_reduce_partials, dim3(K), dim3(256), 0, s, S.partial.p, (int)grid, K, S.nrm.p);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(2 * K), dim3(256), 0, s, S.partial.p, (int)grid, 2 * K,
+                           S.nrm.p);
         HQ_LAUNCH_CHECK();
-        std::vector<double> rn(K);
-        HQ_CHECK(hipMemcpyAsync(rn.data(), S.nrm.p, sizeof(double) * K, hipMemcpyDeviceToHost, s));
+        std::vector<double> rt(2 * K);
+        HQ_CHECK(hipMemcpyAsync(rt.data(), S.nrm.p, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, s));
         HQ_CHECK(hipStreamSynchronize(s));
+        std::vector<double> rn(rt.begin(), rt.begin() + K), tn2(rt.begin() + K, rt.end());
         for (double &x : rn) x = std::sqrt(std::max(0.0, x));
         res0 = rn[0];
         ++iters;
@@ -864,12 +886,19 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
             mprev = 0;
             continue;  // fresh Rayleigh-Ritz with FP64 images
         }
-        // ---- which roots get a correction
-        std::vector<int> add;
+        // ---- which roots get a correction (the others are scaled to zero)
+        std::vector<double> tscale(K, 0.0);
+        int nadd = 0;
         for (int q = 0; q < nroots_eff; ++q)
-            if (rn[q] > o.tol) add.push_back(q);
-        if (add.empty()) add.push_back(0);
-        const int nadd = (int)add.size();
+            if (rn[q] > o.tol && tn2[q] > 0.0 && std::isfinite(tn2[q])) {
+                tscale[q] = 1.0 / std::sqrt(tn2[q]);
+                ++nadd;
+            }
+        if (nadd == 0 && tn2[0] > 0.0 && std::isfinite(tn2[0])) {
+            tscale[0] = 1.0 / std::sqrt(tn2[0]);
+            nadd = 1;
+        }
+        nadd = std::max(nadd, 1);
         // ---- restart (GD+k): keep current and previous Ritz vectors
         std::vector<double> Ycur((size_t)m * nroots_eff);
         for (int a = 0; a < m; ++a)
@@ -902,14 +931,7 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
             rotate_basis(Qk, q);
             Ycur.swap(Yn);
         }
-        // compact T's columns to the roots that need a correction
-        if (nadd < K) {
-            std::vector<double> P((size_t)K * K, 0.0);
-            for (int q = 0; q < nadd; ++q) P[(size_t)add[q] * K + q] = 1.0;
-            S.upload_small(P, S.scratch_b());
-            S.tsmm(S.Tm, K, S.scratch_b(), K, 1.0, 0.0, S.Tm);
-        }
-        int kept = S.orthonormalize(m, nadd);
+        int kept = S.orthonormalize(m, K, tscale.data());
         if (kept == 0) {
             if (!fp32) break;  // no new direction: report the current Ritz pair, not converged
             best_res_fp32 = 0.0;  // FP32 images cannot resolve further directions: refine in FP64
