@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <memory>
 #include <type_traits>
@@ -42,13 +43,13 @@ struct BatchState {
         int64_t ndet, nnz;
     };
     std::vector<Meta> meta;
-    std::vector<std::unique_ptr<Ctx>> pending;  // built, not yet merged into g
-    int nmerged = 0;                             // instances already merged into g
-    Ctx g;                                       // block-diagonal couplings of the merged instances
-    DBuf<int32_t> perm;                          // global sorted row -> caller index inside its instance
-    DBuf<int32_t> row_inst;                      // global row -> instance
-    DBuf<int64_t> inst_row;                      // row offsets (ninst + 1), device
-    std::vector<int64_t> row_off{0}, nz_off{0};  // host copies of the row / coupling offsets
+    std::vector<int64_t> row_off{0}, nz_off{0};  // row / coupling offsets of the instances (host)
+    Ctx scratch;            // per-instance build; its buffers are reused by the next instance
+    Ctx g;                  // block-diagonal couplings of all instances (arrays grow geometrically)
+    DBuf<int32_t> perm;     // global sorted row -> caller index inside its instance
+    DBuf<int32_t> row_inst; // global row -> instance
+    DBuf<int64_t> inst_row; // row offsets (ninst + 1), device copy
+    bool dirty = true;      // inst_row and the XCD row ranges need a refresh
 };
 
 namespace {
@@ -825,80 +826,44 @@ __global__ void k_fill_i32(int64_t n, int32_t *__restrict__ dst, int32_t v) {
 
 // ------------------------------------------------------------- host side
 
+int env_or(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    return (v && *v) ? std::atoi(v) : dflt;
+}
+
 template <typename T>
 void copy_d2d(T *dst, const T *src, int64_t n, hipStream_t s) {
     if (n > 0) HQ_CHECK(hipMemcpyAsync(dst, src, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
 }
 
-// Merge the pending instances into the block-diagonal matrix.
-void batch_plan(Ctx &c, BatchState &B) {
-    if (B.pending.empty()) return;
-    hipStream_t s = c.stream;
-    const int nb = (int)B.meta.size();
-    const int64_t N0 = B.nmerged > 0 ? B.g.ndet : 0, Z0 = B.nmerged > 0 ? B.g.nnz : 0;
-    const int64_t N = B.row_off[nb], Z = B.nz_off[nb];
-    if (N >= ((int64_t)1 << 31) - 1) throw Error(HINQS_E_UNSUPPORTED, "a batch holds fewer than 2^31 determinants");
-    DBuf<int64_t> rowptr;
-    DBuf<int32_t> col, perm, row_inst;
-    DBuf<double> val, diag;
-    rowptr.ensure(N + 1);
-    col.ensure(std::max<int64_t>(Z, 1));
-    val.ensure(std::max<int64_t>(Z, 1));
-    diag.ensure(N);
-    perm.ensure(N);
-    row_inst.ensure(N);
-    if (N0 > 0) {
-        copy_d2d(rowptr.p, B.g.rowptr.p, N0 + 1, s);
-        copy_d2d(col.p, B.g.col.p, Z0, s);
-        copy_d2d(val.p, B.g.val.p, Z0, s);
-        copy_d2d(diag.p, B.g.diag.p, N0, s);
-        copy_d2d(perm.p, B.perm.p, N0, s);
-        copy_d2d(row_inst.p, B.row_inst.p, N0, s);
-    }
-    for (size_t j = 0; j < B.pending.size(); ++j) {
-        Ctx &p = *B.pending[j];
-        const int bi = B.nmerged + (int)j;
-        const int64_t r0 = B.row_off[bi], z0 = B.nz_off[bi];
-        hipLaunchKernelGGL(k_cat_rowptr, dim3(grid_for(p.ndet + 1, 256)), dim3(256), 0, s, p.ndet, p.rowptr.p,
-                           rowptr.p + r0, z0);
-        HQ_LAUNCH_CHECK();
-        if (p.nnz > 0) {
-            hipLaunchKernelGGL(k_cat_col, dim3(grid_for(p.nnz, 256)), dim3(256), 0, s, p.nnz, p.col.p, col.p + z0,
-                               (int32_t)r0);
-            HQ_LAUNCH_CHECK();
-            copy_d2d(val.p + z0, p.val.p, p.nnz, s);
-        }
-        copy_d2d(diag.p + r0, p.diag.p, p.ndet, s);
-        copy_d2d(perm.p + r0, p.perm.p, p.ndet, s);
-        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(p.ndet, 256)), dim3(256), 0, s, p.ndet, row_inst.p + r0,
-                           (int32_t)bi);
-        HQ_LAUNCH_CHECK();
-    }
+// Capacity of b raised to at least `need` elements, keeping the first `used`
+// (geometric growth, so appending instances one by one copies O(total)).
+template <typename T>
+void grow_keep(DBuf<T> &b, size_t used, size_t need, hipStream_t s) {
+    if (b.p && need <= b.n) return;
+    DBuf<T> nbuf;
+    nbuf.ensure(std::max(need, 2 * b.n));
+    copy_d2d(nbuf.p, b.p, (int64_t)used, s);
     HQ_CHECK(hipStreamSynchronize(s));
-    B.g.rowptr.swap(rowptr);
-    B.g.col.swap(col);
-    B.g.val.swap(val);
-    B.g.diag.swap(diag);
-    B.perm.swap(perm);
-    B.row_inst.swap(row_inst);
+    b.swap(nbuf);
+}
+
+// Per-solve tables of the concatenated matrix: instance row offsets on the
+// device and the coupling-balanced XCD row ranges.
+void batch_layout(Ctx &c, BatchState &B) {
+    if (!B.dirty) return;
+    const int nb = (int)B.meta.size();
     B.g.device = c.device;
     B.g.stream = c.stream;
-    B.g.ndet = N;
-    B.g.nnz = Z;
     B.g.have_elements = true;
     for (auto &row : B.g.sigma_cfg)
         for (auto &cfg : row) cfg = SigmaCfg{};
     compute_xcd_rows(B.g);
     B.inst_row.ensure(nb + 1);
-    HQ_CHECK(hipMemcpyAsync(B.inst_row.p, B.row_off.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice, s));
-    HQ_CHECK(hipStreamSynchronize(s));
-    B.pending.clear();
-    B.nmerged = nb;
-}
-
-int env_or(const char *name, int dflt) {
-    const char *v = std::getenv(name);
-    return (v && *v) ? std::atoi(v) : dflt;
+    HQ_CHECK(hipMemcpyAsync(B.inst_row.p, B.row_off.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice,
+                            c.stream));
+    HQ_CHECK(hipStreamSynchronize(c.stream));
+    B.dirty = false;
 }
 
 struct Resources {  // released on every exit path
@@ -1001,6 +966,8 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
         st.energy = p; p += nb;
         st.resid = p;  p += nb;
     }
+    HQ_CHECK(hipStreamSynchronize(s));
+    const auto t_buf = std::chrono::steady_clock::now();
     hipLaunchKernelGGL(k_bvalid_init, dim3(grid_for((int64_t)nb * MS, 256)), dim3(256), 0, s, nb, KK, st.valid);
     HQ_LAUNCH_CHECK();
     HQ_CHECK(hipFuncSetAttribute((const void *)k_brr<KK>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1102,6 +1069,11 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
 
     HQ_CHECK(hipStreamSynchronize(s));
     const auto t1 = std::chrono::steady_clock::now();
+    const bool verbose = env_or("HINQS_VERBOSE", 0) != 0;
+    if (verbose)
+        std::fprintf(stderr, "[hinqs] batch setup %.2f ms (buffers ready %.2f ms)\n",
+                     std::chrono::duration<double, std::milli>(t1 - t0).count(),
+                     std::chrono::duration<double, std::milli>(t_buf - t0).count());
     R.ex.assign(mmax / KK + 1, nullptr);
     int m = KK, it = 0, m_last = KK, ngraphs = 0;
     int32_t ndone = 0;
@@ -1137,6 +1109,9 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
         m = mp + KK;
     }
     const auto t2 = std::chrono::steady_clock::now();
+    if (verbose)
+        std::fprintf(stderr, "[hinqs] batch loop %.2f ms (capture %.2f ms, %d iterations)\n",
+                     std::chrono::duration<double, std::milli>(t2 - t1).count(), ms_capture, it);
 
     // ---- final vectors: x = V y_0, normalized, largest component positive, caller order
     hipLaunchKernelGGL(k_bfinal_x, gch, b256, 0, s, dch, st, m_last, V, xfin.p, fpart.p, ipart.p);
@@ -1195,7 +1170,16 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
 
 }  // namespace
 
-void batch_clear(Ctx &c) { c.batch.reset(); }
+void batch_clear(Ctx &c) {
+    if (!c.batch) return;
+    BatchState &B = *c.batch;  // device buffers are kept for the next instances
+    B.meta.clear();
+    B.row_off.assign(1, 0);
+    B.nz_off.assign(1, 0);
+    B.g.ndet = 0;
+    B.g.nnz = 0;
+    B.dirty = true;
+}
 
 int batch_add(Ctx &c, int norb, const double *h, const double *eri, double ecore, int64_t ndet,
               const uint64_t *alpha, const uint64_t *beta, int na, int nb) {
@@ -1203,19 +1187,53 @@ int batch_add(Ctx &c, int norb, const double *h, const double *eri, double ecore
     BatchState &B = *c.batch;
     if (B.row_off.back() + ndet >= ((int64_t)1 << 31) - 1)
         throw Error(HINQS_E_UNSUPPORTED, "a batch holds fewer than 2^31 determinants");
-    auto p = std::make_unique<Ctx>();
-    p->device = c.device;
-    p->stream = c.stream;
-    build_integrals(*p, norb, h, eri, ecore);
-    build_determinants(*p, ndet, alpha, beta, na, nb, false);
-    build_connectivity(*p);
-    build_elements(*p);
-    // the instance's buffers are kept until the merge (one release per instance then)
-    B.meta.push_back({norb, na, nb, p->ndet, p->nnz});
-    B.row_off.push_back(B.row_off.back() + p->ndet);
-    B.nz_off.push_back(B.nz_off.back() + p->nnz);
-    B.pending.push_back(std::move(p));
-    return (int)B.meta.size() - 1;
+    Ctx &p = B.scratch;
+    p.device = c.device;
+    p.stream = c.stream;
+    p.have_ints = p.have_dets = p.have_elements = false;
+    {
+        struct Grow {
+            Grow() { g_dbuf_grow = true; }
+            ~Grow() { g_dbuf_grow = false; }
+        } grow;
+        build_integrals(p, norb, h, eri, ecore);
+        build_determinants(p, ndet, alpha, beta, na, nb, false);
+        build_connectivity(p);
+        build_elements(p);
+    }
+    // append to the concatenated arrays
+    hipStream_t s = c.stream;
+    const int bi = (int)B.meta.size();
+    const int64_t r0 = B.row_off.back(), z0 = B.nz_off.back();
+    const int64_t r1 = r0 + p.ndet, z1 = z0 + p.nnz;
+    grow_keep(B.g.rowptr, (size_t)(bi ? r0 + 1 : 0), (size_t)(r1 + 1), s);
+    grow_keep(B.g.col, (size_t)z0, (size_t)std::max<int64_t>(z1, 1), s);
+    grow_keep(B.g.val, (size_t)z0, (size_t)std::max<int64_t>(z1, 1), s);
+    grow_keep(B.g.diag, (size_t)r0, (size_t)r1, s);
+    grow_keep(B.perm, (size_t)r0, (size_t)r1, s);
+    grow_keep(B.row_inst, (size_t)r0, (size_t)r1, s);
+    hipLaunchKernelGGL(k_cat_rowptr, dim3(grid_for(p.ndet + 1, 256)), dim3(256), 0, s, p.ndet, p.rowptr.p,
+                       B.g.rowptr.p + r0, z0);
+    HQ_LAUNCH_CHECK();
+    if (p.nnz > 0) {
+        hipLaunchKernelGGL(k_cat_col, dim3(grid_for(p.nnz, 256)), dim3(256), 0, s, p.nnz, p.col.p, B.g.col.p + z0,
+                           (int32_t)r0);
+        HQ_LAUNCH_CHECK();
+        copy_d2d(B.g.val.p + z0, p.val.p, p.nnz, s);
+    }
+    copy_d2d(B.g.diag.p + r0, p.diag.p, p.ndet, s);
+    copy_d2d(B.perm.p + r0, p.perm.p, p.ndet, s);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(p.ndet, 256)), dim3(256), 0, s, p.ndet, B.row_inst.p + r0,
+                       (int32_t)bi);
+    HQ_LAUNCH_CHECK();
+    HQ_CHECK(hipStreamSynchronize(s));
+    B.g.ndet = r1;
+    B.g.nnz = z1;
+    B.meta.push_back({norb, na, nb, p.ndet, p.nnz});
+    B.row_off.push_back(r1);
+    B.nz_off.push_back(z1);
+    B.dirty = true;
+    return bi;
 }
 
 void batch_info(Ctx &c, int *ninst, int64_t *offsets, int64_t *nnz) {
@@ -1242,7 +1260,7 @@ int batch_solve(Ctx &c, const hinqs_opts &o, double *energies, double *coeffs, i
         if (B.meta[b].ndet < mmax)
             throw Error(HINQS_E_UNSUPPORTED, "instance " + std::to_string(b) +
                                                  " has fewer determinants than the subspace size; solve it alone");
-    batch_plan(c, B);
+    batch_layout(c, B);
     switch (K) {
         case 1: return batch_solve_k<1>(c, B, o, mmax, energies, coeffs, status, iters_out, stats, t0);
         case 2: return batch_solve_k<2>(c, B, o, mmax, energies, coeffs, status, iters_out, stats, t0);

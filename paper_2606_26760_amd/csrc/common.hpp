@@ -34,6 +34,11 @@ struct Error : std::runtime_error {
 #define HQ_LAUNCH_CHECK() HQ_CHECK(hipGetLastError())
 
 // ---------------------------------------------------------- device buffer
+// While set, buffers (re)allocated on this thread get twice the requested
+// capacity, so a context rebuilt for a sequence of growing problems (the
+// instances of a batch) reallocates rarely.
+inline thread_local bool g_dbuf_grow = false;
+
 template <typename T>
 struct DBuf {
     T *p = nullptr;
@@ -51,6 +56,7 @@ struct DBuf {
     void ensure(size_t count) {
         if (count <= n && p) return;
         release();
+        if (g_dbuf_grow) count *= 2;
         size_t bytes = (count ? count : 1) * sizeof(T);
         hipError_t e = hipMalloc((void **)&p, bytes);
         if (e != hipSuccess) {
