@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "dense.hpp"
 
 namespace hinqs {
 
@@ -104,15 +105,18 @@ __device__ double wave_sum(double v) {
 }
 
 // Parallel cyclic Jacobi eigensolver for the symmetric n x n matrix A (LDS,
-// leading dimension LD, n <= 64).  Rotations follow a round-robin pairing:
-// each round pairs every index once, the n/2 disjoint rotations are computed
-// from the current matrix and applied together (columns, then rows).  Sweeps
-// stop when the off-diagonal mass falls below 1e-32 of the Frobenius norm.
-// On return A's diagonal holds the eigenvalues and row j of ZT the
-// eigenvector belonging to A[j][j].
-template <int LD>
+// leading dimension LD, n <= MAXN <= 64).  Rotations follow a round-robin
+// pairing: each round pairs every index once, the n/2 disjoint rotations are
+// computed from the current matrix and applied together (columns, then
+// rows); the (pair, index) decomposition of each thread's elements is
+// computed once, so a round costs only LDS traffic and one rotation per
+// pair.  Sweeps stop when the off-diagonal mass falls below 1e-32 of the
+// Frobenius norm.  On return A's diagonal holds the eigenvalues and row j of
+// ZT the eigenvector belonging to A[j][j].
+template <int LD, int MAXN>
 __device__ void block_jacobi(int n, double *A, double *ZT, int *pp, int *pq, double *pc, double *ps,
                              double *red) {
+    constexpr int MAXE = ((MAXN + 1) / 2 * MAXN + NT - 1) / NT;  // elements per thread and phase
     const int tid = threadIdx.x;
     for (int e = tid; e < n * n; e += NT) {
         const int i = e / n, j = e % n;
@@ -126,6 +130,20 @@ __device__ void block_jacobi(int n, double *A, double *ZT, int *pp, int *pq, dou
     const double fro = block_sum(f, red);
     if (n < 2) return;
     const int ne = n + (n & 1), np = ne / 2, nr = ne - 1;
+    const int nel = np * n;
+    // (pair, index) of every element this thread updates, fixed for the whole
+    // solve: column phase pairs vary fastest (neighbouring threads hit
+    // different banks), row phase indices vary fastest (contiguous rows)
+    int ck[MAXE], cj[MAXE], rk[MAXE], rj[MAXE];
+#pragma unroll
+    for (int u = 0; u < MAXE; ++u) {
+        const int e = tid + u * NT;
+        const bool ok = e < nel;
+        ck[u] = ok ? e % np : -1;
+        cj[u] = ok ? e / np : 0;
+        rk[u] = ok ? e / n : -1;
+        rj[u] = ok ? e % n : 0;
+    }
     for (int sweep = 0; sweep < 50; ++sweep) {
         double o = 0.0;
         for (int e = tid; e < n * n; e += NT) {
@@ -141,8 +159,10 @@ __device__ void block_jacobi(int n, double *A, double *ZT, int *pp, int *pq, dou
                     a = r;
                     b = ne - 1;
                 } else {
-                    a = (r + tid) % nr;
-                    b = (r - tid + nr) % nr;
+                    a = r + tid;
+                    if (a >= nr) a -= nr;
+                    b = r - tid;
+                    if (b < 0) b += nr;
                 }
                 const int p = min(a, b), q = max(a, b);
                 double c = 1.0, s = 0.0;
@@ -156,36 +176,35 @@ __device__ void block_jacobi(int n, double *A, double *ZT, int *pp, int *pq, dou
                     }
                 }
                 pp[tid] = p;
-                pq[tid] = q < n ? q : -1;
+                pq[tid] = (q < n && s != 0.0) ? q : -1;  // -1: nothing to rotate
                 pc[tid] = c;
                 ps[tid] = s;
             }
             __syncthreads();
-            // columns p, q (pairs vary fastest so neighbouring threads hit different banks)
-            for (int e = tid; e < np * n; e += NT) {
-                const int k = e % np, j = e / np;
-                const int p = pp[k], q = pq[k];
-                const double s = ps[k];
-                if (q < 0 || s == 0.0) continue;
-                const double c = pc[k];
-                const double ajp = A[j * LD + p], ajq = A[j * LD + q];
-                A[j * LD + p] = c * ajp - s * ajq;
-                A[j * LD + q] = s * ajp + c * ajq;
+#pragma unroll
+            for (int u = 0; u < MAXE; ++u) {  // columns p, q
+                if (ck[u] < 0) continue;
+                const int q = pq[ck[u]];
+                if (q < 0) continue;
+                const int o1 = cj[u] * LD + pp[ck[u]], o2 = cj[u] * LD + q;
+                const double c = pc[ck[u]], s = ps[ck[u]];
+                const double x1 = A[o1], x2 = A[o2];
+                A[o1] = c * x1 - s * x2;
+                A[o2] = s * x1 + c * x2;
             }
             __syncthreads();
-            // rows p, q and the eigenvector rows
-            for (int e = tid; e < np * n; e += NT) {
-                const int k = e / n, j = e % n;
-                const int p = pp[k], q = pq[k];
-                const double s = ps[k];
-                if (q < 0 || s == 0.0) continue;
-                const double c = pc[k];
-                const double apj = A[p * LD + j], aqj = A[q * LD + j];
-                A[p * LD + j] = c * apj - s * aqj;
-                A[q * LD + j] = s * apj + c * aqj;
-                const double zp = ZT[p * LD + j], zq = ZT[q * LD + j];
-                ZT[p * LD + j] = c * zp - s * zq;
-                ZT[q * LD + j] = s * zp + c * zq;
+#pragma unroll
+            for (int u = 0; u < MAXE; ++u) {  // rows p, q and the eigenvector rows
+                if (rk[u] < 0) continue;
+                const int q = pq[rk[u]];
+                if (q < 0) continue;
+                const int o1 = pp[rk[u]] * LD + rj[u], o2 = q * LD + rj[u];
+                const double c = pc[rk[u]], s = ps[rk[u]];
+                const double x1 = A[o1], x2 = A[o2], z1 = ZT[o1], z2 = ZT[o2];
+                A[o1] = c * x1 - s * x2;
+                A[o2] = s * x1 + c * x2;
+                ZT[o1] = c * z1 - s * z2;
+                ZT[o2] = s * z1 + c * z2;
             }
             __syncthreads();
         }
@@ -248,100 +267,55 @@ __global__ __launch_bounds__(256) void k_bgram(const Chunk *__restrict__ chunks,
 }
 
 // Out(i, c) = beta Out(i, c) + alpha sum_{j<m} A(i, j) B_inst[j][c] for the
-// rows of each chunk, with B_inst = Bs + inst * bstride (leading dimension
-// ldb).  A tile's A rows are all read (across a barrier) before the tile is
-// written, so Out may alias A.
-template <int NC>
+// rows of each chunk (tsmm_row), with B_inst = Bs + inst * bstride (leading
+// dimension ldb) and A.kb == KB.  Out may alias A.
+template <int KB, int NC>
 __global__ __launch_bounds__(256) void k_btsmm(const Chunk *__restrict__ chunks, const int32_t *__restrict__ done,
                                                int m, Mat A, const double *__restrict__ Bs, int bstride, int ldb,
                                                int nc, double alpha, double beta, Mat Out) {
     const Chunk ch = chunks[blockIdx.x];
     if (done[ch.inst]) return;
-    constexpr int ROWS = 256 / NC;
-    __shared__ double sA[ROWS * 16];
+    using L = RowLanes<KB>;
+    constexpr int RPB = 256 / L::LPN;
     __shared__ double sB[MS * NC];
     const double *B = Bs + (int64_t)ch.inst * bstride;
-    for (int t = threadIdx.x; t < m * NC; t += 256) {
+    const int nbk = (m + KB - 1) / KB;
+    for (int t = threadIdx.x; t < nbk * KB * NC; t += 256) {
         const int j = t / NC, cc = t % NC;
-        sB[t] = cc < nc ? B[j * ldb + cc] : 0.0;
+        sB[t] = (j < m && cc < nc) ? B[j * ldb + cc] : 0.0;
     }
-    const int r = threadIdx.x / NC, c = threadIdx.x % NC;
-    const int kb = A.kb;
+    __syncthreads();
+    const int g = threadIdx.x / L::LPN, q = threadIdx.x % L::LPN;
     const int64_t end = ch.r0 + ch.n;
-    for (int64_t i0 = ch.r0; i0 < end; i0 += ROWS) {
-        double acc = 0.0;
-        for (int j0 = 0; j0 < m; j0 += kb) {
-            const int jn = min(kb, m - j0);
-            __syncthreads();
-            for (int f = threadIdx.x; f < ROWS * kb; f += 256) {
-                const int rr = f / kb, j = f % kb;
-                const int64_t row = i0 + rr;
-                sA[rr * 16 + j] = (row < end && j < jn) ? *A.at(row, j0 + j) : 0.0;
-            }
-            __syncthreads();
-            for (int j = 0; j < jn; ++j) acc += sA[r * 16 + j] * sB[(j0 + j) * NC + c];
-        }
-        __syncthreads();  // every read of this tile's A rows is done
-        const int64_t row = i0 + r;
-        if (row < end && c < nc) {
-            double *o = Out.at(row, c);
-            *o = (beta == 0.0 ? 0.0 : beta * *o) + alpha * acc;
-        }
-    }
+    for (int64_t i = ch.r0 + g; i < end; i += RPB) tsmm_row<KB, NC>(i, m, A, sB, nc, alpha, beta, Out, q);
 }
 
-// Ritz vectors, residuals and preconditioned corrections of every root:
-//   r_c = W y_c - theta_c V y_c,  T[i][c] = r_c[i] / clamp(theta_c - H_ii)
-// with per-chunk partial sums of r_c^2.
+// Ritz vectors, residuals and preconditioned corrections of every root
+// (ritz_row), with per-chunk partial sums of r_c^2.
 template <int KK>
 __global__ __launch_bounds__(256) void k_britz(const Chunk *__restrict__ chunks, BDev st, int m, Mat V, Mat W,
                                                const double *__restrict__ diag, double floor_,
                                                double *__restrict__ T, double *__restrict__ rpart) {
     const Chunk ch = chunks[blockIdx.x];
     if (st.done[ch.inst]) return;
-    constexpr int ROWS = 256 / KK;
-    __shared__ double sV[ROWS * KK];
-    __shared__ double sW[ROWS * KK];
+    using L = RowLanes<KK>;
+    constexpr int RPB = 256 / L::LPN;
     __shared__ double sY[MS * KK];
-    __shared__ double red[256];
+    __shared__ double sTh[KK];
+    __shared__ double red[512];
     const double *Yb = st.Y + (int64_t)ch.inst * MS * KB;
     for (int t = threadIdx.x; t < m * KK; t += 256) sY[t] = Yb[(t / KK) * KB + t % KK];
-    const int r = threadIdx.x / KK, c = threadIdx.x % KK;
-    const double th = st.theta[ch.inst * KB + c];
-    const int64_t end = ch.r0 + ch.n;
-    double nrm = 0.0;
-    for (int64_t i0 = ch.r0; i0 < end; i0 += ROWS) {
-        double x = 0.0, w = 0.0;
-        const int64_t row = i0 + r;
-        const bool ok = row < end;
-        for (int j0 = 0; j0 < m; j0 += KK) {
-            __syncthreads();
-            sV[threadIdx.x] = ok ? *V.at(row, j0 + c) : 0.0;
-            sW[threadIdx.x] = ok ? *W.at(row, j0 + c) : 0.0;
-            __syncthreads();
+    if (threadIdx.x < KK) sTh[threadIdx.x] = st.theta[ch.inst * KB + threadIdx.x];
+    __syncthreads();
+    const int g = threadIdx.x / L::LPN, q = threadIdx.x % L::LPN;
+    double rn2[L::EPL], tn2[L::EPL];
 #pragma unroll
-            for (int j = 0; j < KK; ++j) {
-                const double y = sY[(j0 + j) * KK + c];
-                x += sV[r * KK + j] * y;
-                w += sW[r * KK + j] * y;
-            }
-        }
-        if (ok) {
-            const double res = w - th * x;
-            nrm += res * res;
-            double den = th - diag[row];
-            if (fabs(den) < floor_) den = den < 0.0 ? -floor_ : floor_;
-            T[row * KK + c] = res / den;
-        }
-    }
-    __syncthreads();
-    red[threadIdx.x] = nrm;
-    __syncthreads();
-    if (threadIdx.x < KK) {
-        double s = 0.0;
-        for (int q = 0; q < ROWS; ++q) s += red[q * KK + threadIdx.x];
-        rpart[(int64_t)blockIdx.x * RSTRIDE + threadIdx.x] = s;
-    }
+    for (int e = 0; e < L::EPL; ++e) rn2[e] = tn2[e] = 0.0;
+    const int64_t end = ch.r0 + ch.n;
+    for (int64_t i = ch.r0 + g; i < end; i += RPB) ritz_row<KK>(i, m, V, W, sY, sTh, diag[i], floor_, KK, T, q, rn2, tn2);
+    double rs, ts;
+    ritz_block_sums<KK>(rn2, tn2, red, rs, ts);
+    if (threadIdx.x < KK) rpart[(int64_t)blockIdx.x * RSTRIDE + threadIdx.x] = rs;
 }
 
 // ------------------------------------------------------- per-instance kernels
@@ -406,7 +380,7 @@ __global__ __launch_bounds__(NT) void k_brr(BDev st, int m, int restart, const d
         A[i * RR_LD + j] = gval(vidx[i], vidx[j]);
     }
     __syncthreads();
-    block_jacobi<RR_LD>(nv, A, ZT, pp, pq, pc, ps, red);
+    block_jacobi<RR_LD, MS>(nv, A, ZT, pp, pq, pc, ps, red);
     __syncthreads();
     for (int e = tid; e < MS * KK; e += NT) Yn[e] = 0.0;
     if (tid < KK) th[tid] = 0.0;
@@ -581,7 +555,7 @@ __global__ __launch_bounds__(NT) void k_bpost_orth(BDev st, const int32_t *__res
         A[i * LD + j] = sc[i] * sc[j] * 0.5 * (ZT[i * LD + j] + ZT[j * LD + i]);
     }
     __syncthreads();
-    block_jacobi<LD>(KK, A, ZT, pp, pq, pc, ps, red);
+    block_jacobi<LD, KK>(KK, A, ZT, pp, pq, pc, ps, red);
     __syncthreads();
     double *Zb = st.Z + (int64_t)b * KB * KB;
     for (int e = tid; e < KB * KB; e += NT) Zb[e] = 0.0;
@@ -996,8 +970,8 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     auto tsmm = [&](Mat A, int m, const double *Bs, int bstride, int ldb, auto ncc, double alpha, double beta,
                     Mat Out, const int32_t *gate) {
         constexpr int NC = decltype(ncc)::value;
-        hipLaunchKernelGGL(k_btsmm<NC>, gch, b256, 0, s, dch, gate, m, A, Bs, bstride, ldb, NC, alpha, beta,
-                           Out);
+        hipLaunchKernelGGL((k_btsmm<KK, NC>), gch, b256, 0, s, dch, gate, m, A, Bs, bstride, ldb, NC, alpha,
+                           beta, Out);
         HQ_LAUNCH_CHECK();
     };
     using NK = std::integral_constant<int, KK>;

@@ -32,6 +32,7 @@
 #include <numeric>
 
 #include "common.hpp"
+#include "dense.hpp"
 
 namespace hinqs {
 
@@ -112,113 +113,56 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restric
     if (threadIdx.x == 0) out[e] = red[0];
 }
 
-// Fused Ritz vector, residual, norm and diagonal preconditioner for KK roots:
+// Fused Ritz vector, residual, norm and diagonal preconditioner for the
+// first nroots of KB roots (ritz_row):
 //   r_c = W y_c - theta_c V y_c,   T[:, c] = r_c / clamp(theta_c - H_ii)
 // partial[blk][c] = sum over the block's rows of r_c^2 and
-// partial[blk][KK + c] the same for T[:, c]^2.  One column block of
-// V and W (ROWS x KK, contiguous) is staged through LDS at a time; thread
-// (r, c) owns row r of the tile and root c.
-template <int KK>
-__global__ __launch_bounds__(256) void k_ritz(int64_t nrows, int m, Mat V, Mat W,
-                                              const double *__restrict__ Y,
-                                              const double *__restrict__ theta,
-                                              const double *__restrict__ diag, double floor_,
-                                              int nroots, double *__restrict__ T,
+// partial[blk][KB + c] the same for T[:, c]^2.
+template <int KB>
+__global__ __launch_bounds__(256) void k_ritz(int64_t nrows, int m, Mat V, Mat W, const double *__restrict__ Y,
+                                              const double *__restrict__ theta, const double *__restrict__ diag,
+                                              double floor_, int nroots, double *__restrict__ T,
                                               double *__restrict__ partial) {
-    constexpr int ROWS = 256 / KK;
-    __shared__ double sV[ROWS * KK];
-    __shared__ double sW[ROWS * KK];
-    __shared__ double sY[96 * KK];
-    __shared__ double red[256];
-    for (int t = threadIdx.x; t < m * KK; t += 256) sY[t] = Y[t];
-    const int r = threadIdx.x / KK, c = threadIdx.x % KK;
-    const double th = theta[c];
-    double nrm = 0.0, tn = 0.0;
-    for (int64_t i0 = (int64_t)blockIdx.x * ROWS; i0 < nrows; i0 += (int64_t)gridDim.x * ROWS) {
-        double x = 0.0, w = 0.0;
-        for (int j0 = 0; j0 < m; j0 += KK) {
-            const int jn = min(KK, m - j0);
-            __syncthreads();
-            {
-                const int64_t row = i0 + r;
-                const bool ok = row < nrows && c < jn;
-                sV[threadIdx.x] = ok ? *V.at(row, j0 + c) : 0.0;
-                sW[threadIdx.x] = ok ? *W.at(row, j0 + c) : 0.0;
-            }
-            __syncthreads();
-            for (int j = 0; j < jn; ++j) {
-                const double y = sY[(j0 + j) * KK + c];
-                x += sV[r * KK + j] * y;
-                w += sW[r * KK + j] * y;
-            }
-        }
-        const int64_t row = i0 + r;
-        if (row < nrows) {
-            double out = 0.0;
-            if (c < nroots) {
-                const double res = w - th * x;
-                nrm += res * res;
-                double den = th - diag[row];
-                if (fabs(den) < floor_) den = den < 0.0 ? -floor_ : floor_;
-                out = res / den;
-                tn += out * out;
-            }
-            T[row * KK + c] = out;
-        }
-    }
+    using L = RowLanes<KB>;
+    constexpr int RPB = 256 / L::LPN;
+    __shared__ double sY[96 * KB];
+    __shared__ double sTh[KB];
+    __shared__ double red[512];
+    const int nbk = (m + KB - 1) / KB;
+    for (int t = threadIdx.x; t < nbk * KB * KB; t += 256) sY[t] = t < m * KB ? Y[t] : 0.0;
+    if (threadIdx.x < KB) sTh[threadIdx.x] = theta[threadIdx.x];
     __syncthreads();
-    red[threadIdx.x] = nrm;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x < KK)
-        for (int q = 0; q < ROWS; ++q) s += red[q * KK + threadIdx.x];
-    __syncthreads();
-    red[threadIdx.x] = tn;
-    __syncthreads();
-    if (threadIdx.x < KK) {
-        double t = 0.0;
-        for (int q = 0; q < ROWS; ++q) t += red[q * KK + threadIdx.x];
-        partial[(int64_t)blockIdx.x * 2 * KK + threadIdx.x] = s;
-        partial[(int64_t)blockIdx.x * 2 * KK + KK + threadIdx.x] = t;
+    const int g = threadIdx.x / L::LPN, q = threadIdx.x % L::LPN;
+    double rn2[L::EPL], tn2[L::EPL];
+#pragma unroll
+    for (int e = 0; e < L::EPL; ++e) rn2[e] = tn2[e] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RPB + g; i < nrows; i += (int64_t)gridDim.x * RPB)
+        ritz_row<KB>(i, m, V, W, sY, sTh, diag[i], floor_, nroots, T, q, rn2, tn2);
+    double rs, ts;
+    ritz_block_sums<KB>(rn2, tn2, red, rs, ts);
+    if (threadIdx.x < KB) {
+        partial[(int64_t)blockIdx.x * 2 * KB + threadIdx.x] = rs;
+        partial[(int64_t)blockIdx.x * 2 * KB + KB + threadIdx.x] = ts;
     }
 }
 
-// Out(i, c) = beta * Out(i, c) + alpha * sum_j A(i, j) B[j][c],  c < nc <= NC, j < m <= 96.
-// A is read one column block (kb <= 16 columns) at a time through LDS.  Every
-// global read of a tile's A rows precedes (across a barrier) every write of
-// the tile, so Out may alias A (in-place basis rotation, nc <= m).
-template <int NC>
-__global__ __launch_bounds__(256) void k_tsmm(int64_t nrows, int m, Mat A, const double *__restrict__ B,
-                                              int nc, double alpha, double beta, Mat Out) {
-    constexpr int ROWS = 256 / NC;
-    __shared__ double sA[ROWS * 16];
+// Out(i, c) = beta * Out(i, c) + alpha * sum_{j<m} A(i, j) B[j][c] (tsmm_row),
+// c < nc <= NC, m <= 96, A.kb == KB; B is m x nc row-major.  Out may alias A.
+template <int KB, int NC>
+__global__ __launch_bounds__(256) void k_tsmm(int64_t nrows, int m, Mat A, const double *__restrict__ B, int nc,
+                                              double alpha, double beta, Mat Out) {
+    using L = RowLanes<KB>;
+    constexpr int RPB = 256 / L::LPN;
     __shared__ double sB[96 * NC];
-    for (int t = threadIdx.x; t < m * NC; t += 256) {
+    const int nbk = (m + KB - 1) / KB;
+    for (int t = threadIdx.x; t < nbk * KB * NC; t += 256) {
         const int j = t / NC, cc = t % NC;
-        sB[t] = cc < nc ? B[j * nc + cc] : 0.0;
+        sB[t] = (j < m && cc < nc) ? B[j * nc + cc] : 0.0;
     }
-    const int r = threadIdx.x / NC, c = threadIdx.x % NC;
-    const int kb = A.kb;
-    for (int64_t i0 = (int64_t)blockIdx.x * ROWS; i0 < nrows; i0 += (int64_t)gridDim.x * ROWS) {
-        double acc = 0.0;
-        for (int j0 = 0; j0 < m; j0 += kb) {
-            const int jn = min(kb, m - j0);
-            __syncthreads();
-            for (int f = threadIdx.x; f < ROWS * kb; f += 256) {
-                const int rr = f / kb, j = f % kb;
-                const int64_t row = i0 + rr;
-                sA[rr * 16 + j] = (row < nrows && j < jn) ? *A.at(row, j0 + j) : 0.0;
-            }
-            __syncthreads();
-            for (int j = 0; j < jn; ++j) acc += sA[r * 16 + j] * sB[(j0 + j) * NC + c];
-        }
-        __syncthreads();  // all reads of this tile's A rows are done
-        const int64_t row = i0 + r;
-        if (row < nrows && c < nc) {
-            double *o = Out.at(row, c);
-            *o = (beta == 0.0 ? 0.0 : beta * *o) + alpha * acc;
-        }
-    }
+    __syncthreads();
+    const int g = threadIdx.x / L::LPN, q = threadIdx.x % L::LPN;
+    for (int64_t i = (int64_t)blockIdx.x * RPB + g; i < nrows; i += (int64_t)gridDim.x * RPB)
+        tsmm_row<KB, NC>(i, m, A, sB, nc, alpha, beta, Out, q);
 }
 
 // dst(i, c0 + c) = src[i * K + c] for c < nc.
@@ -440,6 +384,119 @@ void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w, std::vecto
     }
 }
 
+// Symmetric eigendecomposition by Householder reduction to tridiagonal form
+// followed by the implicit-shift QL iteration (the classic tridiagonal
+// eigenvalue method of Bowdler, Martin, Reinsch and Wilkinson), with the
+// transformations accumulated into the eigenvectors: O(n^3) with a small
+// constant, several times faster than cyclic Jacobi at the subspace sizes of
+// the solver.  Same outputs as jacobi_eig; returns false if an eigenvalue
+// needs more than 60 QL iterations (the caller then falls back to Jacobi).
+bool tridiag_ql_eig(int n, std::vector<double> A, std::vector<double> &w, std::vector<double> &Z) {
+    auto a = [&](int i, int j) -> double & { return A[(size_t)i * n + j]; };
+    std::vector<double> Q((size_t)n * n, 0.0), v(n), pv(n), d(n), e(n, 0.0);
+    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+    // Householder: A <- H A H column by column, Q <- Q H
+    for (int k = 0; k + 2 < n; ++k) {
+        double alpha = 0.0;
+        for (int i = k + 1; i < n; ++i) alpha += a(i, k) * a(i, k);
+        alpha = std::sqrt(alpha);
+        if (alpha == 0.0) continue;
+        if (a(k + 1, k) > 0.0) alpha = -alpha;  // v = x - alpha e1 without cancellation
+        double vv = 0.0;
+        for (int i = 0; i < n; ++i) v[i] = 0.0;
+        for (int i = k + 1; i < n; ++i) v[i] = a(i, k);
+        v[k + 1] -= alpha;
+        for (int i = k + 1; i < n; ++i) vv += v[i] * v[i];
+        if (vv == 0.0) continue;
+        const double beta = 2.0 / vv;
+        // p = beta A v, q = p - (beta/2)(v.p) v, A <- A - v q^T - q v^T
+        double vp = 0.0;
+        for (int i = k; i < n; ++i) {
+            double t = 0.0;
+            for (int j = k + 1; j < n; ++j) t += a(i, j) * v[j];
+            pv[i] = beta * t;
+        }
+        for (int i = k + 1; i < n; ++i) vp += v[i] * pv[i];
+        const double kk = 0.5 * beta * vp;
+        for (int i = k; i < n; ++i) pv[i] -= kk * v[i];
+        for (int i = k; i < n; ++i)
+            for (int j = k; j < n; ++j) a(i, j) -= v[i] * pv[j] + pv[i] * v[j];
+        // Q <- Q (I - beta v v^T)
+        for (int i = 0; i < n; ++i) {
+            double t = 0.0;
+            for (int j = k + 1; j < n; ++j) t += Q[(size_t)i * n + j] * v[j];
+            t *= beta;
+            for (int j = k + 1; j < n; ++j) Q[(size_t)i * n + j] -= t * v[j];
+        }
+    }
+    for (int i = 0; i < n; ++i) d[i] = a(i, i);
+    for (int i = 0; i + 1 < n; ++i) e[i] = a(i + 1, i);
+    // implicit QL on (d, e); columns of Q follow the rotations
+    for (int l = 0; l < n; ++l) {
+        int iter = 0, m;
+        do {
+            for (m = l; m + 1 < n; ++m) {
+                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) + dd == dd) break;
+            }
+            if (m != l) {
+                if (++iter > 60) return false;
+                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+                double r = std::hypot(g, 1.0);
+                g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? std::fabs(r) : -std::fabs(r)));
+                double s = 1.0, c = 1.0, p = 0.0;
+                int i;
+                for (i = m - 1; i >= l; --i) {
+                    double f = s * e[i];
+                    const double b = c * e[i];
+                    r = std::hypot(f, g);
+                    e[i + 1] = r;
+                    if (r == 0.0) {
+                        d[i + 1] -= p;
+                        e[m] = 0.0;
+                        break;
+                    }
+                    s = f / r;
+                    c = g / r;
+                    g = d[i + 1] - p;
+                    r = (d[i] - g) * s + 2.0 * c * b;
+                    p = s * r;
+                    d[i + 1] = g + p;
+                    g = c * r - b;
+                    for (int k = 0; k < n; ++k) {
+                        double *zk = &Q[(size_t)k * n];
+                        f = zk[i + 1];
+                        zk[i + 1] = s * zk[i] + c * f;
+                        zk[i] = c * zk[i] - s * f;
+                    }
+                }
+                if (r == 0.0 && i >= l) continue;
+                d[l] -= p;
+                e[l] = g;
+                e[m] = 0.0;
+            }
+        } while (m != l);
+    }
+    for (double x : d)
+        if (!std::isfinite(x)) return false;
+    std::vector<int> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x] < d[y]; });
+    w.resize(n);
+    Z.assign((size_t)n * n, 0.0);
+    for (int c = 0; c < n; ++c) {
+        w[c] = d[ord[c]];
+        for (int k = 0; k < n; ++k) Z[(size_t)k * n + c] = Q[(size_t)k * n + ord[c]];
+    }
+    return true;
+}
+
+// Eigenpairs of a small symmetric matrix: tridiagonal QL, Jacobi as fallback.
+void small_sym_eig(int n, const std::vector<double> &A, std::vector<double> &w, std::vector<double> &Z) {
+    if (n >= 3 && tridiag_ql_eig(n, A, w, Z)) return;
+    jacobi_eig(n, A, w, Z);
+}
+
 // Orthonormal basis (modified Gram-Schmidt, twice) of the columns of the
 // m x q row-major matrix M; columns whose remaining norm falls below `drop`
 // times their original norm are dropped.  Returns m x qk row-major.
@@ -486,9 +543,14 @@ struct Solver {
     DBuf<int64_t> argi;
     DBuf<double> xfin, signbuf;
     int nblk_gram = 1;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> evs;  // start/stop pairs around every sigma product, read at the end
     double ms_sigma = 0.0;
     int sigma_blocks = 0, sigma_columns = 0;
+    // pinned staging ring for small host -> device uploads (no sync per upload)
+    static constexpr int SLOTS = 16;
+    static constexpr size_t SLOT_DOUBLES = 96 * 96;
+    double *pinned = nullptr;
+    int upload_count = 0;
 
     Solver(Ctx &cc, int k, int m_max) : c(cc), s(cc.stream), D(cc.ndet), K(k), mmax(m_max) {
         nblocks = (mmax + K - 1) / K;
@@ -509,12 +571,14 @@ struct Solver {
         HQ_CHECK(hipMemsetAsync(Wb.p, 0, sizeof(double) * bsz * nblocks, s));
         HQ_CHECK(hipMemsetAsync(T.p, 0, sizeof(double) * bsz, s));
         HQ_CHECK(hipMemsetAsync(Wn.p, 0, sizeof(double) * bsz, s));
-        HQ_CHECK(hipEventCreate(&ev0));
-        HQ_CHECK(hipEventCreate(&ev1));
+        HQ_CHECK(hipHostMalloc((void **)&pinned, sizeof(double) * SLOTS * SLOT_DOUBLES, hipHostMallocDefault));
     }
     ~Solver() {
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
+        if (pinned) {
+            (void)hipStreamSynchronize(s);
+            (void)hipHostFree(pinned);
+        }
+        for (auto e : evs) (void)hipEventDestroy(e);
     }
 
     // small.p regions: [0, 96*96) gram outputs / Y, [96*96, 2*96*96) coefficient uploads
@@ -533,32 +597,60 @@ struct Solver {
         return h;
     }
 
-    // Out[:, 0:nc] = beta Out + alpha A[:, 0:m] Bs (m x nc row-major, device)
+    // Out[:, 0:nc] = beta Out + alpha A[:, 0:m] Bs (m x nc row-major, device);
+    // A has K columns per block.
     void tsmm(Mat A, int m, const double *Bs, int nc, double alpha, double beta, Mat Out) {
         if (m <= 0 || nc <= 0) return;
         if (nc > 32) throw Error(HINQS_E_UNSUPPORTED, "tsmm width");
         if (m > 96) throw Error(HINQS_E_UNSUPPORTED, "tsmm depth");
-        if (A.kb > 16) throw Error(HINQS_E_UNSUPPORTED, "tsmm column block");
+        if (A.kb != K) throw Error(HINQS_E_UNSUPPORTED, "tsmm column block");
+        switch (K) {
+            case 1: tsmm_k<1>(A, m, Bs, nc, alpha, beta, Out); break;
+            case 2: tsmm_k<2>(A, m, Bs, nc, alpha, beta, Out); break;
+            case 4: tsmm_k<4>(A, m, Bs, nc, alpha, beta, Out); break;
+            case 8: tsmm_k<8>(A, m, Bs, nc, alpha, beta, Out); break;
+            default: tsmm_k<16>(A, m, Bs, nc, alpha, beta, Out); break;
+        }
+    }
+    template <int KB>
+    void tsmm_k(Mat A, int m, const double *Bs, int nc, double alpha, double beta, Mat Out) {
+        constexpr int RPB = 256 / RowLanes<KB>::LPN;
+        const unsigned grid = (unsigned)std::min<int64_t>((D + RPB - 1) / RPB, 2048);
         const int NC = nc <= 1 ? 1 : nc <= 2 ? 2 : nc <= 4 ? 4 : nc <= 8 ? 8 : nc <= 16 ? 16 : 32;
-        const int rows = 256 / NC;
-        const int64_t tiles = (D + rows - 1) / rows;
-        const unsigned grid = (unsigned)std::min<int64_t>(tiles, 4096);
         dim3 g(grid), b(256);
         switch (NC) {
-            case 1: hipLaunchKernelGGL(k_tsmm<1>, g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
-            case 2: hipLaunchKernelGGL(k_tsmm<2>, g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
-            case 4: hipLaunchKernelGGL(k_tsmm<4>, g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
-            case 8: hipLaunchKernelGGL(k_tsmm<8>, g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
-            case 16: hipLaunchKernelGGL(k_tsmm<16>, g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
-            default: hipLaunchKernelGGL(k_tsmm<32>, g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
+            case 1: hipLaunchKernelGGL((k_tsmm<KB, 1>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
+            case 2: hipLaunchKernelGGL((k_tsmm<KB, 2>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
+            case 4: hipLaunchKernelGGL((k_tsmm<KB, 4>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
+            case 8: hipLaunchKernelGGL((k_tsmm<KB, 8>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
+            case 16: hipLaunchKernelGGL((k_tsmm<KB, 16>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
+            default: hipLaunchKernelGGL((k_tsmm<KB, 32>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
         }
         HQ_LAUNCH_CHECK();
     }
 
-    // Synchronous so the host vector may be released on return.
+    // Copied through a pinned staging slot, so the host vector may be released
+    // on return without waiting; a slot is reused only after SLOTS further
+    // uploads, and every SLOTS-th upload waits for the stream first.
     void upload_small(const std::vector<double> &h, double *dst) {
-        HQ_CHECK(hipMemcpyAsync(dst, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, s));
-        HQ_CHECK(hipStreamSynchronize(s));
+        if (h.size() > SLOT_DOUBLES) throw Error(HINQS_E_UNSUPPORTED, "small upload too large");
+        if (++upload_count % SLOTS == 0) HQ_CHECK(hipStreamSynchronize(s));
+        double *slot = pinned + (size_t)(upload_count % SLOTS) * SLOT_DOUBLES;
+        std::copy(h.begin(), h.end(), slot);
+        HQ_CHECK(hipMemcpyAsync(dst, slot, sizeof(double) * h.size(), hipMemcpyHostToDevice, s));
+    }
+
+    // Sum of the sigma launch times recorded so far (waits for the last one).
+    void collect_sigma_times() {
+        if (evs.empty()) return;
+        HQ_CHECK(hipEventSynchronize(evs.back()));
+        for (size_t i = 0; i + 1 < evs.size(); i += 2) {
+            float ms = 0.f;
+            HQ_CHECK(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));
+            ms_sigma += ms;
+        }
+        for (auto e : evs) (void)hipEventDestroy(e);
+        evs.clear();
     }
 
     void put_columns(const double *src, int nc, Mat dst, int c0) {
@@ -569,7 +661,12 @@ struct Solver {
 
     // Wn = H X for a contiguous ndet x K block X (columns >= nc are zero).
     void apply_h(const double *X, int nc, bool fp32) {
-        HQ_CHECK(hipEventRecord(ev0, s));
+        hipEvent_t e0, e1;
+        HQ_CHECK(hipEventCreate(&e0));
+        evs.push_back(e0);
+        HQ_CHECK(hipEventCreate(&e1));
+        evs.push_back(e1);
+        HQ_CHECK(hipEventRecord(e0, s));
         if (!fp32) {
             sigma_sorted(c, K, X, K, Wn.p, K, HINQS_FP64, s);
         } else {
@@ -582,11 +679,7 @@ struct Solver {
             hipLaunchKernelGGL(k_to_f64, dim3(grid_for(n, 256)), dim3(256), 0, s, n, S32.p, Wn.p);
             HQ_LAUNCH_CHECK();
         }
-        HQ_CHECK(hipEventRecord(ev1, s));
-        HQ_CHECK(hipEventSynchronize(ev1));
-        float ms = 0.f;
-        HQ_CHECK(hipEventElapsedTime(&ms, ev0, ev1));
-        ms_sigma += ms;
+        HQ_CHECK(hipEventRecord(e1, s));
         ++sigma_blocks;
         sigma_columns += nc;
     }
@@ -638,7 +731,7 @@ struct Solver {
                     g[(size_t)a * kept + b] = g[(size_t)b * kept + a] = v;
                 }
             std::vector<double> w, Z;
-            jacobi_eig(kept, g, w, Z);
+            small_sym_eig(kept, g, w, Z);
             const double thresh = round == 0 ? 1e-14 : 1e-4;
             std::vector<int> keep;
             for (int j = kept - 1; j >= 0; --j)  // largest first
@@ -819,7 +912,7 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
         for (int a = 0; a < m; ++a)
             for (int b = 0; b < m; ++b) Gm[(size_t)a * m + b] = G[(size_t)a * 96 + b];
         std::vector<double> w, Z;
-        jacobi_eig(m, Gm, w, Z);
+        small_sym_eig(m, Gm, w, Z);
         nroots_eff = std::min(kroots, m);
         theta.assign(K, 0.0);
         Y.assign((size_t)m * K, 0.0);
@@ -957,6 +1050,7 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
         st->sigma_columns = S.sigma_columns;
         st->restarts = restarts;
         st->residual = res0;
+        S.collect_sigma_times();
         st->ms_sigma = S.ms_sigma;
         st->nnz = c.nnz;
         st->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
