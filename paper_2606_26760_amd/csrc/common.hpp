@@ -292,8 +292,13 @@ void sigma_sorted(Ctx &c, int k, const void *X, int ldx, void *S, int lds, int p
 // Time the candidate launch shapes on c's couplings, keep the fastest in c
 // (and in a process-wide cache keyed by problem shape).  Returns it.
 SigmaCfg autotune_sigma(Ctx &c, int k, int precision);
-// Shape the next sigma launch will use for (k, precision).
+// Shape the next sigma launch will use for (k, precision), and the shape
+// used before any tuning.
 SigmaCfg sigma_config(const Ctx &c, int k, int precision);
+SigmaCfg default_cfg(const Ctx &c, int k, int precision);
+// S = H X in sorted order with an explicit launch shape.
+void sigma_launch(const Ctx &c, int k, int precision, const SigmaCfg &cfg, const void *X, int ldx, void *S,
+                  int lds, hipStream_t s);
 // FP64 sigma over the rows that mk leaves live (X, S with leading dimension k).
 void sigma_masked_fp64(const Ctx &c, int k, const double *X, double *S, const SigmaMask &mk, hipStream_t s);
 

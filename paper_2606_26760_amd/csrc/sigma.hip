@@ -18,10 +18,6 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
-#include <fstream>
-#include <map>
-#include <mutex>
-#include <string>
 
 #include "common.hpp"
 
@@ -456,6 +452,9 @@ void dispatch_k(const Ctx &c, int k, const SigmaCfg &cfg, const T *val, const T 
     }
 }
 
+
+}  // namespace
+
 // Default shape before tuning: team sized to about four unrolled steps per mean row.
 SigmaCfg default_cfg(const Ctx &c, int k, int precision) {
     const int vw = precision == HINQS_FP64 ? 2 : 4;
@@ -468,43 +467,6 @@ SigmaCfg default_cfg(const Ctx &c, int k, int precision) {
     g.occ = 4;
     return g;
 }
-
-// Process-wide cache of tuned shapes keyed by (device arch, precision, k, problem-size bucket).
-std::mutex g_tune_mutex;
-std::map<std::string, SigmaCfg> g_tune_cache;
-
-std::string tune_key(const Ctx &c, int k, int precision) {
-    hipDeviceProp_t prop;
-    std::string arch = "gpu";
-    if (hipGetDeviceProperties(&prop, c.device) == hipSuccess) arch = prop.gcnArchName;
-    const int dbucket = c.ndet > 0 ? (int)std::lround(2.0 * std::log2((double)c.ndet)) : 0;
-    const int nbucket = c.ndet > 0 ? (int)std::lround((double)c.nnz / (double)c.ndet / 16.0) : 0;
-    return arch + "|p" + std::to_string(precision) + "|k" + std::to_string(k) + "|d" + std::to_string(dbucket) +
-           "|n" + std::to_string(nbucket);
-}
-
-void load_tune_file() {
-    static bool loaded = false;
-    if (loaded) return;
-    loaded = true;
-    const char *path = std::getenv("HINQS_TUNE_CACHE");
-    if (!path || !*path) return;
-    std::ifstream f(path);
-    std::string key;
-    SigmaCfg g;
-    while (f >> key >> g.team >> g.unr >> g.occ >> g.pipe >> g.ms) g_tune_cache[key] = g;
-}
-
-void store_tune_file() {
-    const char *path = std::getenv("HINQS_TUNE_CACHE");
-    if (!path || !*path) return;
-    std::ofstream f(path, std::ios::trunc);
-    for (const auto &kv : g_tune_cache)
-        f << kv.first << " " << kv.second.team << " " << kv.second.unr << " " << kv.second.occ << " "
-          << kv.second.pipe << " " << kv.second.ms << "\n";
-}
-
-}  // namespace
 
 SigmaCfg sigma_config(const Ctx &c, int k, int precision) {
     SigmaCfg g = c.sigma_cfg[precision == HINQS_FP64 ? 0 : 1][kindex(k)];
@@ -537,78 +499,15 @@ void sigma_masked_fp64(const Ctx &c, int k, const double *X, double *S, const Si
     dispatch_k<double, true>(c, k, cfg, c.val.p, c.diag.p, X, k, S, k, s, mk);
 }
 
-SigmaCfg autotune_sigma(Ctx &c, int k, int precision) {
+void sigma_launch(const Ctx &c, int k, int precision, const SigmaCfg &cfg, const void *X, int ldx, void *S,
+                  int lds, hipStream_t s) {
     if (!c.have_elements) throw Error(HINQS_E_NOT_READY, "matrix elements are not built");
-    if (precision != HINQS_FP64 && precision != HINQS_FP32)
+    if (precision == HINQS_FP64)
+        dispatch_k<double>(c, k, cfg, c.val.p, c.diag.p, (const double *)X, ldx, (double *)S, lds, s);
+    else if (precision == HINQS_FP32)
+        dispatch_k<float>(c, k, cfg, c.val32.p, c.diag32.p, (const float *)X, ldx, (float *)S, lds, s);
+    else
         throw Error(HINQS_E_INVALID_ARG, "precision must be HINQS_FP64 or HINQS_FP32");
-    const int K = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
-    SigmaCfg &slot = c.sigma_cfg[precision == HINQS_FP64 ? 0 : 1][kindex(K)];
-    const std::string key = tune_key(c, K, precision);
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mutex);
-        load_tune_file();
-        auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
-            slot = it->second;
-            return slot;
-        }
-    }
-    hipStream_t s = c.stream;
-    const size_t esz = precision == HINQS_FP64 ? 8 : 4;
-    DBuf<char> X, S;
-    X.ensure((size_t)c.ndet * K * esz);
-    S.ensure((size_t)c.ndet * K * esz);
-    HQ_CHECK(hipMemsetAsync(X.p, 0, (size_t)c.ndet * K * esz, s));
-    hipEvent_t e0, e1;
-    HQ_CHECK(hipEventCreate(&e0));
-    HQ_CHECK(hipEventCreate(&e1));
-    const int vw = precision == HINQS_FP64 ? 2 : 4;
-    const int lpn = K >= vw ? K / vw : 1;
-    const bool verbose = env_int("HINQS_VERBOSE", 0) != 0;
-    SigmaCfg best;
-    best.ms = 1e30;
-    const int teams[] = {16, 32, 64};
-    const int unrs[] = {2, 4};
-    const int occs[] = {2, 4, 8};
-    for (int pipe = 0; pipe < 2; ++pipe)
-    for (int team : teams) {
-        if (team < 4 * lpn) continue;
-        for (int unr : unrs)
-            for (int occ : occs) {
-                SigmaCfg g;
-                g.team = team;
-                g.unr = unr;
-                g.occ = occ;
-                g.pipe = pipe;
-                auto run = [&]() {
-                    if (precision == HINQS_FP64)
-                        dispatch_k<double>(c, K, g, c.val.p, c.diag.p, (const double *)X.p, K, (double *)S.p, K, s);
-                    else
-                        dispatch_k<float>(c, K, g, c.val32.p, c.diag32.p, (const float *)X.p, K, (float *)S.p, K, s);
-                };
-                run();
-                HQ_CHECK(hipEventRecord(e0, s));
-                for (int r = 0; r < 3; ++r) run();
-                HQ_CHECK(hipEventRecord(e1, s));
-                HQ_CHECK(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HQ_CHECK(hipEventElapsedTime(&ms, e0, e1));
-                g.ms = ms / 3.0;
-                if (verbose)
-                    std::fprintf(stderr, "[hinqs] tune k=%d p=%d pipe %d team %d unr %d occ %d: %.4f ms\n", K,
-                                 precision, pipe, team, unr, occ, g.ms);
-                if (g.ms < best.ms) best = g;
-            }
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    slot = best;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mutex);
-        g_tune_cache[key] = best;
-        store_tune_file();
-    }
-    return best;
 }
 
 }  // namespace hinqs
