@@ -342,3 +342,21 @@ def test_autotune_then_solve():
     e, c, st = s.lowest_eigenpair(tol=1e-9, autotune=True, mixed=True)
     e_ref, _ = o.lowest_eigenpair()
     assert abs(e - e_ref) <= 1e-8
+
+
+@pytest.mark.parametrize("block,max_space,mixed", [(1, 8, False), (2, 12, False), (4, 24, False),
+                                                   (16, 96, False), (16, 48, False), (4, 12, True)])
+def test_eigenpair_every_block_size(block, max_space, mixed):
+    """Every block size and subspace limit reaches the dense eigenpair (the
+    tall-skinny kernels are compiled per block size)."""
+    ints, a, b, cfg = W.config_inputs(1, ndet=3000)
+    log(f"davidson block={block} max_space={max_space} mixed={mixed}")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    o = oracle_for(ints, a, b, cfg.na, cfg.nb)
+    e_ref, c_ref = o.lowest_eigenpair()
+    e, c, st = s.lowest_eigenpair(tol=1e-9, block=block, max_space=max_space, mixed=mixed, max_iter=600)
+    assert abs(e - e_ref) <= (1e-8 if mixed else 1e-10)
+    w = o.spectrum(2)
+    if w[1] - w[0] > 1e-6:
+        assert abs(np.dot(c.cpu().numpy(), c_ref)) >= 1 - 1e-9
+    assert st["restarts"] >= 1 or st["iterations"] * block < max_space
