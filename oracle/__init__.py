@@ -10,6 +10,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
   (paper Sec. 2.2, the Hamiltonian before Step 1, and Step 3), the sigma
   product H_B X, the excitation class and canonical sign of every coupled
   pair, and the one- and two-particle density matrices.
+* The selection steps around Step 3 (Sec. 2.2, Steps 1' and 2): the classical
+  expansion of Eq. 2 and the PT2 importance of Eq. 3, from the same operator
+  application extended to determinants outside B.
 * The lowest eigenpair (Step 3, "diagonalized with a Davidson eigensolver")
   is taken from LAPACK ``eigh`` on the dense matrix, or ARPACK ``eigsh`` on
   the sparse one for larger sets -- a library primitive standing in for the
@@ -69,6 +72,9 @@ def _load():
             lib.or_rdm12.argtypes = [P, P, P, P]
             lib.or_rdm2_elements.argtypes = [P, P, i64, P, P]
             lib.or_num_threads.restype = ctypes.c_int
+            lib.or_pt2.argtypes = [P, P, ctypes.c_double, i64, P, P, P, P, P]
+            lib.or_expand.restype = i64
+            lib.or_expand.argtypes = [P, P, i64, P, i64, P, P]
             _lib = lib
     return _lib
 
@@ -212,3 +218,33 @@ class Oracle:
         out = np.empty(len(idx))
         lib.or_rdm2_elements(self._h, _ptr(c), len(idx), _ptr(idx), _ptr(out))
         return out
+
+    # ------------------------------------------------ selection (Eq. 2, Eq. 3)
+    def pt2(self, c, e0, cand_alpha, cand_beta):
+        """(numerator <x|H|Psi_0>, H_xx, score) of each candidate determinant (Eq. 3);
+        c in caller order."""
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        ca = np.ascontiguousarray(cand_alpha, dtype=np.uint64)
+        cb = np.ascontiguousarray(cand_beta, dtype=np.uint64)
+        n = len(ca)
+        num = np.zeros(n)
+        hxx = np.zeros(n)
+        score = np.zeros(n)
+        _load().or_pt2(self._h, _ptr(c), float(e0), n, _ptr(ca), _ptr(cb), _ptr(num), _ptr(hxx),
+                       _ptr(score))
+        return num, hxx, score
+
+    def expand(self, c, ntop):
+        """Classical expansion (Eq. 2): (alpha, beta) of every determinant outside B
+        coupled to one of the ntop largest-|c| determinants, ascending (alpha, beta),
+        and the caller indices of those ntop determinants."""
+        lib = _load()
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        ntop = int(min(ntop, self.ndet))
+        top = np.zeros(max(ntop, 1), dtype=np.int32)
+        z = np.zeros(1, dtype=np.uint64)
+        n = lib.or_expand(self._h, _ptr(c), ntop, _ptr(top), 0, _ptr(z), _ptr(z))
+        out_a = np.zeros(max(n, 1), dtype=np.uint64)
+        out_b = np.zeros(max(n, 1), dtype=np.uint64)
+        lib.or_expand(self._h, _ptr(c), ntop, _ptr(top), n, _ptr(out_a), _ptr(out_b))
+        return out_a[:n], out_b[:n], top[:ntop]

@@ -23,6 +23,13 @@
  * [H_B]_ij = <x_i|H|x_j> (Step 3) are read off the expansion of H|x_j> in the
  * determinants of B, looked up in a hash map.  No Slater-Condon rule is used.
  *
+ * Selection steps around Step 3 (paper Sec. 2.2, Steps 1' and 2), from the
+ * expansion of H|x> over all determinants, not only those of B:
+ *   classical expansion (Eq. 2): every y not in B with <y|H|x> != 0 for some
+ *     x among the n_top determinants of B with the largest |c_i|;
+ *   PT2 importance (Eq. 3): s(x) = |<x|H|Psi_0>|^2 / |E_0 - H_xx| with
+ *     <x|H|Psi_0> = sum_i c_i <x|H|x_i>.
+ *
  * Reduced density matrices (used as dE/dh and dE/d(pq|rs)):
  *   rdm1[p,q]     = sum_s     <c| a+_{p s} a_{q s} |c>
  *   rdm2[p,q,r,s] = sum_{s t} <c| a+_{p s} a+_{r t} a_{s t} a_{q s} |c>
@@ -273,6 +280,210 @@ static void scratch_free(scratch_t *w)
 
 /* Difference between x_i (bra) and x_j (ket): holes are spin-orbitals occupied in
  * x_j and empty in x_i, particles the reverse.  Returns the number of holes. */
+/* ------------------------------------------- H applied to any determinant */
+
+/* Amplitudes of H|x> keyed by determinant (open addressing), insertion order kept. */
+typedef struct {
+    int64_t cap;
+    uint64_t *key;
+    double *amp;
+    int8_t *used;
+    int64_t *order;
+    int64_t n;
+} ampmap_t;
+
+static ampmap_t *ampmap_new(int64_t want)
+{
+    ampmap_t *m = (ampmap_t *)malloc(sizeof(ampmap_t));
+    m->cap = 1;
+    while (m->cap < 2 * want + 2) m->cap <<= 1;
+    m->key = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)m->cap);
+    m->amp = (double *)malloc(sizeof(double) * (size_t)m->cap);
+    m->used = (int8_t *)calloc((size_t)m->cap, 1);
+    m->order = (int64_t *)malloc(sizeof(int64_t) * (size_t)m->cap);
+    m->n = 0;
+    return m;
+}
+
+static void ampmap_free(ampmap_t *m)
+{
+    free(m->key); free(m->amp); free(m->used); free(m->order); free(m);
+}
+
+static void ampmap_clear(ampmap_t *m)
+{
+    for (int64_t k = 0; k < m->n; ++k) m->used[m->order[k]] = 0;
+    m->n = 0;
+}
+
+static void ampmap_add(ampmap_t *m, uint64_t y, double v)
+{
+    uint64_t mask = (uint64_t)m->cap - 1;
+    uint64_t s = mix64(y) & mask;
+    while (m->used[s] && m->key[s] != y) s = (s + 1) & mask;
+    if (!m->used[s]) {
+        m->used[s] = 1;
+        m->key[s] = y;
+        m->amp[s] = 0.0;
+        m->order[m->n++] = (int64_t)s;
+    }
+    m->amp[s] += v;
+}
+
+/* Number of determinants H|x> can reach (x itself, singles, doubles): the map size. */
+static int64_t reach_bound(const oracle_t *o)
+{
+    int64_t n = o->norb, a = o->na, b = o->nb;
+    int64_t sa = a * (n - a), sb = b * (n - b);
+    int64_t daa = (a * (a - 1) / 2) * ((n - a) * (n - a - 1) / 2);
+    int64_t dbb = (b * (b - 1) / 2) * ((n - b) * (n - b - 1) / 2);
+    return 1 + sa + sb + daa + dbb + sa * sb;
+}
+
+/* Expand H|x> over all determinants: afterwards m holds <y|H|x> for every y
+ * some term of H produces from x (the same operator-by-operator rules as
+ * apply_h, without the restriction to B). */
+static void expand_h(const oracle_t *o, uint64_t x, ampmap_t *m)
+{
+    const int n = o->norb, n2 = 2 * n;
+    ampmap_clear(m);
+    ampmap_add(m, x, o->ecore);
+    for (int Q = 0; Q < n2; ++Q) {
+        uint64_t y1 = x;
+        int s1 = annihilate(&y1, Q);
+        if (!s1) continue;
+        for (int P = 0; P < n2; ++P) {
+            if ((P < n) != (Q < n)) continue;
+            uint64_t y2 = y1;
+            int s2 = create(&y2, P);
+            if (!s2) continue;
+            ampmap_add(m, y2, s1 * s2 * o->h[(P % n) * n + (Q % n)]);
+        }
+    }
+    for (int R = 0; R < n2; ++R) {
+        uint64_t y1 = x;
+        int s1 = annihilate(&y1, R);
+        if (!s1) continue;
+        for (int S = 0; S < n2; ++S) {
+            uint64_t y2 = y1;
+            int s2 = annihilate(&y2, S);
+            if (!s2) continue;
+            for (int Q = 0; Q < n2; ++Q) {
+                if ((Q < n) != (S < n)) continue;
+                uint64_t y3 = y2;
+                int s3 = create(&y3, Q);
+                if (!s3) continue;
+                for (int P = 0; P < n2; ++P) {
+                    if ((P < n) != (R < n)) continue;
+                    uint64_t y4 = y3;
+                    int s4 = create(&y4, P);
+                    if (!s4) continue;
+                    ampmap_add(m, y4, 0.5 * s1 * s2 * s3 * s4 * eri_at(o, P % n, R % n, Q % n, S % n));
+                }
+            }
+        }
+    }
+}
+
+/*
+ * PT2 importance of candidate determinants (Eq. 3): for each (alpha, beta)
+ * the numerator <x|H|Psi_0> = sum_i c_i <x_i|H|x> (c in caller order; the
+ * diagonal term is included when x lies in B), the diagonal element H_xx and
+ * the score numer^2 / |e0 - H_xx| (IEEE division).
+ */
+void or_pt2(void *handle, const double *c, double e0, int64_t ncand, const uint64_t *ca,
+            const uint64_t *cb, double *numer, double *hxx, double *score)
+{
+    const oracle_t *o = (const oracle_t *)handle;
+    const int64_t bound = reach_bound(o);
+#pragma omp parallel
+    {
+        ampmap_t *m = ampmap_new(bound);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t t = 0; t < ncand; ++t) {
+            const uint64_t x = ca[t] | (cb[t] << o->norb);
+            expand_h(o, x, m);
+            double num = 0.0, d = 0.0;
+            for (int64_t k = 0; k < m->n; ++k) {
+                const int64_t s = m->order[k];
+                if (m->key[s] == x) d = m->amp[s];
+                const int64_t j = lookup(o, m->key[s]);
+                if (j >= 0) num += c[j] * m->amp[s];
+            }
+            numer[t] = num;
+            hxx[t] = d;
+            score[t] = num * num / fabs(e0 - d);
+        }
+        ampmap_free(m);
+    }
+}
+
+typedef struct {
+    double mag;
+    int64_t idx;
+} magidx_t;
+
+static int cmp_mag_desc(const void *a, const void *b)
+{
+    const magidx_t *x = (const magidx_t *)a, *y = (const magidx_t *)b;
+    if (x->mag > y->mag) return -1;
+    if (x->mag < y->mag) return 1;
+    return x->idx < y->idx ? -1 : (x->idx > y->idx ? 1 : 0);
+}
+
+static int cmp_u64(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/*
+ * Classical expansion (Eq. 2).  top[0..ntop) receives the caller indices of
+ * the ntop determinants with the largest |c_i| (ties: lower index first).
+ * The distinct y not in B with <y|H|x> != 0 for some chosen x are written
+ * in ascending (alpha, beta) order, at most cap of them; returns how many
+ * there are.
+ */
+int64_t or_expand(void *handle, const double *c, int64_t ntop, int32_t *top, int64_t cap, uint64_t *out_a,
+                  uint64_t *out_b)
+{
+    const oracle_t *o = (const oracle_t *)handle;
+    if (ntop > o->ndet) ntop = o->ndet;
+    magidx_t *mi = (magidx_t *)malloc(sizeof(magidx_t) * (size_t)(o->ndet > 0 ? o->ndet : 1));
+    for (int64_t i = 0; i < o->ndet; ++i) {
+        mi[i].mag = fabs(c[i]);
+        mi[i].idx = i;
+    }
+    qsort(mi, (size_t)o->ndet, sizeof(magidx_t), cmp_mag_desc);
+    for (int64_t t = 0; t < ntop; ++t) top[t] = (int32_t)mi[t].idx;
+    const int64_t bound = reach_bound(o);
+    const uint64_t lowmask = ((uint64_t)1 << o->norb) - 1;
+    uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(ntop * bound + 1));
+    int64_t nk = 0;
+    ampmap_t *m = ampmap_new(bound);
+    for (int64_t t = 0; t < ntop; ++t) {
+        expand_h(o, o->x[mi[t].idx], m);
+        for (int64_t k = 0; k < m->n; ++k) {
+            const int64_t s = m->order[k];
+            if (m->amp[s] == 0.0 || lookup(o, m->key[s]) >= 0) continue;
+            const uint64_t y = m->key[s];
+            keys[nk++] = ((y & lowmask) << o->norb) | (y >> o->norb);  /* (alpha, beta) order */
+        }
+    }
+    ampmap_free(m);
+    qsort(keys, (size_t)nk, sizeof(uint64_t), cmp_u64);
+    int64_t nu = 0;
+    for (int64_t k = 0; k < nk; ++k)
+        if (nu == 0 || keys[k] != keys[nu - 1]) keys[nu++] = keys[k];
+    for (int64_t k = 0; k < nu && k < cap; ++k) {
+        out_a[k] = keys[k] >> o->norb;
+        out_b[k] = keys[k] & lowmask;
+    }
+    free(keys);
+    free(mi);
+    return nu;
+}
+
 static int differences(const oracle_t *o, uint64_t xi, uint64_t xj, int *holes, int *parts)
 {
     int nh = 0, np_ = 0;

@@ -1,0 +1,113 @@
+"""Pins of the oracle's selection steps (paper Sec. 2.2, Steps 1' and 2): the
+classical expansion of Eq. 2 and the PT2 importance of Eq. 3, checked against
+an independent Jordan-Wigner construction of the Fock-space Hamiltonian, a
+closed form and a combinatorial count."""
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import jw
+
+
+def _small_case(norb=5, na=2, nb=2, nB=35, seed=11):
+    ints = W.gen_integrals(norb, norb, -2.0, -0.5, 300 + seed)
+    fa, fb = W.full_space(norb, na, nb)
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(len(fa), nB, replace=False)
+    a, b = fa[pick], fb[pick]
+    c = rng.standard_normal(nB)
+    c /= np.linalg.norm(c)
+    return ints, fa, fb, a, b, c
+
+
+def test_pt2_matches_jordan_wigner():
+    ints, fa, fb, a, b, c = _small_case()
+    o = oracle.Oracle(ints.norb, 2, 2, ints.h, ints.eri, ints.e_core, a, b)
+    H = jw.hamiltonian(ints.h, ints.eri, ints.e_core)
+    iB = jw.basis_index(a, b, ints.norb)
+    ix = jw.basis_index(fa, fb, ints.norb)
+    e0 = -3.25
+    num, hxx, score = o.pt2(c, e0, fa, fb)
+    num_ref = H[ix][:, iB] @ c
+    hxx_ref = H[ix, ix].A1 if hasattr(H[ix, ix], "A1") else np.asarray(H[ix, ix]).ravel()
+    scale = np.abs(H[ix][:, iB]).toarray() @ np.abs(c) + 1e-300
+    assert np.all(np.abs(num - num_ref) <= 1e-12 * scale + 1e-15)
+    assert np.allclose(hxx, hxx_ref, rtol=0, atol=1e-12)
+    assert np.allclose(score, num_ref ** 2 / np.abs(e0 - hxx_ref), rtol=1e-11, atol=1e-15)
+    # a member of B: the numerator is the row of H_B c, diagonal included
+    HB = jw.projected(ints.h, ints.eri, ints.e_core, a, b)
+    nB, hB, _ = o.pt2(c, e0, a, b)
+    assert np.allclose(nB, HB @ c, rtol=0, atol=1e-12)
+    assert np.allclose(hB, np.diag(HB), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("ntop", [1, 4, 35])
+def test_expand_matches_jordan_wigner(ntop):
+    ints, fa, fb, a, b, c = _small_case()
+    o = oracle.Oracle(ints.norb, 2, 2, ints.h, ints.eri, ints.e_core, a, b)
+    ya, yb, top = o.expand(c, ntop)
+    order = sorted(range(len(c)), key=lambda i: (-abs(c[i]), i))
+    assert list(top) == order[:ntop]
+    H = jw.hamiltonian(ints.h, ints.eri, ints.e_core).tocsc()
+    inB = set(jw.basis_index(a, b, ints.norb).tolist())
+    ref = set()
+    for i in order[:ntop]:
+        col = H[:, int(jw.basis_index(a[i:i + 1], b[i:i + 1], ints.norb)[0])]
+        for y, v in zip(col.indices, col.data):
+            if abs(v) > 1e-12 and y not in inB:
+                ref.add(int(y))
+    lo = (1 << ints.norb) - 1
+    got = [(int(x), int(y)) for x, y in zip(ya, yb)]
+    assert got == sorted(got)                       # ascending (alpha, beta)
+    assert len(set(got)) == len(got)                # distinct
+    assert {al | (be << ints.norb) for al, be in got} == ref
+    assert all((k & lo).bit_count() == 2 and (k >> ints.norb).bit_count() == 2 for k in ref)
+
+
+def test_expand_reaches_every_single_and_double():
+    """One determinant in B: the expansion is every single and double excitation
+    of it (generic integrals make every Slater-Condon element nonzero)."""
+    for norb, na, nb in ((6, 3, 3), (7, 4, 2), (5, 1, 3)):
+        ints = W.gen_integrals(norb, norb, -2.0, -0.5, 40 + norb)
+        a = np.array([(1 << na) - 1], dtype=np.uint64)
+        b = np.array([(1 << nb) - 1], dtype=np.uint64)
+        o = oracle.Oracle(norb, na, nb, ints.h, ints.eri, ints.e_core, a, b)
+        ya, yb, top = o.expand(np.array([1.0]), 1)
+        sa, sb = na * (norb - na), nb * (norb - nb)
+        n = sa + sb + comb(na, 2) * comb(norb - na, 2) + comb(nb, 2) * comb(norb - nb, 2) + sa * sb
+        assert len(ya) == n
+
+
+def test_diagonal_hamiltonian_closed_form():
+    """eri = 0 and diagonal h: H is diagonal, so nothing couples out of B, every
+    outside numerator is 0 and H_xx = E_core + sum of the occupied h_pp."""
+    norb, na, nb = 5, 2, 2
+    hd = np.array([-1.0, -0.7, 0.2, 0.5, 1.1])
+    h = np.diag(hd)
+    eri = np.zeros((norb,) * 4)
+    fa, fb = W.full_space(norb, na, nb)
+    a, b = fa[:10], fb[:10]
+    o = oracle.Oracle(norb, na, nb, h, eri, 0.25, a, b)
+    c = np.linspace(1.0, 2.0, 10)
+    ya, yb, _ = o.expand(c, 10)
+    assert len(ya) == 0
+    num, hxx, _ = o.pt2(c, -1.0, fa, fb)
+    occ = lambda s: [p for p in range(norb) if (int(s) >> p) & 1]
+    ref = np.array([0.25 + hd[occ(x)].sum() + hd[occ(y)].sum() for x, y in zip(fa, fb)])
+    assert np.allclose(hxx, ref, atol=1e-14)
+    assert np.allclose(num[:10], c * ref[:10], atol=1e-14)
+    assert np.all(num[10:] == 0.0)
+
+
+def test_expand_ties_prefer_lower_index():
+    ints, fa, fb, a, b, c = _small_case()
+    o = oracle.Oracle(ints.norb, 2, 2, ints.h, ints.eri, ints.e_core, a, b)
+    cc = np.zeros(len(c))
+    cc[[3, 7, 9, 12, 15, 20]] = [0.5, -0.5, 0.5, -0.5, 0.5, 0.25]
+    _, _, top = o.expand(cc, 3)
+    assert list(top) == [3, 7, 9]
+    _, _, top = o.expand(cc, 6)
+    assert list(top) == [3, 7, 9, 12, 15, 20]
