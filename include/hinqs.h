@@ -63,6 +63,7 @@ extern "C" {
 #define HINQS_SORTED_ORDER 1   /* vectors are in the library's internal sorted order */
 #define HINQS_AUTOTUNE     2   /* hinqs_opts.flags: tune the sigma launch shape before solving */
 #define HINQS_NO_GRAPH     4   /* hinqs_opts.flags, batched solves: launch each kernel directly */
+#define HINQS_LARGEST      8   /* hinqs_top_k: select the largest values instead of the smallest */
 
 /* excitation classes stored in a coupling descriptor (bits 0..2) */
 #define HINQS_EXC_1A   1   /* single, alpha */
@@ -321,6 +322,72 @@ int hinqs_batch_info(hinqs_ctx *ctx, int *ninst, int64_t *offsets, int64_t *nnz)
 int hinqs_batch_lowest_eigenpair(hinqs_ctx *ctx, const hinqs_opts *opts, double *energies,
                                  double *coeffs, int *status, int *iterations,
                                  hinqs_batch_stats *stats);
+
+/*
+ * Classical expansion of the determinant set (paper Sec. 2.2, Eq. 2): the
+ * ntop determinants of B with the largest |c_i| are chosen (ties: the lower
+ * index first; ntop is clamped to ndet), and every determinant y outside B
+ * with <y|H|x> != 0 for at least one chosen x is returned once, in ascending
+ * (alpha, beta) order (alpha compared first).  A connection is an element
+ * whose computed Slater-Condon value is not exactly zero; every single and
+ * double excitation of x is examined, so the result holds at most
+ * ntop * (singles + doubles per determinant) entries.
+ *   coeffs     device, ndet doubles (caller order unless HINQS_SORTED_ORDER);
+ *              NaN or Inf gives NONFINITE
+ *   ntop       >= 1
+ *   capacity   entries available in out_alpha / out_beta (>= 0); the first
+ *              min(capacity, *count) determinants are written
+ *   out_alpha, out_beta  device, capacity uint64 each (may be NULL when
+ *              capacity is 0)
+ *   count      host, receives the number of distinct determinants found
+ *   top        device, ntop int32, or NULL: the chosen determinants, largest
+ *              |c| first (caller indices, or sorted positions with
+ *              HINQS_SORTED_ORDER)
+ * Device scratch of about 12 bytes per determinant of B plus 20 bytes per
+ * examined excitation is allocated for the call.  Needs integrals and
+ * determinants.
+ * Errors: NOT_READY, INVALID_ARG, NONFINITE, UNSUPPORTED (2^31 or more
+ * examined excitations: expand fewer determinants per call), OOM, HIP.
+ */
+int hinqs_expand(hinqs_ctx *ctx, const double *coeffs, int64_t ntop, int64_t capacity,
+                 uint64_t *out_alpha, uint64_t *out_beta, int64_t *count, int32_t *top, int flags);
+
+/*
+ * Second-order (Epstein-Nesbet) importance of candidate determinants
+ * (paper Sec. 2.2, Eq. 3) against Psi_0 = sum_i c_i |x_i> over B:
+ *   numer[t] = sum_i c_i <x_t|H|x_i>   (the diagonal term is included when
+ *                                      x_t lies in B)
+ *   hxx[t]   = <x_t|H|x_t>            (including e_core)
+ *   score[t] = numer[t]^2 / |e0 - hxx[t]|   (IEEE division: inf when
+ *                                      e0 == hxx[t] and numer != 0)
+ *   coeffs     device, ndet doubles (caller order unless HINQS_SORTED_ORDER)
+ *   e0         the reference energy E_0 (finite)
+ *   cand_alpha, cand_beta  device, ncand uint64 each; any determinants with
+ *              the electron counts of B (duplicates and members of B allowed)
+ *   numer, hxx, score      device, ncand doubles each, or NULL to skip
+ * Sums are in an unspecified but fixed order (bitwise reproducible on one
+ * device).  A candidate with bits at or above norb or the wrong electron
+ * count gets NaN outputs and the call returns BAD_OCCUPATION after the
+ * others are written.
+ * Errors: NOT_READY, INVALID_ARG, NONFINITE, BAD_OCCUPATION, OOM, HIP.
+ */
+int hinqs_pt2(hinqs_ctx *ctx, const double *coeffs, double e0, int64_t ncand,
+              const uint64_t *cand_alpha, const uint64_t *cand_beta, double *numer, double *hxx,
+              double *score, int flags);
+
+/*
+ * Stable selection of the k smallest (or, with HINQS_LARGEST, the k
+ * largest) of n doubles: idx (device, k int32) receives their indices in
+ * that order, ties broken by the lower index; -0.0 equals +0.0.  This is the
+ * ranking of Sec. 2.2: the cold start keeps the candidates of lowest H_xx,
+ * later iterations the candidates of highest PT2 score (Eq. 3).
+ *   values  device, n doubles; NaN gives NONFINITE
+ * Needs no integrals or determinants.  Allocates about 12 n bytes of device
+ * scratch for the call.
+ * Errors: INVALID_ARG (k < 1, k > n), UNSUPPORTED (n >= 2^31), NONFINITE,
+ * OOM, HIP.
+ */
+int hinqs_top_k(hinqs_ctx *ctx, int64_t n, const double *values, int64_t k, int flags, int32_t *idx);
 
 /*
  * Host-only helper (no device work): descriptor of the pair x_i <- x_j as

@@ -72,7 +72,7 @@ def _load():
             lib.or_rdm12.argtypes = [P, P, P, P]
             lib.or_rdm2_elements.argtypes = [P, P, i64, P, P]
             lib.or_num_threads.restype = ctypes.c_int
-            lib.or_pt2.argtypes = [P, P, ctypes.c_double, i64, P, P, P, P, P]
+            lib.or_pt2.argtypes = [P, P, ctypes.c_double, i64, P, P, P, P, P, P]
             lib.or_expand.restype = i64
             lib.or_expand.argtypes = [P, P, i64, P, i64, P, P]
             _lib = lib
@@ -220,9 +220,9 @@ class Oracle:
         return out
 
     # ------------------------------------------------ selection (Eq. 2, Eq. 3)
-    def pt2(self, c, e0, cand_alpha, cand_beta):
+    def pt2(self, c, e0, cand_alpha, cand_beta, with_scale=False):
         """(numerator <x|H|Psi_0>, H_xx, score) of each candidate determinant (Eq. 3);
-        c in caller order."""
+        c in caller order.  with_scale adds sum_i |c_i <x_i|H|x>| per candidate."""
         c = np.ascontiguousarray(c, dtype=np.float64)
         ca = np.ascontiguousarray(cand_alpha, dtype=np.uint64)
         cb = np.ascontiguousarray(cand_beta, dtype=np.uint64)
@@ -230,9 +230,10 @@ class Oracle:
         num = np.zeros(n)
         hxx = np.zeros(n)
         score = np.zeros(n)
+        absnum = np.zeros(n) if with_scale else None
         _load().or_pt2(self._h, _ptr(c), float(e0), n, _ptr(ca), _ptr(cb), _ptr(num), _ptr(hxx),
-                       _ptr(score))
-        return num, hxx, score
+                       _ptr(score), _ptr(absnum) if with_scale else None)
+        return (num, hxx, score, absnum) if with_scale else (num, hxx, score)
 
     def expand(self, c, ntop):
         """Classical expansion (Eq. 2): (alpha, beta) of every determinant outside B
@@ -248,3 +249,14 @@ class Oracle:
         out_b = np.zeros(max(n, 1), dtype=np.uint64)
         lib.or_expand(self._h, _ptr(c), ntop, _ptr(top), n, _ptr(out_a), _ptr(out_b))
         return out_a[:n], out_b[:n], top[:ntop]
+
+
+def top_k(values, k, largest=False):
+    """Indices of the k smallest (largest) values, ties by the lower index and
+    -0.0 equal to +0.0: the ranking of Sec. 2.2 (cold start by H_xx, later
+    iterations by the Eq. 3 score), written as a plain sort."""
+    v = [float(x) + 0.0 for x in np.asarray(values, dtype=np.float64)]
+    if any(x != x for x in v):
+        raise OracleError("NaN in values")
+    order = sorted(range(len(v)), key=lambda i: ((-v[i]) if largest else v[i], i))
+    return np.array(order[:k], dtype=np.int64)

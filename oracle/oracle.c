@@ -389,10 +389,11 @@ static void expand_h(const oracle_t *o, uint64_t x, ampmap_t *m)
  * PT2 importance of candidate determinants (Eq. 3): for each (alpha, beta)
  * the numerator <x|H|Psi_0> = sum_i c_i <x_i|H|x> (c in caller order; the
  * diagonal term is included when x lies in B), the diagonal element H_xx and
- * the score numer^2 / |e0 - H_xx| (IEEE division).
+ * the score numer^2 / |e0 - H_xx| (IEEE division).  absnum (may be NULL)
+ * receives sum_i |c_i <x_i|H|x>|, the scale of the numerator's rounding.
  */
 void or_pt2(void *handle, const double *c, double e0, int64_t ncand, const uint64_t *ca,
-            const uint64_t *cb, double *numer, double *hxx, double *score)
+            const uint64_t *cb, double *numer, double *hxx, double *score, double *absnum)
 {
     const oracle_t *o = (const oracle_t *)handle;
     const int64_t bound = reach_bound(o);
@@ -403,13 +404,17 @@ void or_pt2(void *handle, const double *c, double e0, int64_t ncand, const uint6
         for (int64_t t = 0; t < ncand; ++t) {
             const uint64_t x = ca[t] | (cb[t] << o->norb);
             expand_h(o, x, m);
-            double num = 0.0, d = 0.0;
+            double num = 0.0, d = 0.0, anum = 0.0;
             for (int64_t k = 0; k < m->n; ++k) {
                 const int64_t s = m->order[k];
                 if (m->key[s] == x) d = m->amp[s];
                 const int64_t j = lookup(o, m->key[s]);
-                if (j >= 0) num += c[j] * m->amp[s];
+                if (j >= 0) {
+                    num += c[j] * m->amp[s];
+                    anum += fabs(c[j] * m->amp[s]);
+                }
             }
+            if (absnum) absnum[t] = anum;
             numer[t] = num;
             hxx[t] = d;
             score[t] = num * num / fabs(e0 - d);

@@ -35,6 +35,7 @@ SOLVE_FP64, SOLVE_MIXED = 0, 1
 SORTED_ORDER = 1
 AUTOTUNE = 2
 NO_GRAPH = 4
+LARGEST = 8
 EXC_1A, EXC_1B, EXC_2AA, EXC_2BB, EXC_2AB = 1, 2, 3, 4, 5
 
 EXPORTED = ["hinqs_opts_default", "hinqs_create", "hinqs_destroy", "hinqs_last_error",
@@ -43,7 +44,7 @@ EXPORTED = ["hinqs_opts_default", "hinqs_create", "hinqs_destroy", "hinqs_last_e
             "hinqs_connectivity", "hinqs_permutation", "hinqs_get_info",
             "hinqs_pair_descriptor", "hinqs_gram", "hinqs_set_determinants_device",
             "hinqs_autotune", "hinqs_batch_clear", "hinqs_batch_add", "hinqs_batch_info",
-            "hinqs_batch_lowest_eigenpair"]
+            "hinqs_batch_lowest_eigenpair", "hinqs_expand", "hinqs_pt2", "hinqs_top_k"]
 
 
 class HinqsError(RuntimeError):
@@ -132,6 +133,9 @@ def load_library() -> ctypes.CDLL:
             "hinqs_batch_add": (i32, [P, i32, P, P, dbl, i64, P, P, i32, i32, P]),
             "hinqs_batch_info": (i32, [P, P, P, P]),
             "hinqs_batch_lowest_eigenpair": (i32, [P, P, P, P, P, P, P]),
+            "hinqs_expand": (i32, [P, P, i64, i64, P, P, P, P, i32]),
+            "hinqs_pt2": (i32, [P, P, dbl, i64, P, P, P, P, P, i32]),
+            "hinqs_top_k": (i32, [P, i64, P, i64, i32, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -419,6 +423,59 @@ class Hinqs:
         ms = ctypes.c_double(0.0)
         self._check(self._lib.hinqs_autotune(self._h, k, precision, shape, ctypes.byref(ms)))
         return tuple(shape), ms.value
+
+    # ------------------------------------------------------------ selection
+    def _dev_strings(self, x):
+        """Determinant strings as a contiguous int64 device tensor (uint64 bit patterns)."""
+        torch = _torch()
+        if isinstance(x, torch.Tensor) and x.device.type == "cuda":
+            return self._dev(x, torch.int64)
+        return torch.from_numpy(_host_u64(x).view(np.int64)).to(self.device)
+
+    def expand(self, c, ntop, sorted_order=False):
+        """Classical expansion (Eq. 2) of the ntop largest-|c| determinants:
+        (alpha, beta) of every coupled determinant outside B, ascending, as
+        int64 device tensors, and the chosen indices (int32, largest |c| first)."""
+        torch = _torch()
+        self._dev(c, torch.float64)
+        ntop = int(min(ntop, self.ndet))
+        nv_a, nv_b = self.norb - self.na, self.norb - self.nb
+        sa, sb = self.na * nv_a, self.nb * nv_b
+        per = (sa + sb + self.na * (self.na - 1) // 2 * (nv_a * (nv_a - 1) // 2)
+               + self.nb * (self.nb - 1) // 2 * (nv_b * (nv_b - 1) // 2) + sa * sb)
+        cap = max(ntop * per, 1)
+        out_a = torch.empty(cap, dtype=torch.int64, device=self.device)
+        out_b = torch.empty(cap, dtype=torch.int64, device=self.device)
+        top = torch.empty(max(ntop, 1), dtype=torch.int32, device=self.device)
+        n = ctypes.c_int64(0)
+        self._check(self._lib.hinqs_expand(self._h, self._ptr(c), ntop, cap, self._ptr(out_a),
+                                           self._ptr(out_b), ctypes.byref(n), self._ptr(top),
+                                           SORTED_ORDER if sorted_order else 0))
+        n = n.value
+        return out_a[:n].clone(), out_b[:n].clone(), top[:ntop]
+
+    def pt2(self, c, e0, cand_alpha, cand_beta, sorted_order=False):
+        """(numerator <x|H|Psi_0>, H_xx, score) of each candidate (Eq. 3) as
+        float64 device tensors; candidates as device int64 tensors or host arrays."""
+        torch = _torch()
+        self._dev(c, torch.float64)
+        ca, cb = self._dev_strings(cand_alpha), self._dev_strings(cand_beta)
+        if ca.shape != cb.shape or ca.dim() != 1:
+            raise ValueError("candidate alpha and beta must be 1-D and equally long")
+        n = ca.numel()
+        out = [torch.empty(max(n, 1), dtype=torch.float64, device=self.device) for _ in range(3)]
+        self._check(self._lib.hinqs_pt2(self._h, self._ptr(c), float(e0), n, self._ptr(ca), self._ptr(cb),
+                                        *[self._ptr(t) for t in out], SORTED_ORDER if sorted_order else 0))
+        return tuple(t[:n] for t in out)
+
+    def top_k(self, values, k, largest=False):
+        """Indices (int32 device tensor) of the k smallest (largest) values, ties by lower index."""
+        torch = _torch()
+        self._dev(values, torch.float64)
+        idx = torch.empty(max(int(k), 1), dtype=torch.int32, device=self.device)
+        self._check(self._lib.hinqs_top_k(self._h, values.numel(), self._ptr(values), int(k),
+                                          LARGEST if largest else 0, self._ptr(idx)))
+        return idx[:k]
 
     def info(self):
         inf = Info()

@@ -349,17 +349,45 @@ int hinqs_get_info(hinqs_ctx *ctx, hinqs_info *info) {
     });
 }
 
+int hinqs_expand(hinqs_ctx *ctx, const double *coeffs, int64_t ntop, int64_t capacity, uint64_t *out_alpha,
+                 uint64_t *out_beta, int64_t *count, int32_t *top, int flags) {
+    return guarded(ctx, [&](Ctx &c) {
+        require_dets(c);
+        if (!coeffs || !count) throw Error(HINQS_E_INVALID_ARG, "null pointer");
+        if (ntop < 1) throw Error(HINQS_E_INVALID_ARG, "ntop must be at least 1");
+        if (capacity < 0 || (capacity > 0 && (!out_alpha || !out_beta)))
+            throw Error(HINQS_E_INVALID_ARG, "capacity needs output arrays");
+        *count = expand(c, coeffs, (flags & HINQS_SORTED_ORDER) != 0, ntop, capacity, out_alpha, out_beta, top);
+        return HINQS_OK;
+    });
+}
+
+int hinqs_pt2(hinqs_ctx *ctx, const double *coeffs, double e0, int64_t ncand, const uint64_t *cand_alpha,
+              const uint64_t *cand_beta, double *numer, double *hxx, double *score, int flags) {
+    return guarded(ctx, [&](Ctx &c) {
+        require_dets(c);
+        if (!coeffs) throw Error(HINQS_E_INVALID_ARG, "null coefficients");
+        if (ncand < 0) throw Error(HINQS_E_INVALID_ARG, "ncand must be non-negative");
+        if (!std::isfinite(e0)) throw Error(HINQS_E_NONFINITE, "e0 is NaN/Inf");
+        if (ncand == 0) return HINQS_OK;
+        if (!cand_alpha || !cand_beta) throw Error(HINQS_E_INVALID_ARG, "null candidate strings");
+        pt2(c, coeffs, (flags & HINQS_SORTED_ORDER) != 0, e0, ncand, cand_alpha, cand_beta, numer, hxx, score);
+        return HINQS_OK;
+    });
+}
+
+int hinqs_top_k(hinqs_ctx *ctx, int64_t n, const double *values, int64_t k, int flags, int32_t *idx) {
+    return guarded(ctx, [&](Ctx &c) {
+        if (!values || !idx) throw Error(HINQS_E_INVALID_ARG, "null pointer");
+        if (n < 1 || k < 1 || k > n) throw Error(HINQS_E_INVALID_ARG, "need 1 <= k <= n");
+        if (n >= ((int64_t)1 << 31)) throw Error(HINQS_E_UNSUPPORTED, "n must be below 2^31");
+        top_k(c, n, values, k, (flags & HINQS_LARGEST) != 0, idx);
+        return HINQS_OK;
+    });
+}
+
 uint32_t hinqs_pair_descriptor(uint64_t alpha_i, uint64_t beta_i, uint64_t alpha_j, uint64_t beta_j) {
-    const uint32_t ai = (uint32_t)alpha_i, bi = (uint32_t)beta_i, aj = (uint32_t)alpha_j,
-                   bj = (uint32_t)beta_j;
-    const int da = popc32(ai ^ aj), db = popc32(bi ^ bj);
-    if (da + db == 0 || da + db > 4) return 0u;
-    if (db == 0) return same_spin_desc(ai, aj, HINQS_EXC_1A, HINQS_EXC_2AA);
-    if (da == 0) return same_spin_desc(bi, bj, HINQS_EXC_1B, HINQS_EXC_2BB);
-    // one alpha and one beta move
-    const uint32_t ha_m = aj & ~ai, pa_m = ai & ~aj;
-    const int ha = lowbit(ha_m), pa = lowbit(pa_m);
-    return ab_desc(ha, pa, single_parity(aj, ha, pa), bi, bj);
+    return pair_desc((uint32_t)alpha_i, (uint32_t)beta_i, (uint32_t)alpha_j, (uint32_t)beta_j);
 }
 
 int hinqs_connectivity(hinqs_ctx *ctx, int64_t *rowptr, int32_t *col, uint32_t *desc) {

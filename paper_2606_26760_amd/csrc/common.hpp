@@ -156,6 +156,17 @@ __host__ __device__ inline uint32_t ab_desc(int ha, int pa, uint32_t na, uint32_
     return make_desc(HINQS_EXC_2AB, na ^ single_parity(bj, hb, pb), ha, hb, pa, pb);
 }
 
+// Descriptor of the pair bra (ai, bi) <- ket (aj, bj), or 0 when they differ
+// by more than two electrons or not at all.
+__host__ __device__ inline uint32_t pair_desc(uint32_t ai, uint32_t bi, uint32_t aj, uint32_t bj) {
+    const int da = popc32(ai ^ aj), db = popc32(bi ^ bj);
+    if (da + db == 0 || da + db > 4) return 0u;
+    if (db == 0) return same_spin_desc(ai, aj, HINQS_EXC_1A, HINQS_EXC_2AA);
+    if (da == 0) return same_spin_desc(bi, bj, HINQS_EXC_1B, HINQS_EXC_2BB);
+    const int ha = lowbit(aj & ~ai), pa = lowbit(ai & ~aj);  // one alpha and one beta move
+    return ab_desc(ha, pa, single_parity(aj, ha, pa), bi, bj);
+}
+
 // ------------------------------------------------- packed integral indexing
 // Pair index of (p, q) with p >= q: p(p+1)/2 + q; 8-fold symmetric (pq|rs) is
 // stored once per unordered pair of pair indices.
@@ -309,6 +320,14 @@ int batch_add(Ctx &c, int norb, const double *h, const double *eri, double ecore
 void batch_info(Ctx &c, int *ninst, int64_t *offsets, int64_t *nnz);
 int batch_solve(Ctx &c, const hinqs_opts &o, double *energies, double *coeffs, int *status, int *iters,
                 hinqs_batch_stats *st);
+
+// Selection (select.hip): c in caller order unless `sorted`.
+int64_t excitations_per_det(int norb, int na, int nb);
+void top_k(Ctx &c, int64_t n, const double *v, int64_t k, bool largest, int32_t *idx);
+int64_t expand(Ctx &c, const double *coeffs, bool sorted, int64_t ntop, int64_t capacity, uint64_t *out_a,
+               uint64_t *out_b, int32_t *top);
+void pt2(Ctx &c, const double *coeffs, bool sorted, double e0, int64_t ncand, const uint64_t *ca,
+         const uint64_t *cb, double *numer, double *hxx, double *score);
 
 // Davidson (davidson.hip)
 int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, double *coeffs,

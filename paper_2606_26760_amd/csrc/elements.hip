@@ -5,17 +5,12 @@
 // value per unordered pair of orbital pairs (9,316 doubles = 74.5 KB at
 // norb = 16), small enough to sit in the LDS of a gfx950 workgroup next to h.
 //
-// Element rules for <x_i|H|x_j> (x_i the bra; holes occupied in x_j,
-// particles in x_i; s the canonical sign stored in the descriptor):
-//   diagonal        E_core + sum_k h_kk + 1/2 sum_{k,l}[(kk|ll) - delta_spin (kl|lk)]
-//   single q -> p   s [h_pq + sum_{k in common, same spin} ((pq|kk) - (pk|kq))
-//                        + sum_{k, other spin} (pq|kk)]
-//   same-spin double  s [(p1 h1|p2 h2) - (p1 h2|p2 h1)]
-//   opposite-spin     s (pa ha|pb hb)
+// The element rules are in slater.hpp.
 #include <chrono>
 #include <cmath>
 
 #include "common.hpp"
+#include "slater.hpp"
 
 namespace hinqs {
 
@@ -60,20 +55,6 @@ struct ElemArgs {
     float *diag32;
 };
 
-__device__ inline double single_value(const double *eri, const double *h, int norb, int p, int q,
-                                      uint32_t common_same, uint32_t other) {
-    double v = h[p * norb + q];
-    for (uint32_t m = common_same; m; m &= m - 1) {
-        int k = lowbit(m);
-        v += eri[eri_index(p, q, k, k)] - eri[eri_index(p, k, k, q)];
-    }
-    for (uint32_t m = other; m; m &= m - 1) {
-        int k = lowbit(m);
-        v += eri[eri_index(p, q, k, k)];
-    }
-    return v;
-}
-
 // One wave per row; lanes stride over the row's couplings.  Integrals in LDS
 // (USE_LDS) or read through the caches for orbital counts whose packed tensor
 // exceeds the LDS.
@@ -95,20 +76,7 @@ __global__ __launch_bounds__(256) void k_elements(ElemArgs a) {
         const uint32_t ai = a.sa[row], bi = a.sb[row];
         const int64_t beg = a.rowptr[row], end = a.rowptr[row + 1];
         for (int64_t e = beg + lane; e < end; e += 64) {
-            const uint32_t d = a.desc[e];
-            const uint32_t type = desc_type(d);
-            const int h1 = desc_h1(d), h2 = desc_h2(d), p1 = desc_p1(d), p2 = desc_p2(d);
-            double v;
-            if (type == HINQS_EXC_1A) {
-                v = single_value(eri, h, a.norb, p1, h1, ai & ~(1u << p1), bi);
-            } else if (type == HINQS_EXC_1B) {
-                v = single_value(eri, h, a.norb, p1, h1, bi & ~(1u << p1), ai);
-            } else if (type == HINQS_EXC_2AB) {
-                v = eri[eri_index(p1, h1, p2, h2)];
-            } else {
-                v = eri[eri_index(p1, h1, p2, h2)] - eri[eri_index(p1, h2, p2, h1)];
-            }
-            if (desc_neg(d)) v = -v;
+            const double v = coupling_value(eri, h, a.norb, a.desc[e], ai, bi);
             a.val[e] = v;
             a.val32[e] = (float)v;
         }
@@ -129,29 +97,7 @@ __global__ __launch_bounds__(256) void k_diag(ElemArgs a) {
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.ndet;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t ai = a.sa[i], bi = a.sb[i];
-        double e1 = 0.0, e2 = 0.0;
-        for (uint32_t m = ai; m; m &= m - 1) {
-            int k = lowbit(m);
-            e1 += h[k * a.norb + k];
-            for (uint32_t n = ai; n; n &= n - 1) {
-                int l = lowbit(n);
-                e2 += eri[eri_index(k, k, l, l)] - eri[eri_index(k, l, l, k)];
-            }
-            for (uint32_t n = bi; n; n &= n - 1) {
-                int l = lowbit(n);
-                e2 += 2.0 * eri[eri_index(k, k, l, l)];
-            }
-        }
-        for (uint32_t m = bi; m; m &= m - 1) {
-            int k = lowbit(m);
-            e1 += h[k * a.norb + k];
-            for (uint32_t n = bi; n; n &= n - 1) {
-                int l = lowbit(n);
-                e2 += eri[eri_index(k, k, l, l)] - eri[eri_index(k, l, l, k)];
-            }
-        }
-        double v = a.ecore + e1 + 0.5 * e2;
+        const double v = diag_value(eri, h, a.norb, a.ecore, a.sa[i], a.sb[i]);
         a.diag[i] = v;
         a.diag32[i] = (float)v;
     }

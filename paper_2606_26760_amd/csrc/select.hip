@@ -1,0 +1,494 @@
+// Selection steps around the subspace solve (Sec. 2.2): the classical
+// expansion of Eq. 2 (every determinant outside B that H connects to one of
+// the largest-|c| determinants of B), the PT2 importance of Eq. 3 (the
+// numerator sum_i c_i <x|H|x_i> of a candidate x over B, its diagonal H_xx
+// and the score), and a stable top-k over a vector of scores, used both for
+// the cold-start ranking by H_xx and for keeping the best-scored candidates.
+//
+// Both the expansion and the PT2 numerator reach into B only through its
+// sorted string tables: alpha groups (distinct alpha strings ua, rows
+// ga[g] .. ga[g+1] with ascending beta strings sb) and beta groups (distinct
+// beta strings ub, entries gb[g] .. gb[g+1] of the beta-major listing bperm
+// with their alpha strings bm_alpha).  A determinant is found by two binary
+// searches; every partner of a candidate is found by scanning at most
+// 2 + na (norb - na) groups.  Matrix elements follow slater.hpp, with the
+// packed integrals in LDS when they fit.
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+#include "slater.hpp"
+
+namespace hinqs {
+
+namespace {
+
+constexpr int EX_NT = 256;  // expansion: one workgroup per chosen determinant at a time
+constexpr int PT_NT = 512;  // PT2: one wave per candidate at a time
+constexpr int NPAIR32 = 32 * 31 / 2;
+
+struct BTables {
+    int32_t nua, nub;
+    const uint32_t *ua, *ub;      // distinct strings, ascending
+    const uint32_t *sa, *sb;      // strings in sorted order
+    const int32_t *ga, *gb;       // group offsets
+    const int32_t *bperm;         // beta-major listing of sorted positions
+    const uint32_t *bm_alpha;     // alpha string of bperm[u]
+};
+
+BTables tables_of(const Ctx &c) {
+    return BTables{c.nua, c.nub, c.ua.p, c.ub.p, c.sa.p, c.sb.p, c.ga.p, c.gb.p, c.bperm.p, c.bm_alpha.p};
+}
+
+// Index of x in the ascending array v[0..n), or -1.
+__device__ inline int32_t find_u32(const uint32_t *v, int32_t n, uint32_t x) {
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (v[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (lo < n && v[lo] == x) ? lo : -1;
+}
+
+// Sorted position of the determinant (a, b) in B, or -1.
+__device__ inline int64_t find_det(const BTables &t, uint32_t a, uint32_t b) {
+    const int32_t g = find_u32(t.ua, t.nua, a);
+    if (g < 0) return -1;
+    const int32_t lo = t.ga[g], hi = t.ga[g + 1];
+    const int32_t r = find_u32(t.sb + lo, hi - lo, b);
+    return r < 0 ? -1 : (int64_t)lo + r;
+}
+
+// Orbital of the n-th set bit (from the lowest) of m; m has more than n bits.
+__device__ inline int nth_bit(uint32_t m, int n) {
+    for (int i = 0; i < n; ++i) m &= m - 1;
+    return lowbit(m);
+}
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Stage the packed integrals and h in LDS (USE_LDS) or point at them.
+template <bool USE_LDS>
+__device__ inline void stage_integrals(double *smem, const double *eri_g, const double *h_g, int npack, int norb,
+                                       const double *&eri, const double *&h) {
+    eri = eri_g;
+    h = h_g;
+    if (USE_LDS) {
+        for (int t = threadIdx.x; t < npack; t += blockDim.x) smem[t] = eri_g[t];
+        for (int t = threadIdx.x; t < norb * norb; t += blockDim.x) smem[npack + t] = h_g[t];
+        __syncthreads();
+        eri = smem;
+        h = smem + npack;
+    }
+}
+
+// ------------------------------------------------------------ top-k keys
+// Order-preserving unsigned image of a double (ascending values give
+// ascending keys; -0 is taken as +0, so equal values tie); with `largest`
+// the order is reversed.  NaN raises the flag.
+__global__ void k_order_keys(const double *v, int64_t n, bool largest, uint64_t *keys, int32_t *vals,
+                             unsigned *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x = v[i];
+    if (x != x) atomicOr(bad, 1u);
+    if (x == 0.0) x = 0.0;
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    uint64_t k = (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+    keys[i] = largest ? ~k : k;
+    vals[i] = (int32_t)i;
+}
+
+// Keys ordering |c| descending; non-finite c raises the flag.
+__global__ void k_mag_keys(const double *c, int64_t n, uint64_t *keys, int32_t *vals, unsigned *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double x = c[i];
+    if (!isfinite(x)) atomicOr(bad, 1u);
+    keys[i] = 0x7fffffffffffffffull - (uint64_t)__double_as_longlong(fabs(x));
+    vals[i] = (int32_t)i;
+}
+
+// top_out[t] = vals[t] (index in the caller's order of the vector); pos[t] =
+// its sorted position.
+__global__ void k_take_top(const int32_t *vals, int64_t ntop, const int32_t *inv, int32_t *top_out,
+                           int32_t *pos) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntop) return;
+    const int32_t v = vals[t];
+    if (top_out) top_out[t] = v;
+    if (pos) pos[t] = inv ? inv[v] : v;
+}
+
+// ------------------------------------------------------ classical expansion
+struct ExpArgs {
+    BTables B;
+    int norb, npack, na, nb;
+    int64_t ntop;
+    const int32_t *pos;  // sorted positions of the chosen determinants
+    const double *eri, *h;
+    uint64_t *keys;      // ntop * (excitations per determinant) entries
+    unsigned long long *count;
+};
+
+// Every single and double excitation y of a chosen determinant x, indexed
+// r = 0 .. nexc-1 in five ranges: alpha singles, beta singles, alpha-alpha
+// doubles, beta-beta doubles, alpha-beta doubles.  y is kept when
+// <y|H|x> != 0 and y is not in B; kept keys (alpha << norb | beta) are
+// appended with one atomic per wave.
+template <bool USE_LDS>
+__global__ __launch_bounds__(EX_NT) void k_expand(ExpArgs a) {
+    extern __shared__ double smem[];
+    __shared__ uint16_t pairs[NPAIR32];      // k = j (j - 1) / 2 + i  ->  i | j << 8, i < j
+    __shared__ uint8_t occ[2][32], vir[2][32];
+    const double *eri, *h;
+    stage_integrals<USE_LDS>(smem, a.eri, a.h, a.npack, a.norb, eri, h);
+    for (int k = threadIdx.x; k < NPAIR32; k += blockDim.x) {
+        int j = 1;
+        while ((j + 1) * j / 2 <= k) ++j;
+        pairs[k] = (uint16_t)((k - j * (j - 1) / 2) | (j << 8));
+    }
+    const int norb = a.norb, na = a.na, nb = a.nb, nva = norb - na, nvb = norb - nb;
+    const uint32_t full = norb >= 32 ? 0xffffffffu : ((1u << norb) - 1u);
+    const int64_t sA = (int64_t)na * nva, sB = (int64_t)nb * nvb;
+    const int64_t cva = (int64_t)nva * (nva - 1) / 2, cvb = (int64_t)nvb * (nvb - 1) / 2;
+    const int64_t dAA = (int64_t)na * (na - 1) / 2 * cva, dBB = (int64_t)nb * (nb - 1) / 2 * cvb;
+    const int64_t total = sA + sB + dAA + dBB + sA * sB;
+    const int lane = threadIdx.x & 63;
+    for (int64_t t = blockIdx.x; t < a.ntop; t += gridDim.x) {
+        const int32_t p = a.pos[t];
+        const uint32_t xa = a.B.sa[p], xb = a.B.sb[p];
+        __syncthreads();  // the previous determinant's lists are no longer read
+        if (threadIdx.x < 2) {
+            const uint32_t s = threadIdx.x == 0 ? xa : xb;
+            int no = 0, nv = 0;
+            for (int q = 0; q < norb; ++q) {
+                if ((s >> q) & 1u)
+                    occ[threadIdx.x][no++] = (uint8_t)q;
+                else
+                    vir[threadIdx.x][nv++] = (uint8_t)q;
+            }
+        }
+        __syncthreads();
+        for (int64_t r0 = 0; r0 < total; r0 += EX_NT) {
+            int64_t r = r0 + threadIdx.x;
+            bool keep = false;
+            uint64_t key = 0;
+            if (r < total) {
+                uint32_t ya = xa, yb = xb;
+                if (r < sA) {
+                    ya ^= (1u << occ[0][r / nva]) | (1u << vir[0][r % nva]);
+                } else if ((r -= sA) < sB) {
+                    yb ^= (1u << occ[1][r / nvb]) | (1u << vir[1][r % nvb]);
+                } else if ((r -= sB) < dAA) {
+                    const int po = pairs[r / cva], pv = pairs[r % cva];
+                    ya ^= (1u << occ[0][po & 255]) | (1u << occ[0][po >> 8]) | (1u << vir[0][pv & 255]) |
+                          (1u << vir[0][pv >> 8]);
+                } else if ((r -= dAA) < dBB) {
+                    const int po = pairs[r / cvb], pv = pairs[r % cvb];
+                    yb ^= (1u << occ[1][po & 255]) | (1u << occ[1][po >> 8]) | (1u << vir[1][pv & 255]) |
+                          (1u << vir[1][pv >> 8]);
+                } else {
+                    r -= dBB;
+                    const int64_t s1 = r / sB, s2 = r % sB;
+                    ya ^= (1u << occ[0][s1 / nva]) | (1u << vir[0][s1 % nva]);
+                    yb ^= (1u << occ[1][s2 / nvb]) | (1u << vir[1][s2 % nvb]);
+                }
+                const double v = coupling_value(eri, h, norb, pair_desc(ya, yb, xa, xb), ya, yb);
+                if (v != 0.0 && find_det(a.B, ya, yb) < 0) {
+                    keep = true;
+                    key = ((uint64_t)ya << norb) | (uint64_t)(yb & full);
+                }
+            }
+            const uint64_t m = __ballot(keep);
+            if (m) {
+                const int leader = __builtin_ctzll(m);
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(a.count, (unsigned long long)__popcll(m));
+                base = __shfl(base, leader, 64);
+                if (keep) a.keys[base + __popcll(m & ((1ull << lane) - 1ull))] = key;
+            }
+        }
+    }
+}
+
+__global__ void k_unique_flags(const uint64_t *keys, int64_t n, int32_t *flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+
+__global__ void k_unique_write(const uint64_t *keys, const int32_t *flag, const int32_t *pos, int64_t n,
+                               int norb, int64_t cap, uint64_t *out_a, uint64_t *out_b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    const int64_t p = pos[i];
+    if (p >= cap) return;
+    const uint64_t lo = norb >= 64 ? ~0ull : ((1ull << norb) - 1ull);
+    out_a[p] = keys[i] >> norb;
+    out_b[p] = keys[i] & lo;
+}
+
+// ------------------------------------------------------------------- PT2
+struct Pt2Args {
+    BTables B;
+    int norb, npack, na, nb;
+    double ecore, e0;
+    int64_t ncand;
+    const uint64_t *ca, *cb;
+    const double *cs;  // coefficients in sorted order
+    const double *eri, *h;
+    double *numer, *hxx, *score;
+    unsigned *bad;
+};
+
+// One wave per candidate x = (xa, xb).  Its partners in B fall into three
+// disjoint classes, each read from one kind of group:
+//   same alpha string        the alpha group of xa (beta differs by 0, 1 or 2)
+//   same beta string         the beta group of xb (alpha differs by 1 or 2)
+//   one move in each spin    the alpha groups of the na (norb - na) strings one
+//                            move from xa, keeping beta strings one move from xb
+// The diagonal enters through the first class when x lies in B.
+template <bool USE_LDS>
+__global__ __launch_bounds__(PT_NT) void k_pt2(Pt2Args a) {
+    extern __shared__ double smem[];
+    const double *eri, *h;
+    stage_integrals<USE_LDS>(smem, a.eri, a.h, a.npack, a.norb, eri, h);
+    const int lane = threadIdx.x & 63;
+    const int norb = a.norb, nva = norb - a.na, nmov = a.na * nva;
+    const uint32_t full = norb >= 32 ? 0xffffffffu : ((1u << norb) - 1u);
+    const int64_t nwaves = (int64_t)gridDim.x * (PT_NT / 64);
+    for (int64_t t = (int64_t)blockIdx.x * (PT_NT / 64) + (threadIdx.x >> 6); t < a.ncand; t += nwaves) {
+        const uint64_t a64 = a.ca[t], b64 = a.cb[t];
+        if ((a64 >> norb) != 0 || (b64 >> norb) != 0 || __popcll(a64) != a.na || __popcll(b64) != a.nb) {
+            if (lane == 0) {
+                atomicOr(a.bad, 1u);
+                const double nan = __longlong_as_double(0x7ff8000000000000ll);
+                if (a.numer) a.numer[t] = nan;
+                if (a.hxx) a.hxx[t] = nan;
+                if (a.score) a.score[t] = nan;
+            }
+            continue;
+        }
+        const uint32_t xa = (uint32_t)a64, xb = (uint32_t)b64;
+        const double d = diag_value(eri, h, norb, a.ecore, xa, xb);
+        double acc = 0.0;
+        const int32_t g = find_u32(a.B.ua, a.B.nua, xa);
+        if (g >= 0) {
+            const int32_t end = a.B.ga[g + 1];
+            for (int32_t j = a.B.ga[g] + lane; j < end; j += 64) {
+                const uint32_t bj = a.B.sb[j];
+                const int db = popc32(xb ^ bj);
+                if (db == 0)
+                    acc += a.cs[j] * d;
+                else if (db <= 4)
+                    acc += a.cs[j] * coupling_value(eri, h, norb, pair_desc(xa, xb, xa, bj), xa, xb);
+            }
+        }
+        const int32_t gbx = find_u32(a.B.ub, a.B.nub, xb);
+        if (gbx >= 0) {
+            const int32_t end = a.B.gb[gbx + 1];
+            for (int32_t u = a.B.gb[gbx] + lane; u < end; u += 64) {
+                const uint32_t aj = a.B.bm_alpha[u];
+                const int da = popc32(xa ^ aj);
+                if (da != 0 && da <= 4)
+                    acc += a.cs[a.B.bperm[u]] *
+                           coupling_value(eri, h, norb, pair_desc(xa, xb, aj, xb), xa, xb);
+            }
+        }
+        for (int m0 = 0; m0 < nmov; m0 += 64) {
+            const int m = m0 + lane;
+            int32_t gm = -1;
+            uint32_t am = 0;
+            if (m < nmov) {
+                am = xa ^ (1u << nth_bit(xa, m / nva)) ^ (1u << nth_bit(~xa & full, m % nva));
+                gm = find_u32(a.B.ua, a.B.nua, am);
+            }
+            uint64_t found = __ballot(gm >= 0);
+            while (found) {
+                const int src = __builtin_ctzll(found);
+                found &= found - 1;
+                const int32_t gg = __shfl(gm, src, 64);
+                const uint32_t aj = (uint32_t)__shfl((int)am, src, 64);
+                const int32_t end = a.B.ga[gg + 1];
+                for (int32_t j = a.B.ga[gg] + lane; j < end; j += 64) {
+                    const uint32_t bj = a.B.sb[j];
+                    if (popc32(xb ^ bj) == 2)
+                        acc += a.cs[j] * coupling_value(eri, h, norb, pair_desc(xa, xb, aj, bj), xa, xb);
+                }
+            }
+        }
+        acc = wave_sum_d(acc);
+        if (lane == 0) {
+            if (a.numer) a.numer[t] = acc;
+            if (a.hxx) a.hxx[t] = d;
+            if (a.score) a.score[t] = acc * acc / fabs(a.e0 - d);
+        }
+    }
+}
+
+int device_cus(const Ctx &c) {
+    int n = 256;
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, c.device);
+    return n;
+}
+
+size_t integral_lds(const Ctx &c) {
+    return sizeof(double) * ((size_t)neri_packed(c.norb) + (size_t)c.norb * c.norb);
+}
+
+}  // namespace
+
+int64_t excitations_per_det(int norb, int na, int nb) {
+    const int64_t nva = norb - na, nvb = norb - nb;
+    const int64_t sA = na * nva, sB = nb * nvb;
+    return sA + sB + (int64_t)na * (na - 1) / 2 * (nva * (nva - 1) / 2) +
+           (int64_t)nb * (nb - 1) / 2 * (nvb * (nvb - 1) / 2) + sA * sB;
+}
+
+void top_k(Ctx &c, int64_t n, const double *v, int64_t k, bool largest, int32_t *idx) {
+    hipStream_t s = c.stream;
+    DBuf<uint64_t> keys;
+    DBuf<int32_t> vals;
+    DBuf<unsigned> bad;
+    keys.ensure(n);
+    vals.ensure(n);
+    bad.ensure(1);
+    HQ_CHECK(hipMemsetAsync(bad.p, 0, sizeof(unsigned), s));
+    hipLaunchKernelGGL(k_order_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, v, n, largest, keys.p, vals.p,
+                       bad.p);
+    HQ_LAUNCH_CHECK();
+    radix_sort_u64(s, keys.p, vals.p, n, 64, c.work);
+    unsigned hbad = 0;
+    HQ_CHECK(hipMemcpyAsync(&hbad, bad.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipStreamSynchronize(s));
+    if (hbad) throw Error(HINQS_E_NONFINITE, "values contain NaN");
+    hipLaunchKernelGGL(k_take_top, dim3(grid_for(k, 256)), dim3(256), 0, s, vals.p, k, (const int32_t *)nullptr,
+                       idx, (int32_t *)nullptr);
+    HQ_LAUNCH_CHECK();
+    HQ_CHECK(hipStreamSynchronize(s));
+}
+
+int64_t expand(Ctx &c, const double *coeffs, bool sorted, int64_t ntop, int64_t capacity, uint64_t *out_a,
+               uint64_t *out_b, int32_t *top) {
+    hipStream_t s = c.stream;
+    const int64_t n = c.ndet;
+    if (ntop > n) ntop = n;
+    // the ntop largest |c| (stable: ties keep the lower index first)
+    DBuf<uint64_t> keys;
+    DBuf<int32_t> vals, pos;
+    DBuf<unsigned> bad;
+    keys.ensure(n);
+    vals.ensure(n);
+    pos.ensure(ntop);
+    bad.ensure(1);
+    HQ_CHECK(hipMemsetAsync(bad.p, 0, sizeof(unsigned), s));
+    hipLaunchKernelGGL(k_mag_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, coeffs, n, keys.p, vals.p, bad.p);
+    HQ_LAUNCH_CHECK();
+    radix_sort_u64(s, keys.p, vals.p, n, 63, c.work);
+    unsigned hbad = 0;
+    HQ_CHECK(hipMemcpyAsync(&hbad, bad.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipStreamSynchronize(s));
+    if (hbad) throw Error(HINQS_E_NONFINITE, "coefficients contain NaN/Inf");
+    hipLaunchKernelGGL(k_take_top, dim3(grid_for(ntop, 256)), dim3(256), 0, s, vals.p, ntop,
+                       sorted ? (const int32_t *)nullptr : (const int32_t *)c.inv.p, top, pos.p);
+    HQ_LAUNCH_CHECK();
+    keys.release();
+    vals.release();
+
+    // every single and double of the chosen determinants, kept when coupled and outside B
+    const int64_t nexc = excitations_per_det(c.norb, c.na, c.nb);
+    const int64_t cap = ntop * nexc;
+    if (cap >= ((int64_t)1 << 31))
+        throw Error(HINQS_E_UNSUPPORTED, "expansion of " + std::to_string(ntop) +
+                                             " determinants exceeds 2^31 excitations; expand fewer at once");
+    DBuf<uint64_t> raw;
+    DBuf<unsigned long long> cnt;
+    raw.ensure(cap);
+    cnt.ensure(1);
+    HQ_CHECK(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
+    ExpArgs ea{tables_of(c), c.norb, neri_packed(c.norb), c.na, c.nb, ntop, pos.p, c.d_eri.p, c.d_h.p, raw.p,
+               cnt.p};
+    const size_t lds = integral_lds(c);
+    const int cus = device_cus(c);
+    if (lds <= 150 * 1024) {
+        HQ_CHECK(hipFuncSetAttribute((const void *)k_expand<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds));
+        const unsigned grid = (unsigned)std::min<int64_t>(ntop, (int64_t)cus * 2);
+        hipLaunchKernelGGL(k_expand<true>, dim3(grid), dim3(EX_NT), lds, s, ea);
+    } else {
+        const unsigned grid = (unsigned)std::min<int64_t>(ntop, (int64_t)cus * 8);
+        hipLaunchKernelGGL(k_expand<false>, dim3(grid), dim3(EX_NT), 0, s, ea);
+    }
+    HQ_LAUNCH_CHECK();
+    unsigned long long hcnt = 0;
+    HQ_CHECK(hipMemcpyAsync(&hcnt, cnt.p, sizeof(hcnt), hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipStreamSynchronize(s));
+    const int64_t nraw = (int64_t)hcnt;
+    if (nraw == 0) return 0;
+
+    // sort and drop repeats: ascending (alpha, beta)
+    DBuf<int32_t> rv, flag, fpos;
+    rv.ensure(nraw);
+    radix_sort_u64(s, raw.p, rv.p, nraw, 2 * c.norb, c.work);
+    flag.ensure(nraw);
+    fpos.ensure(nraw);
+    hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(nraw, 256)), dim3(256), 0, s, raw.p, nraw, flag.p);
+    HQ_LAUNCH_CHECK();
+    exclusive_scan_i32(s, flag.p, fpos.p, nraw, c.work);
+    int32_t last[2] = {0, 0};
+    HQ_CHECK(hipMemcpyAsync(&last[0], fpos.p + nraw - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipMemcpyAsync(&last[1], flag.p + nraw - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (capacity > 0) {
+        hipLaunchKernelGGL(k_unique_write, dim3(grid_for(nraw, 256)), dim3(256), 0, s, raw.p, flag.p, fpos.p,
+                           nraw, c.norb, capacity, out_a, out_b);
+        HQ_LAUNCH_CHECK();
+    }
+    HQ_CHECK(hipStreamSynchronize(s));
+    return (int64_t)last[0] + last[1];
+}
+
+void pt2(Ctx &c, const double *coeffs, bool sorted, double e0, int64_t ncand, const uint64_t *ca,
+         const uint64_t *cb, double *numer, double *hxx, double *score) {
+    hipStream_t s = c.stream;
+    DBuf<double> cs;
+    const double *csp = coeffs;
+    if (!sorted) {
+        cs.ensure(c.ndet);
+        gather_rows(s, coeffs, cs.p, c.perm.p, c.ndet, 8);
+        csp = cs.p;
+    }
+    DBuf<unsigned> bad;
+    bad.ensure(1);
+    HQ_CHECK(hipMemsetAsync(bad.p, 0, sizeof(unsigned), s));
+    Pt2Args pa{tables_of(c), c.norb, neri_packed(c.norb), c.na, c.nb, c.ecore, e0, ncand, ca, cb, csp,
+               c.d_eri.p, c.d_h.p, numer, hxx, score, bad.p};
+    const size_t lds = integral_lds(c);
+    const int cus = device_cus(c);
+    const int64_t want = (ncand + PT_NT / 64 - 1) / (PT_NT / 64);
+    if (lds <= 150 * 1024) {
+        HQ_CHECK(hipFuncSetAttribute((const void *)k_pt2<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds));
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)cus * 2));
+        hipLaunchKernelGGL(k_pt2<true>, dim3(grid), dim3(PT_NT), lds, s, pa);
+    } else {
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)cus * 4));
+        hipLaunchKernelGGL(k_pt2<false>, dim3(grid), dim3(PT_NT), 0, s, pa);
+    }
+    HQ_LAUNCH_CHECK();
+    unsigned hbad = 0;
+    HQ_CHECK(hipMemcpyAsync(&hbad, bad.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipStreamSynchronize(s));
+    if (hbad)
+        throw Error(HINQS_E_BAD_OCCUPATION,
+                    "a candidate has bits at or above norb or the wrong electron count (its outputs are NaN)");
+}
+
+}  // namespace hinqs

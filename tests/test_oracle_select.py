@@ -30,11 +30,12 @@ def test_pt2_matches_jordan_wigner():
     iB = jw.basis_index(a, b, ints.norb)
     ix = jw.basis_index(fa, fb, ints.norb)
     e0 = -3.25
-    num, hxx, score = o.pt2(c, e0, fa, fb)
+    num, hxx, score, absnum = o.pt2(c, e0, fa, fb, with_scale=True)
     num_ref = H[ix][:, iB] @ c
     hxx_ref = H[ix, ix].A1 if hasattr(H[ix, ix], "A1") else np.asarray(H[ix, ix]).ravel()
     scale = np.abs(H[ix][:, iB]).toarray() @ np.abs(c) + 1e-300
     assert np.all(np.abs(num - num_ref) <= 1e-12 * scale + 1e-15)
+    assert np.allclose(absnum, scale, rtol=1e-12, atol=1e-15)
     assert np.allclose(hxx, hxx_ref, rtol=0, atol=1e-12)
     assert np.allclose(score, num_ref ** 2 / np.abs(e0 - hxx_ref), rtol=1e-11, atol=1e-15)
     # a member of B: the numerator is the row of H_B c, diagonal included
@@ -111,3 +112,15 @@ def test_expand_ties_prefer_lower_index():
     assert list(top) == [3, 7, 9]
     _, _, top = o.expand(cc, 6)
     assert list(top) == [3, 7, 9, 12, 15, 20]
+
+
+def test_top_k_definition():
+    """Hand-checked ranking: ties keep the lower index, -0.0 equals +0.0,
+    infinities order at the ends, NaN is refused."""
+    v = [0.5, -1.0, 0.0, -0.0, 0.5, np.inf, -np.inf, 2.0, -1.0]
+    assert list(oracle.top_k(v, 4)) == [6, 1, 8, 2]
+    assert list(oracle.top_k(v, 9)) == [6, 1, 8, 2, 3, 0, 4, 7, 5]
+    assert list(oracle.top_k(v, 3, largest=True)) == [5, 7, 0]
+    assert list(oracle.top_k(v, 9, largest=True)) == [5, 7, 0, 4, 2, 3, 1, 8, 6]
+    with pytest.raises(oracle.OracleError):
+        oracle.top_k([1.0, float("nan")], 1)
