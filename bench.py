@@ -22,6 +22,12 @@ The roofline object covers the FP64 sigma kernel: algorithmic bytes per launch
 (12 nnz + 16 k ndet + 16 ndet + 8) over its average launch time, taken from
 HIP events recorded around each launch on the library's stream.
 cpu_baseline times the CPU oracle's matrix-free sigma on a bounded row sample.
+
+After the timed steps, the "select" object times one pass of the selection
+steps that follow the solve (Sec. 2.2): the classical expansion of the 1000
+largest |c| of the FP64 eigenvector (Eq. 2), the PT2 score of every expanded
+determinant (Eq. 3) and the top 1e5 by score, with the oracle's PT2 rate on a
+sample beside it.
 """
 import argparse
 import json
@@ -37,13 +43,12 @@ METRIC = "sigma H·X elements/s + HBM GB/s; Davidson solve time to 1e-8 Ha, mixe
 HBM_PEAK_GBS = 8000.0
 
 
-def cpu_baseline(ints, alpha, beta, cfg, target_s=10.0):
+def cpu_baseline(o, alpha, cfg, target_s=10.0):
     """The oracle's matrix-free sigma (k = 8) on a random row sample, as it stands."""
     import numpy as np
 
     import oracle
     import workloads as W
-    o = oracle.Oracle.from_inputs(ints, alpha, beta, cfg.na, cfg.nb)
     X = W.random_block(len(alpha), cfg.k, 99)
     rng = np.random.default_rng(123)
     n = 256
@@ -110,6 +115,48 @@ def sequential_batch(hq, insts, block, tol):
     return t_build, t_solve, energies
 
 
+def selection_pass(hq, solver, c, e0, ntop, keep, reps=3):
+    """One pass of the selection steps that follow the solve, on the solved
+    determinant set: classical expansion of the ntop largest |c| (Eq. 2),
+    PT2 scores of every expanded determinant (Eq. 3), and the top `keep` of
+    them.  Median wall time of each phase over `reps` passes (each call
+    synchronizes the library's stream)."""
+    import numpy as np
+    import torch
+    times = {"expand": [], "pt2": [], "top_k": []}
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ya, yb, _ = solver.expand(c, ntop)
+        t1 = time.perf_counter()
+        num, hxx, score = solver.pt2(c, e0, ya, yb)
+        t2 = time.perf_counter()
+        k = min(keep, len(ya))
+        idx = solver.top_k(score, k, largest=True)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        times["expand"].append(t1 - t0)
+        times["pt2"].append(t2 - t1)
+        times["top_k"].append(t3 - t2)
+    med = {kk: float(np.median(v)) * 1e3 for kk, v in times.items()}
+    n = len(ya)
+    return {"ntop": ntop, "candidates": n, "keep": k,
+            "ms_expand": med["expand"], "ms_pt2": med["pt2"], "ms_top_k": med["top_k"],
+            "pt2_candidates_per_s": n / (med["pt2"] * 1e-3),
+            "max_score": float(score[idx[0]].item()) if n else None}, (ya, yb)
+
+
+def cpu_pt2_rate(o, c, e0, ya, yb, n=2000):
+    """The oracle's PT2 (Eq. 3) on a sample of the expanded determinants, as it stands."""
+    import oracle
+    m = min(n, len(ya))
+    t0 = time.perf_counter()
+    o.pt2(c, e0, ya[:m], yb[:m])
+    dt = time.perf_counter() - t0
+    return {"value": m / dt, "unit": "candidates/s", "cores": oracle.Oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {m} expanded determinants, {dt:.2f} s"}
+
+
 def recorded_traffic():
     """HBM bytes per FP64 sigma launch from the committed counter summary, or None
     when the sigma kernel source has changed since the counters were taken."""
@@ -135,6 +182,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="leave the batched instances out of the step")
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
+    ap.add_argument("--ntop", type=int, default=1000, help="determinants expanded by the selection pass")
+    ap.add_argument("--keep", type=int, default=100000, help="candidates kept by score in the selection pass")
     ap.add_argument("--mode", choices=["step", "sigma"], default="step",
                     help="sigma: only repeated FP64 sigma launches plus a copy kernel of known "
                          "size (for hardware-counter runs)")
@@ -163,6 +212,8 @@ def main():
     insts = None if args.no_batch else batch_inputs()
     bsolver = None if args.no_batch else hq.Hinqs(0)
 
+    last = {}
+
     def step():
         t = {}
         t0 = time.perf_counter()
@@ -170,6 +221,7 @@ def main():
         solver.set_determinants(a_d, b_d, cfg.na, cfg.nb)
         t1 = time.perf_counter()
         e64, c64, st64 = solver.lowest_eigenpair(tol=cfg.tol, block=cfg.k, autotune=True)
+        last["c64"] = c64
         t2 = time.perf_counter()
         em, cm, stm = solver.lowest_eigenpair(tol=cfg.tol, block=cfg.k, mixed=True, autotune=True)
         t3 = time.perf_counter()
@@ -267,8 +319,19 @@ def main():
             "solve_speedup_vs_sequential": ss * 1e3 / ms_solve,
             "max_abs_dE_vs_sequential": float(np.max(np.abs(np.asarray(se) - be))),
         }
+    # the selection steps after the solve, on the last FP64 eigenpair (outside the timed region)
+    e_sel = res[-1][1][0]
+    sel, (ya, yb) = selection_pass(hq, solver, last["c64"], e_sel, args.ntop, args.keep)
+    out["select"] = dict(sel, workload=f"expansion of the {args.ntop} largest |c| of the FP64 eigenvector "
+                                       f"of the {D}-determinant set, PT2 of every expanded determinant, "
+                                       f"top {args.keep} by score")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(ints, alpha, beta, cfg, args.cpu_seconds)
+        import oracle
+        o = oracle.Oracle.from_inputs(ints, alpha, beta, cfg.na, cfg.nb)
+        out["cpu_baseline"] = cpu_baseline(o, alpha, cfg, args.cpu_seconds)
+        out["select"]["cpu_pt2"] = cpu_pt2_rate(o, last["c64"].cpu().numpy(), e_sel,
+                                                ya.cpu().numpy().view(np.uint64),
+                                                yb.cpu().numpy().view(np.uint64))
     print(json.dumps(out), flush=True)
 
 

@@ -24,7 +24,7 @@ namespace hinqs {
 namespace {
 
 constexpr int EX_NT = 256;  // expansion: one workgroup per chosen determinant at a time
-constexpr int PT_NT = 512;  // PT2: one wave per candidate at a time
+constexpr int PT_NT = 1024; // PT2: one wave per candidate at a time
 constexpr int NPAIR32 = 32 * 31 / 2;
 
 struct BTables {
@@ -240,6 +240,8 @@ __global__ void k_unique_write(const uint64_t *keys, const int32_t *flag, const 
 struct Pt2Args {
     BTables B;
     int norb, npack, na, nb;
+    int alink_max;
+    const int32_t *alink_ptr, *alink;  // single alpha moves between strings of B
     double ecore, e0;
     int64_t ncand;
     const uint64_t *ca, *cb;
@@ -249,15 +251,50 @@ struct Pt2Args {
     unsigned *bad;
 };
 
+constexpr int SCAN_U = 4;  // group entries in flight per lane
+
+// acc += c_j <x|H|x_j> over the rows j in [lo, hi) of one alpha group (alpha
+// string aj) whose beta string differs from xb by a number of electrons in
+// the accepted set: SAME_ALPHA accepts 0 (the diagonal d), 1 or 2 electrons,
+// otherwise exactly one.
+template <bool SAME_ALPHA>
+__device__ inline void scan_alpha_group(const Pt2Args &a, const double *eri, const double *h, int32_t lo,
+                                        int32_t hi, uint32_t xa, uint32_t xb, uint32_t aj, double d, int lane,
+                                        double &acc) {
+    for (int32_t j0 = lo + lane; j0 < hi; j0 += 64 * SCAN_U) {
+        uint32_t bj[SCAN_U];
+#pragma unroll
+        for (int u = 0; u < SCAN_U; ++u) {
+            const int32_t j = j0 + 64 * u;
+            bj[u] = j < hi ? a.B.sb[j] : ~xb;
+        }
+#pragma unroll
+        for (int u = 0; u < SCAN_U; ++u) {
+            const int32_t j = j0 + 64 * u;
+            const int db = popc32(xb ^ bj[u]);
+            if (SAME_ALPHA) {
+                if (db == 0)
+                    acc += a.cs[j] * d;
+                else if (db <= 4)
+                    acc += a.cs[j] * coupling_value(eri, h, a.norb, pair_desc(xa, xb, aj, bj[u]), xa, xb);
+            } else if (db == 2) {
+                acc += a.cs[j] * coupling_value(eri, h, a.norb, pair_desc(xa, xb, aj, bj[u]), xa, xb);
+            }
+        }
+    }
+}
+
 // One wave per candidate x = (xa, xb).  Its partners in B fall into three
 // disjoint classes, each read from one kind of group:
 //   same alpha string        the alpha group of xa (beta differs by 0, 1 or 2)
 //   same beta string         the beta group of xb (alpha differs by 1 or 2)
-//   one move in each spin    the alpha groups of the na (norb - na) strings one
-//                            move from xa, keeping beta strings one move from xb
+//   one move in each spin    the alpha groups of the strings one move from xa
+//                            (from the link table when xa is an alpha string
+//                            of B, else by search), keeping beta strings one
+//                            move from xb
 // The diagonal enters through the first class when x lies in B.
 template <bool USE_LDS>
-__global__ __launch_bounds__(PT_NT) void k_pt2(Pt2Args a) {
+__global__ __launch_bounds__(PT_NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_pt2(Pt2Args a) {
     extern __shared__ double smem[];
     const double *eri, *h;
     stage_integrals<USE_LDS>(smem, a.eri, a.h, a.npack, a.norb, eri, h);
@@ -281,48 +318,44 @@ __global__ __launch_bounds__(PT_NT) void k_pt2(Pt2Args a) {
         const double d = diag_value(eri, h, norb, a.ecore, xa, xb);
         double acc = 0.0;
         const int32_t g = find_u32(a.B.ua, a.B.nua, xa);
-        if (g >= 0) {
-            const int32_t end = a.B.ga[g + 1];
-            for (int32_t j = a.B.ga[g] + lane; j < end; j += 64) {
-                const uint32_t bj = a.B.sb[j];
-                const int db = popc32(xb ^ bj);
-                if (db == 0)
-                    acc += a.cs[j] * d;
-                else if (db <= 4)
-                    acc += a.cs[j] * coupling_value(eri, h, norb, pair_desc(xa, xb, xa, bj), xa, xb);
-            }
-        }
+        if (g >= 0) scan_alpha_group<true>(a, eri, h, a.B.ga[g], a.B.ga[g + 1], xa, xb, xa, d, lane, acc);
         const int32_t gbx = find_u32(a.B.ub, a.B.nub, xb);
         if (gbx >= 0) {
             const int32_t end = a.B.gb[gbx + 1];
-            for (int32_t u = a.B.gb[gbx] + lane; u < end; u += 64) {
-                const uint32_t aj = a.B.bm_alpha[u];
-                const int da = popc32(xa ^ aj);
-                if (da != 0 && da <= 4)
-                    acc += a.cs[a.B.bperm[u]] *
-                           coupling_value(eri, h, norb, pair_desc(xa, xb, aj, xb), xa, xb);
+            for (int32_t u0 = a.B.gb[gbx] + lane; u0 < end; u0 += 64 * SCAN_U) {
+                uint32_t aj[SCAN_U];
+#pragma unroll
+                for (int u = 0; u < SCAN_U; ++u) {
+                    const int32_t q = u0 + 64 * u;
+                    aj[u] = q < end ? a.B.bm_alpha[q] : xa;
+                }
+#pragma unroll
+                for (int u = 0; u < SCAN_U; ++u) {
+                    const int da = popc32(xa ^ aj[u]);
+                    if (da != 0 && da <= 4)
+                        acc += a.cs[a.B.bperm[u0 + 64 * u]] *
+                               coupling_value(eri, h, norb, pair_desc(xa, xb, aj[u], xb), xa, xb);
+                }
             }
         }
-        for (int m0 = 0; m0 < nmov; m0 += 64) {
+        const int nlink = g >= 0 ? a.alink_ptr[g] : nmov;
+        for (int m0 = 0; m0 < nlink; m0 += 64) {
             const int m = m0 + lane;
             int32_t gm = -1;
-            uint32_t am = 0;
-            if (m < nmov) {
-                am = xa ^ (1u << nth_bit(xa, m / nva)) ^ (1u << nth_bit(~xa & full, m % nva));
-                gm = find_u32(a.B.ua, a.B.nua, am);
+            if (m < nlink) {
+                if (g >= 0) {
+                    gm = a.alink[(int64_t)g * a.alink_max + m];
+                } else {
+                    const uint32_t am = xa ^ (1u << nth_bit(xa, m / nva)) ^ (1u << nth_bit(~xa & full, m % nva));
+                    gm = find_u32(a.B.ua, a.B.nua, am);
+                }
             }
             uint64_t found = __ballot(gm >= 0);
             while (found) {
                 const int src = __builtin_ctzll(found);
                 found &= found - 1;
                 const int32_t gg = __shfl(gm, src, 64);
-                const uint32_t aj = (uint32_t)__shfl((int)am, src, 64);
-                const int32_t end = a.B.ga[gg + 1];
-                for (int32_t j = a.B.ga[gg] + lane; j < end; j += 64) {
-                    const uint32_t bj = a.B.sb[j];
-                    if (popc32(xb ^ bj) == 2)
-                        acc += a.cs[j] * coupling_value(eri, h, norb, pair_desc(xa, xb, aj, bj), xa, xb);
-                }
+                scan_alpha_group<false>(a, eri, h, a.B.ga[gg], a.B.ga[gg + 1], xa, xb, a.B.ua[gg], d, lane, acc);
             }
         }
         acc = wave_sum_d(acc);
@@ -468,8 +501,8 @@ void pt2(Ctx &c, const double *coeffs, bool sorted, double e0, int64_t ncand, co
     DBuf<unsigned> bad;
     bad.ensure(1);
     HQ_CHECK(hipMemsetAsync(bad.p, 0, sizeof(unsigned), s));
-    Pt2Args pa{tables_of(c), c.norb, neri_packed(c.norb), c.na, c.nb, c.ecore, e0, ncand, ca, cb, csp,
-               c.d_eri.p, c.d_h.p, numer, hxx, score, bad.p};
+    Pt2Args pa{tables_of(c), c.norb, neri_packed(c.norb), c.na, c.nb, c.alink_max, c.alink_ptr.p, c.alink.p,
+               c.ecore, e0, ncand, ca, cb, csp, c.d_eri.p, c.d_h.p, numer, hxx, score, bad.p};
     const size_t lds = integral_lds(c);
     const int cus = device_cus(c);
     const int64_t want = (ncand + PT_NT / 64 - 1) / (PT_NT / 64);
