@@ -26,8 +26,8 @@ cpu_baseline times the CPU oracle's matrix-free sigma on a bounded row sample.
 After the timed steps, the "select" object times one pass of the selection
 steps that follow the solve (Sec. 2.2): the classical expansion of the 1000
 largest |c| of the FP64 eigenvector (Eq. 2), the PT2 score of every expanded
-determinant (Eq. 3) and the top 1e5 by score, with the oracle's PT2 rate on a
-sample beside it.
+determinant (Eq. 3), the top 1e5 by score and the spin-marginal teacher
+weights (Eqs. 5-6), with the oracle's PT2 rate on a sample beside it.
 """
 import argparse
 import json
@@ -118,12 +118,12 @@ def sequential_batch(hq, insts, block, tol):
 def selection_pass(hq, solver, c, e0, ntop, keep, reps=3):
     """One pass of the selection steps that follow the solve, on the solved
     determinant set: classical expansion of the ntop largest |c| (Eq. 2),
-    PT2 scores of every expanded determinant (Eq. 3), and the top `keep` of
-    them.  Median wall time of each phase over `reps` passes (each call
+    PT2 scores of every expanded determinant (Eq. 3), the top `keep` of
+    them, and the spin-marginal teacher weights of c (Eqs. 5-6).  Median wall time of each phase over `reps` passes (each call
     synchronizes the library's stream)."""
     import numpy as np
     import torch
-    times = {"expand": [], "pt2": [], "top_k": []}
+    times = {"expand": [], "pt2": [], "top_k": [], "weights": []}
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -135,6 +135,9 @@ def selection_pass(hq, solver, c, e0, ntop, keep, reps=3):
         idx = solver.top_k(score, k, largest=True)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
+        solver.teacher_weights(c)
+        torch.cuda.synchronize()
+        times["weights"].append(time.perf_counter() - t3)
         times["expand"].append(t1 - t0)
         times["pt2"].append(t2 - t1)
         times["top_k"].append(t3 - t2)
@@ -142,6 +145,7 @@ def selection_pass(hq, solver, c, e0, ntop, keep, reps=3):
     n = len(ya)
     return {"ntop": ntop, "candidates": n, "keep": k,
             "ms_expand": med["expand"], "ms_pt2": med["pt2"], "ms_top_k": med["top_k"],
+            "ms_teacher_weights": med["weights"],
             "pt2_candidates_per_s": n / (med["pt2"] * 1e-3),
             "max_score": float(score[idx[0]].item()) if n else None}, (ya, yb)
 

@@ -390,6 +390,30 @@ int hinqs_pt2(hinqs_ctx *ctx, const double *coeffs, double e0, int64_t ncand,
 int hinqs_top_k(hinqs_ctx *ctx, int64_t n, const double *values, int64_t k, int flags, int32_t *idx);
 
 /*
+ * Spin-marginal teacher weights of a vector over B (paper Sec. 2.2, Step 4,
+ * Eqs. 5-6):
+ *   p_alpha(s) = sum of c_x^2 over the x in B with alpha string s
+ *   p_beta(s)  = sum of c_x^2 over the x in B with beta string s
+ *   weights[x] = p_alpha(alpha_x) p_beta(beta_x) / Z,  Z = the sum over B
+ *                of those products, so the weights sum to 1
+ *   coeffs   device, ndet doubles (caller order unless HINQS_SORTED_ORDER)
+ *   weights  device, ndet doubles (same order), or NULL
+ *   p_alpha  device, n_alpha_strings doubles indexed like the ascending
+ *            distinct alpha strings of hinqs_distinct_strings, or NULL
+ *   p_beta   device, n_beta_strings doubles, likewise, or NULL
+ * Sums run in a fixed order (bitwise reproducible).  The weights keep no
+ * phase and no alpha-beta correlation of c, as the factorized target does.
+ * Errors: NOT_READY (no determinants), INVALID_ARG (all coefficients zero),
+ * NONFINITE, OOM, HIP.
+ */
+int hinqs_teacher_weights(hinqs_ctx *ctx, const double *coeffs, double *weights, double *p_alpha,
+                          double *p_beta, int flags);
+
+/* The distinct alpha and beta strings of B in ascending order (device,
+ * n_alpha_strings and n_beta_strings uint64; either may be NULL). */
+int hinqs_distinct_strings(hinqs_ctx *ctx, uint64_t *alpha, uint64_t *beta);
+
+/*
  * Host-only helper (no device work): descriptor of the pair x_i <- x_j as
  * the coupling enumerator encodes it, or 0 if the pair differs by more than
  * two electrons or not at all.  Used to check the sign rules on the CPU.

@@ -260,3 +260,23 @@ def top_k(values, k, largest=False):
         raise OracleError("NaN in values")
     order = sorted(range(len(v)), key=lambda i: ((-v[i]) if largest else v[i], i))
     return np.array(order[:k], dtype=np.int64)
+
+
+def teacher_weights(alpha, beta, c):
+    """Spin-marginal teacher weights of Sec. 2.2 Step 4 (Eqs. 5-6), c in the
+    order of (alpha, beta): p_alpha(s) sums c^2 over the determinants with
+    alpha string s, p_beta likewise, and w(x) = p_alpha p_beta normalized over
+    the set.  Returns (w, distinct alpha strings, p_alpha, distinct beta
+    strings, p_beta), strings ascending."""
+    a = np.asarray(alpha, dtype=np.uint64)
+    b = np.asarray(beta, dtype=np.uint64)
+    c2 = np.asarray(c, dtype=np.float64) ** 2
+    ua, ia = np.unique(a, return_inverse=True)
+    ub, ib = np.unique(b, return_inverse=True)
+    pa = np.bincount(ia, weights=c2, minlength=len(ua))
+    pb = np.bincount(ib, weights=c2, minlength=len(ub))
+    w = pa[ia] * pb[ib]
+    z = w.sum()
+    if not z > 0:
+        raise OracleError("the weights sum to zero")
+    return w / z, ua, pa, ub, pb

@@ -44,7 +44,8 @@ EXPORTED = ["hinqs_opts_default", "hinqs_create", "hinqs_destroy", "hinqs_last_e
             "hinqs_connectivity", "hinqs_permutation", "hinqs_get_info",
             "hinqs_pair_descriptor", "hinqs_gram", "hinqs_set_determinants_device",
             "hinqs_autotune", "hinqs_batch_clear", "hinqs_batch_add", "hinqs_batch_info",
-            "hinqs_batch_lowest_eigenpair", "hinqs_expand", "hinqs_pt2", "hinqs_top_k"]
+            "hinqs_batch_lowest_eigenpair", "hinqs_expand", "hinqs_pt2", "hinqs_top_k",
+            "hinqs_teacher_weights", "hinqs_distinct_strings"]
 
 
 class HinqsError(RuntimeError):
@@ -136,6 +137,8 @@ def load_library() -> ctypes.CDLL:
             "hinqs_expand": (i32, [P, P, i64, i64, P, P, P, P, i32]),
             "hinqs_pt2": (i32, [P, P, dbl, i64, P, P, P, P, P, i32]),
             "hinqs_top_k": (i32, [P, i64, P, i64, i32, P]),
+            "hinqs_teacher_weights": (i32, [P, P, P, P, P, i32]),
+            "hinqs_distinct_strings": (i32, [P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -476,6 +479,28 @@ class Hinqs:
         self._check(self._lib.hinqs_top_k(self._h, values.numel(), self._ptr(values), int(k),
                                           LARGEST if largest else 0, self._ptr(idx)))
         return idx[:k]
+
+    def teacher_weights(self, c, sorted_order=False):
+        """Spin-marginal teacher weights (Eqs. 5-6): (w over B, p_alpha, p_beta)
+        as float64 device tensors; the marginals follow distinct_strings()."""
+        torch = _torch()
+        self._dev(c, torch.float64)
+        inf = self.info()
+        w = torch.empty(self.ndet, dtype=torch.float64, device=self.device)
+        pa = torch.empty(inf["n_alpha_strings"], dtype=torch.float64, device=self.device)
+        pb = torch.empty(inf["n_beta_strings"], dtype=torch.float64, device=self.device)
+        self._check(self._lib.hinqs_teacher_weights(self._h, self._ptr(c), self._ptr(w), self._ptr(pa),
+                                                    self._ptr(pb), SORTED_ORDER if sorted_order else 0))
+        return w, pa, pb
+
+    def distinct_strings(self):
+        """Ascending distinct alpha and beta strings of B (int64 device tensors)."""
+        torch = _torch()
+        inf = self.info()
+        a = torch.empty(inf["n_alpha_strings"], dtype=torch.int64, device=self.device)
+        b = torch.empty(inf["n_beta_strings"], dtype=torch.int64, device=self.device)
+        self._check(self._lib.hinqs_distinct_strings(self._h, self._ptr(a), self._ptr(b)))
+        return a, b
 
     def info(self):
         inf = Info()

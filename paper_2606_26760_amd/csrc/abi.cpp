@@ -386,6 +386,24 @@ int hinqs_top_k(hinqs_ctx *ctx, int64_t n, const double *values, int64_t k, int 
     });
 }
 
+int hinqs_teacher_weights(hinqs_ctx *ctx, const double *coeffs, double *weights, double *p_alpha,
+                          double *p_beta, int flags) {
+    return guarded(ctx, [&](Ctx &c) {
+        if (!c.have_dets) throw Error(HINQS_E_NOT_READY, "determinants are not set");
+        if (!coeffs) throw Error(HINQS_E_INVALID_ARG, "null coefficients");
+        teacher_weights(c, coeffs, (flags & HINQS_SORTED_ORDER) != 0, weights, p_alpha, p_beta);
+        return HINQS_OK;
+    });
+}
+
+int hinqs_distinct_strings(hinqs_ctx *ctx, uint64_t *alpha, uint64_t *beta) {
+    return guarded(ctx, [&](Ctx &c) {
+        if (!c.have_dets) throw Error(HINQS_E_NOT_READY, "determinants are not set");
+        distinct_strings(c, alpha, beta);
+        return HINQS_OK;
+    });
+}
+
 uint32_t hinqs_pair_descriptor(uint64_t alpha_i, uint64_t beta_i, uint64_t alpha_j, uint64_t beta_j) {
     return pair_desc((uint32_t)alpha_i, (uint32_t)beta_i, (uint32_t)alpha_j, (uint32_t)beta_j);
 }

@@ -329,6 +329,10 @@ int64_t expand(Ctx &c, const double *coeffs, bool sorted, int64_t ntop, int64_t 
 void pt2(Ctx &c, const double *coeffs, bool sorted, double e0, int64_t ncand, const uint64_t *ca,
          const uint64_t *cb, double *numer, double *hxx, double *score);
 
+// Teacher weights (weights.hip): c in caller order unless `sorted`.
+void teacher_weights(Ctx &c, const double *coeffs, bool sorted, double *w, double *p_alpha, double *p_beta);
+void distinct_strings(Ctx &c, uint64_t *alpha, uint64_t *beta);
+
 // Davidson (davidson.hip)
 int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, double *coeffs,
              hinqs_stats *st);

@@ -213,3 +213,58 @@ def test_top_k_matches_oracle(n):
     with pytest.raises(hq.HinqsError) as ex:
         s.top_k(torch.from_numpy(v).cuda(), 1)
     assert ex.value.name == "NONFINITE"
+
+
+# ------------------------------------------------------------ teacher weights
+# Bars: every marginal and weight within 1e-12 relative (sums of positive
+# terms: the oracle's sequential bincount over groups of <= 2,284 entries is
+# the larger rounding, <= 2.6e-13 relative); sorted and caller order bitwise
+# equal after the permutation.
+def _check_weights(s, a, b, c):
+    w, pa, pb = s.teacher_weights(torch.from_numpy(c).cuda())
+    rw, rua, rpa, rub, rpb = oracle.teacher_weights(a, b, c)
+    ua, ub = s.distinct_strings()
+    assert np.array_equal(_strings(ua), rua) and np.array_equal(_strings(ub), rub)
+    for got, ref in ((w, rw), (pa, rpa), (pb, rpb)):
+        got = got.cpu().numpy()
+        assert np.all(np.abs(got - ref) <= 1e-12 * np.abs(ref)), float(np.max(np.abs(got - ref) / np.abs(ref)))
+    return w
+
+
+def test_teacher_weights_cas10(cas10):
+    ints, a, b, cfg, s, o = cas10
+    log("teacher weights cas10")
+    c = _coeffs(len(a), 17)
+    w = _check_weights(s, a, b, c)
+    perm = s.permutation().cpu().numpy().astype(np.int64)
+    ws, pas, pbs = s.teacher_weights(torch.from_numpy(c[perm]).cuda(), sorted_order=True)
+    assert torch.equal(ws.cpu(), w.cpu()[perm])
+    with pytest.raises(hq.HinqsError) as ex:
+        s.teacher_weights(torch.zeros(len(a), dtype=torch.float64, device="cuda"))
+    assert ex.value.name == "INVALID_ARG"
+    bad = torch.from_numpy(c).cuda()
+    bad[5] = float("inf")
+    with pytest.raises(hq.HinqsError) as ex:
+        s.teacher_weights(bad)
+    assert ex.value.name == "NONFINITE"
+
+
+def test_teacher_weights_full_space_product_state():
+    """Product vector on the full CAS(6,6) space: the weights are |c|^2."""
+    log("teacher weights: product state")
+    ints, a, b, cfg = W.config_inputs(0)
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    sa, sb = W.fci_strings(6, 3), W.fci_strings(6, 3)
+    rng = np.random.default_rng(21)
+    u, v = rng.standard_normal(len(sa)), rng.standard_normal(len(sb))
+    c = u[np.searchsorted(sa, a)] * v[np.searchsorted(sb, b)]
+    c /= np.linalg.norm(c)
+    w = _check_weights(s, a, b, c).cpu().numpy()
+    assert np.allclose(w, c ** 2, rtol=1e-12, atol=1e-18)
+
+
+def test_teacher_weights_full_size():
+    ints, a, b, cfg = W.config_inputs(2)
+    log("teacher weights cas16 1e6")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    _check_weights(s, a, b, _coeffs(len(a), 99))

@@ -124,3 +124,64 @@ def test_top_k_definition():
     assert list(oracle.top_k(v, 9, largest=True)) == [5, 7, 0, 4, 2, 3, 1, 8, 6]
     with pytest.raises(oracle.OracleError):
         oracle.top_k([1.0, float("nan")], 1)
+
+
+def test_teacher_weights_hand_example():
+    """Three determinants (a1,b1), (a1,b2), (a2,b1) with c = (0.6, 0, 0.8):
+    p_alpha = (0.36, 0.64), p_beta = (1.0, 0.0), so w = (0.36, 0, 0.64)."""
+    a = np.array([3, 3, 5], dtype=np.uint64)
+    b = np.array([3, 6, 3], dtype=np.uint64)
+    w, ua, pa, ub, pb = oracle.teacher_weights(a, b, [0.6, 0.0, 0.8])
+    assert list(ua) == [3, 5] and list(ub) == [3, 6]
+    assert np.allclose(pa, [0.36, 0.64], rtol=0, atol=1e-15)
+    assert np.allclose(pb, [1.0, 0.0], rtol=0, atol=1e-15)
+    assert np.allclose(w, [0.36, 0.0, 0.64], rtol=0, atol=1e-15)
+    # a sign flip or an overall scale changes nothing; one determinant gets weight 1
+    w2 = oracle.teacher_weights(a, b, [-1.2, 0.0, 1.6])[0]
+    assert np.allclose(w2, w, rtol=0, atol=1e-15)
+    assert oracle.teacher_weights(a[:1], b[:1], [0.3])[0].tolist() == [1.0]
+    with pytest.raises(oracle.OracleError):
+        oracle.teacher_weights(a, b, [0.0, 0.0, 0.0])
+
+
+def test_teacher_weights_product_state_is_exact():
+    """On the full space a product vector c(alpha, beta) = u(alpha) v(beta) has
+    marginals u^2 and v^2 (unit u, v), and the factorized weights reproduce
+    |c|^2 exactly (the factorization drops nothing)."""
+    norb, na, nb = 6, 2, 3
+    sa = W.fci_strings(norb, na)
+    sb = W.fci_strings(norb, nb)
+    rng = np.random.default_rng(4)
+    u = rng.standard_normal(len(sa))
+    v = rng.standard_normal(len(sb))
+    u /= np.linalg.norm(u)
+    v /= np.linalg.norm(v)
+    fa, fb = W.full_space(norb, na, nb)
+    ia = np.searchsorted(sa, fa)
+    ib = np.searchsorted(sb, fb)
+    perm = rng.permutation(len(fa))
+    c = (u[ia] * v[ib])[perm]
+    w, ua, pa, ub, pb = oracle.teacher_weights(fa[perm], fb[perm], c)
+    assert np.array_equal(ua, np.sort(sa)) and np.array_equal(ub, np.sort(sb))
+    assert np.allclose(pa, u[np.argsort(sa)] ** 2, rtol=1e-13, atol=1e-16)
+    assert np.allclose(pb, v[np.argsort(sb)] ** 2, rtol=1e-13, atol=1e-16)
+    assert np.allclose(w, c ** 2, rtol=1e-12, atol=1e-17)
+    assert abs(pa.sum() - 1) < 1e-14 and abs(pb.sum() - 1) < 1e-14 and abs(w.sum() - 1) < 1e-14
+
+
+def test_teacher_weights_brute_force():
+    """Tiny random set: every weight against a direct double loop over B."""
+    norb, na, nb = 5, 2, 2
+    fa, fb = W.full_space(norb, na, nb)
+    rng = np.random.default_rng(8)
+    pick = rng.choice(len(fa), 40, replace=False)
+    a, b = fa[pick], fb[pick]
+    c = rng.standard_normal(40)
+    w = oracle.teacher_weights(a, b, c)[0]
+    raw = []
+    for i in range(40):
+        pa = sum(c[j] ** 2 for j in range(40) if a[j] == a[i])
+        pb = sum(c[j] ** 2 for j in range(40) if b[j] == b[i])
+        raw.append(pa * pb)
+    raw = np.array(raw)
+    assert np.allclose(w, raw / raw.sum(), rtol=1e-13, atol=0)
