@@ -27,7 +27,10 @@ After the timed steps, the "select" object times one pass of the selection
 steps that follow the solve (Sec. 2.2): the classical expansion of the 1000
 largest |c| of the FP64 eigenvector (Eq. 2), the PT2 score of every expanded
 determinant (Eq. 3), the top 1e5 by score and the spin-marginal teacher
-weights (Eqs. 5-6), with the oracle's PT2 rate on a sample beside it.
+weights (Eqs. 5-6), with the oracle's PT2 rate on a sample beside it.  The "iteration" object then completes that outer iteration:
+PT2 of the set's own members (their eviction ranking), the growth rule
+(append the 1e5 best-scored, cap at 1.05e6) applied as an incremental update
+of the couplings, and the FP64 Davidson warm-started from the carried vector.
 """
 import argparse
 import json
@@ -148,6 +151,28 @@ def selection_pass(hq, solver, c, e0, ntop, keep, reps=3):
             "ms_teacher_weights": med["weights"],
             "pt2_candidates_per_s": n / (med["pt2"] * 1e-3),
             "max_score": float(score[idx[0]].item()) if n else None}, (ya, yb)
+
+
+def outer_iteration(hq, solver, c, e0, ya, yb, cand_score, keep, b_max, k, tol):
+    """The rest of one outer iteration after scoring (Sec. 2.2, Steps 2-3 at
+    t >= 2): PT2 scores of the current set (its eviction ranking), the growth
+    rule (append the `keep` best candidates, cap at b_max), then the FP64
+    Davidson warm-started from the carried eigenvector."""
+    import torch
+    a_b, b_b = solver.determinants()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, bscore = solver.pt2(c, e0, a_b, b_b)
+    t1 = time.perf_counter()
+    c_new, _, ms_upd = solver.grow_basis(ya, yb, cand_score, keep, basis_score=bscore, b_max=b_max, coeffs=c)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    e1, _, st = solver.lowest_eigenpair(guess=c_new, tol=tol, block=k)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    return {"ndet_new": solver.ndet, "ms_rescore_set": (t1 - t0) * 1e3, "ms_grow_update": (t2 - t1) * 1e3,
+            "ms_update_kernels": ms_upd, "ms_warm_solve": (t3 - t2) * 1e3, "warm_iterations": st["iterations"],
+            "energy": e1, "energy_drop": e0 - e1}
 
 
 def cpu_pt2_rate(o, c, e0, ya, yb, n=2000):
@@ -329,6 +354,13 @@ def main():
     out["select"] = dict(sel, workload=f"expansion of the {args.ntop} largest |c| of the FP64 eigenvector "
                                        f"of the {D}-determinant set, PT2 of every expanded determinant, "
                                        f"top {args.keep} by score")
+    _, _, score = solver.pt2(last["c64"], e_sel, ya, yb)
+    out["iteration"] = dict(outer_iteration(hq, solver, last["c64"], e_sel, ya, yb, score, args.keep,
+                                            D + args.keep // 2, cfg.k, cfg.tol),
+                            workload=f"append the {args.keep} best-scored expanded determinants, cap at "
+                                     f"{D + args.keep // 2} (the lowest PT2 scores of the set and the "
+                                     f"appended ones go), FP64 Davidson to {cfg.tol} from the carried vector; "
+                                     f"cold FP64 solve of the original set: {res[-1][1][1]['iterations']} iterations")
     if not args.no_cpu_baseline:
         import oracle
         o = oracle.Oracle.from_inputs(ints, alpha, beta, cfg.na, cfg.nb)

@@ -65,6 +65,10 @@ extern "C" {
 #define HINQS_NO_GRAPH     4   /* hinqs_opts.flags, batched solves: launch each kernel directly */
 #define HINQS_LARGEST      8   /* hinqs_top_k: select the largest values instead of the smallest */
 
+/* hinqs_grow_basis modes */
+#define HINQS_GROW_APPEND   0   /* append the K best candidates, then cap the set at b_max */
+#define HINQS_GROW_REBUILD  1   /* keep the K best of the set and the candidates together */
+
 /* excitation classes stored in a coupling descriptor (bits 0..2) */
 #define HINQS_EXC_1A   1   /* single, alpha */
 #define HINQS_EXC_1B   2   /* single, beta */
@@ -412,6 +416,76 @@ int hinqs_teacher_weights(hinqs_ctx *ctx, const double *coeffs, double *weights,
 /* The distinct alpha and beta strings of B in ascending order (device,
  * n_alpha_strings and n_beta_strings uint64; either may be NULL). */
 int hinqs_distinct_strings(hinqs_ctx *ctx, uint64_t *alpha, uint64_t *beta);
+
+/*
+ * Incremental update of the determinant set (paper Sec. 2.2: from the second
+ * iteration on, Step 2 appends the best-scored new candidates to B and
+ * evicts the lowest-scored entries beyond a cap, and Step 3 keeps its state
+ * across iterations and warm-starts from the previous eigenvector).
+ * The new set B' lists the kept determinants (B without the evicted ones, in
+ * their caller order) followed by the appended ones in the given order, and
+ * replaces the context's set: afterwards every call sees B' exactly as
+ * hinqs_set_determinants would have built it (the same coupled pairs with
+ * the same descriptors and values; entries within a row may come in another
+ * order, so sigma products agree to rounding).  Couplings between kept
+ * determinants are carried over with their values; only pairs that involve
+ * an appended determinant are enumerated and evaluated.
+ *   n_evict, evict   device, n_evict distinct int32: caller indices of B (or
+ *                    sorted positions with HINQS_SORTED_ORDER); may be NULL
+ *                    when n_evict is 0
+ *   n_add, add_alpha, add_beta  device, n_add uint64 each, determinants not in
+ *                    B' otherwise (one that is being evicted may come back);
+ *                    may be NULL when n_add is 0
+ *   coeffs_old       device, old ndet doubles (old caller order, or old sorted
+ *                    order with HINQS_SORTED_ORDER), or NULL
+ *   coeffs_new       device, new ndet doubles (new order), or NULL: the warm
+ *                    start, coeffs_old on the kept determinants and 0 on the
+ *                    appended ones (not renormalized)
+ *   ms               host, may be NULL: wall time of the update in ms
+ * Device memory for both the old and the new couplings is held during the
+ * call.  On INVALID_ARG, BAD_OCCUPATION or DUPLICATE the context is left
+ * unchanged; after OOM or HIP it needs hinqs_set_determinants again.
+ * Errors: NOT_READY, INVALID_ARG (index out of range or repeated, empty
+ * result), BAD_OCCUPATION, DUPLICATE, UNSUPPORTED, OOM, HIP.
+ */
+int hinqs_update_determinants(hinqs_ctx *ctx, int64_t n_evict, const int32_t *evict, int64_t n_add,
+                              const uint64_t *add_alpha, const uint64_t *add_beta, const double *coeffs_old,
+                              double *coeffs_new, int flags, double *ms);
+
+/*
+ * The basis-update rules of paper Sec. 2.2, Step 2, applied with
+ * hinqs_update_determinants (same carried couplings, same warm start):
+ *   HINQS_GROW_APPEND (iterations t >= 2): the k candidates of highest score
+ *     are appended, highest first; if the set would then exceed b_max
+ *     (b_max > 0), the lowest-scored entries of the set and of those k are
+ *     dropped until b_max remain.
+ *   HINQS_GROW_REBUILD (iteration t = 1): the set becomes the k highest-scored
+ *     of the current set and the candidates together, with no cap; kept
+ *     members stay in their order, chosen candidates follow, highest first.
+ * Ties go to the lower index of the list (current set in caller order, then
+ * candidates); -0.0 equals +0.0; NaN scores give NONFINITE.
+ *   ncand, cand_alpha, cand_beta, cand_score  device, candidates outside the
+ *                    set (uint64 strings, double scores)
+ *   k                candidates to append / size of the rebuilt set
+ *   basis_score      device, ndet doubles (caller order): required by
+ *                    REBUILD, by a capped APPEND and for score_new
+ *   b_max            cap (0: none)
+ *   coeffs_old/new   as for hinqs_update_determinants (coeffs_new holds at
+ *                    least ndet + k doubles)
+ *   score_new        device, at least ndet + k doubles, or NULL: the scores of
+ *                    the new set in its caller order
+ *   ndet_new         host, may be NULL; ms host, may be NULL
+ * Errors: as hinqs_top_k and hinqs_update_determinants; INVALID_ARG for a
+ * missing basis_score or an unknown mode.
+ */
+int hinqs_grow_basis(hinqs_ctx *ctx, int mode, int64_t ncand, const uint64_t *cand_alpha,
+                     const uint64_t *cand_beta, const double *cand_score, int64_t k,
+                     const double *basis_score, int64_t b_max, const double *coeffs_old,
+                     double *coeffs_new, double *score_new, int64_t *ndet_new, double *ms);
+
+/* The determinant strings of the current set in caller order (device, ndet
+ * uint64 each; either may be NULL). */
+int hinqs_get_determinants(hinqs_ctx *ctx, uint64_t *alpha, uint64_t *beta);
 
 /*
  * Host-only helper (no device work): descriptor of the pair x_i <- x_j as

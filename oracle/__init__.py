@@ -280,3 +280,27 @@ def teacher_weights(alpha, beta, c):
     if not z > 0:
         raise OracleError("the weights sum to zero")
     return w / z, ua, pa, ub, pb
+
+
+def grow_basis(basis_score, cand_score, k, b_max=0, rebuild=False):
+    """The basis-update rules of Sec. 2.2 Step 2, on indices: returns (kept
+    basis indices in their order, chosen candidate indices in append order).
+    Append (t >= 2): the k best candidates, best first; if the set then
+    exceeds b_max (> 0), the lowest-scored of the set and of those k are
+    dropped.  Rebuild (t = 1): the k best of set and candidates together.
+    Ties by the lower index of [set; candidates] (via top_k)."""
+    nb = len(basis_score) if basis_score is not None else 0
+    if rebuild:
+        comb = list(basis_score) + list(cand_score)
+        chosen = [int(i) for i in top_k(comb, min(k, len(comb)), largest=True)]
+        keep = set(i for i in chosen if i < nb)
+        return [i for i in range(nb) if i in keep], [i - nb for i in chosen if i >= nb]
+    kk = min(k, len(cand_score))
+    apps = [int(i) for i in top_k(cand_score, kk, largest=True)] if kk else []
+    kept = list(range(nb))
+    if b_max and nb + kk > b_max:
+        comb = list(basis_score) + [float(cand_score[t]) for t in apps]
+        low = set(int(i) for i in top_k(comb, nb + kk - b_max))
+        kept = [i for i in range(nb) if i not in low]
+        apps = [t for j, t in enumerate(apps) if nb + j not in low]
+    return kept, apps

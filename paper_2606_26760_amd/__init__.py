@@ -36,6 +36,7 @@ SORTED_ORDER = 1
 AUTOTUNE = 2
 NO_GRAPH = 4
 LARGEST = 8
+GROW_APPEND, GROW_REBUILD = 0, 1
 EXC_1A, EXC_1B, EXC_2AA, EXC_2BB, EXC_2AB = 1, 2, 3, 4, 5
 
 EXPORTED = ["hinqs_opts_default", "hinqs_create", "hinqs_destroy", "hinqs_last_error",
@@ -45,7 +46,8 @@ EXPORTED = ["hinqs_opts_default", "hinqs_create", "hinqs_destroy", "hinqs_last_e
             "hinqs_pair_descriptor", "hinqs_gram", "hinqs_set_determinants_device",
             "hinqs_autotune", "hinqs_batch_clear", "hinqs_batch_add", "hinqs_batch_info",
             "hinqs_batch_lowest_eigenpair", "hinqs_expand", "hinqs_pt2", "hinqs_top_k",
-            "hinqs_teacher_weights", "hinqs_distinct_strings"]
+            "hinqs_teacher_weights", "hinqs_distinct_strings", "hinqs_update_determinants",
+            "hinqs_grow_basis", "hinqs_get_determinants"]
 
 
 class HinqsError(RuntimeError):
@@ -139,6 +141,9 @@ def load_library() -> ctypes.CDLL:
             "hinqs_top_k": (i32, [P, i64, P, i64, i32, P]),
             "hinqs_teacher_weights": (i32, [P, P, P, P, P, i32]),
             "hinqs_distinct_strings": (i32, [P, P, P]),
+            "hinqs_update_determinants": (i32, [P, i64, P, i64, P, P, P, P, i32, P]),
+            "hinqs_grow_basis": (i32, [P, i32, i64, P, P, P, i64, P, i64, P, P, P, P, P]),
+            "hinqs_get_determinants": (i32, [P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -500,6 +505,76 @@ class Hinqs:
         a = torch.empty(inf["n_alpha_strings"], dtype=torch.int64, device=self.device)
         b = torch.empty(inf["n_beta_strings"], dtype=torch.int64, device=self.device)
         self._check(self._lib.hinqs_distinct_strings(self._h, self._ptr(a), self._ptr(b)))
+        return a, b
+
+    def update_determinants(self, add_alpha=None, add_beta=None, evict=None, coeffs=None, sorted_order=False):
+        """Evict (int32 indices) and append (strings) determinants in place; returns
+        (warm-start vector on the new set or None, update wall ms)."""
+        torch = _torch()
+        na_ = 0
+        pa = pb = None
+        if add_alpha is not None:
+            ta, tb = self._dev_strings(add_alpha), self._dev_strings(add_beta)
+            if ta.shape != tb.shape or ta.dim() != 1:
+                raise ValueError("appended alpha and beta must be 1-D and equally long")
+            na_ = ta.numel()
+            pa, pb = self._ptr(ta), self._ptr(tb)
+        ne = 0
+        pe = None
+        if evict is not None:
+            te = evict if isinstance(evict, torch.Tensor) else torch.as_tensor(np.asarray(evict), dtype=torch.int32)
+            te = te.to(device=self.device, dtype=torch.int32).contiguous()
+            ne = te.numel()
+            pe = self._ptr(te)
+        c_new = None
+        pc = pn = None
+        if coeffs is not None:
+            self._dev(coeffs, torch.float64)
+            pc = self._ptr(coeffs)
+            # sized for the largest possible new set; trimmed once the size is known
+            c_new = torch.empty(self.ndet + na_, dtype=torch.float64, device=self.device)
+            pn = self._ptr(c_new)
+        ms = ctypes.c_double(0.0)
+        self._check(self._lib.hinqs_update_determinants(self._h, ne, pe, na_, pa, pb, pc, pn,
+                                                        SORTED_ORDER if sorted_order else 0, ctypes.byref(ms)))
+        self.ndet = self.info()["ndet"]
+        return (c_new[:self.ndet] if c_new is not None else None), ms.value
+
+    def grow_basis(self, cand_alpha, cand_beta, cand_score, k, basis_score=None, b_max=0, coeffs=None,
+                   rebuild=False):
+        """Step-2 basis rules (append the k best candidates and cap at b_max, or
+        rebuild from the k best of set + candidates).  Returns (warm start or
+        None, scores of the new set or None, update ms)."""
+        torch = _torch()
+        ca, cb = self._dev_strings(cand_alpha), self._dev_strings(cand_beta)
+        self._dev(cand_score, torch.float64)
+        n = ca.numel()
+        room = self.ndet + int(k)
+        pc = pn = ps = pbs = None
+        c_new = s_new = None
+        if coeffs is not None:
+            self._dev(coeffs, torch.float64)
+            c_new = torch.empty(room, dtype=torch.float64, device=self.device)
+            pc, pn = self._ptr(coeffs), self._ptr(c_new)
+        if basis_score is not None:
+            self._dev(basis_score, torch.float64)
+            s_new = torch.empty(room, dtype=torch.float64, device=self.device)
+            pbs, ps = self._ptr(basis_score), self._ptr(s_new)
+        nn = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        self._check(self._lib.hinqs_grow_basis(
+            self._h, GROW_REBUILD if rebuild else GROW_APPEND, n, self._ptr(ca), self._ptr(cb),
+            self._ptr(cand_score), int(k), pbs, int(b_max), pc, pn, ps, ctypes.byref(nn), ctypes.byref(ms)))
+        self.ndet = nn.value
+        return (c_new[:self.ndet] if c_new is not None else None,
+                s_new[:self.ndet] if s_new is not None else None, ms.value)
+
+    def determinants(self):
+        """(alpha, beta) of the current set in caller order (int64 device tensors)."""
+        torch = _torch()
+        a = torch.empty(self.ndet, dtype=torch.int64, device=self.device)
+        b = torch.empty(self.ndet, dtype=torch.int64, device=self.device)
+        self._check(self._lib.hinqs_get_determinants(self._h, self._ptr(a), self._ptr(b)))
         return a, b
 
     def info(self):

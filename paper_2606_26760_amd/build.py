@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhinqs.so")
-SOURCES = ["scan.hip", "dets.hip", "connect.hip", "elements.hip", "sigma.hip", "autotune.hip", "davidson.hip", "batch.hip", "select.hip", "weights.hip",
+SOURCES = ["scan.hip", "dets.hip", "connect.hip", "elements.hip", "sigma.hip", "autotune.hip", "davidson.hip", "batch.hip", "select.hip", "weights.hip", "update.hip",
            "rdm.hip", "abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

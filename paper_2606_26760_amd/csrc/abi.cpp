@@ -1,6 +1,7 @@
 // extern "C" boundary of the library (declared in include/hinqs.h).
 // Each entry point validates its arguments on the host, converts internal
 // exceptions into status codes and records the message for hinqs_last_error.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 
@@ -400,6 +401,54 @@ int hinqs_distinct_strings(hinqs_ctx *ctx, uint64_t *alpha, uint64_t *beta) {
     return guarded(ctx, [&](Ctx &c) {
         if (!c.have_dets) throw Error(HINQS_E_NOT_READY, "determinants are not set");
         distinct_strings(c, alpha, beta);
+        return HINQS_OK;
+    });
+}
+
+int hinqs_update_determinants(hinqs_ctx *ctx, int64_t n_evict, const int32_t *evict, int64_t n_add,
+                              const uint64_t *add_alpha, const uint64_t *add_beta, const double *coeffs_old,
+                              double *coeffs_new, int flags, double *ms) {
+    return guarded(ctx, [&](Ctx &c) {
+        require_dets(c);
+        if (n_evict < 0 || n_add < 0) throw Error(HINQS_E_INVALID_ARG, "negative count");
+        if (n_evict > 0 && !evict) throw Error(HINQS_E_INVALID_ARG, "null evict list");
+        if (n_add > 0 && (!add_alpha || !add_beta)) throw Error(HINQS_E_INVALID_ARG, "null appended strings");
+        if ((coeffs_old == nullptr) != (coeffs_new == nullptr))
+            throw Error(HINQS_E_INVALID_ARG, "coeffs_old and coeffs_new go together");
+        if (n_evict > c.ndet) throw Error(HINQS_E_INVALID_ARG, "more evictions than determinants");
+        update_determinants(c, n_evict, evict, n_add, add_alpha, add_beta, coeffs_old, coeffs_new,
+                            (flags & HINQS_SORTED_ORDER) != 0, ms);
+        return HINQS_OK;
+    });
+}
+
+int hinqs_grow_basis(hinqs_ctx *ctx, int mode, int64_t ncand, const uint64_t *cand_alpha, const uint64_t *cand_beta,
+                     const double *cand_score, int64_t k, const double *basis_score, int64_t b_max,
+                     const double *coeffs_old, double *coeffs_new, double *score_new, int64_t *ndet_new, double *ms) {
+    return guarded(ctx, [&](Ctx &c) {
+        require_dets(c);
+        if (mode != HINQS_GROW_APPEND && mode != HINQS_GROW_REBUILD)
+            throw Error(HINQS_E_INVALID_ARG, "unknown mode");
+        if (ncand < 0 || k < 0 || b_max < 0) throw Error(HINQS_E_INVALID_ARG, "negative size");
+        if (ncand > 0 && (!cand_alpha || !cand_beta || !cand_score))
+            throw Error(HINQS_E_INVALID_ARG, "null candidate arrays");
+        const bool capped = mode == HINQS_GROW_APPEND && b_max > 0 && c.ndet + std::min(k, ncand) > b_max;
+        if (!basis_score && (mode == HINQS_GROW_REBUILD || capped || score_new))
+            throw Error(HINQS_E_INVALID_ARG, "basis_score is required");
+        if ((coeffs_old == nullptr) != (coeffs_new == nullptr))
+            throw Error(HINQS_E_INVALID_ARG, "coeffs_old and coeffs_new go together");
+        if (c.ndet + ncand >= ((int64_t)1 << 31)) throw Error(HINQS_E_UNSUPPORTED, "too many entries");
+        const int64_t n = grow_basis(c, mode, ncand, cand_alpha, cand_beta, cand_score, k, basis_score, b_max,
+                                     coeffs_old, coeffs_new, score_new, ms);
+        if (ndet_new) *ndet_new = n;
+        return HINQS_OK;
+    });
+}
+
+int hinqs_get_determinants(hinqs_ctx *ctx, uint64_t *alpha, uint64_t *beta) {
+    return guarded(ctx, [&](Ctx &c) {
+        if (!c.have_dets) throw Error(HINQS_E_NOT_READY, "determinants are not set");
+        caller_strings(c, alpha, beta);
         return HINQS_OK;
     });
 }

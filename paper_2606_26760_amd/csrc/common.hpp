@@ -286,6 +286,10 @@ void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint6
                         int nb, bool on_device);
 void build_connectivity(Ctx &c);
 void build_elements(Ctx &c);
+// Values of the entries of each row after its first skip[row] (whose values
+// are already in place), and every diagonal element.
+void build_elements_after(Ctx &c, const int64_t *skip);
+
 void export_connectivity(Ctx &c, int64_t *rowptr_c, int32_t *col_c, uint32_t *desc_c);
 // Row ranges with equal coupling counts, one per XCD, from c.rowptr.
 void compute_xcd_rows(Ctx &c);
@@ -332,6 +336,18 @@ void pt2(Ctx &c, const double *coeffs, bool sorted, double e0, int64_t ncand, co
 // Teacher weights (weights.hip): c in caller order unless `sorted`.
 void teacher_weights(Ctx &c, const double *coeffs, bool sorted, double *w, double *p_alpha, double *p_beta);
 void distinct_strings(Ctx &c, uint64_t *alpha, uint64_t *beta);
+
+// Incremental basis update (update.hip): evict (caller indices, or sorted
+// positions when `sorted`), append (device strings), carry c_old over.
+void update_determinants(Ctx &c, int64_t n_evict, const int32_t *evict, int64_t n_add, const uint64_t *add_a,
+                         const uint64_t *add_b, const double *c_old, double *c_new, bool sorted, double *ms_out);
+
+// The basis-growth rules (update.hip); returns the new ndet.
+int64_t grow_basis(Ctx &c, int mode, int64_t ncand, const uint64_t *ca, const uint64_t *cb, const double *cscore,
+                   int64_t k, const double *bscore, int64_t bmax, const double *c_old, double *c_new,
+                   double *score_new, double *ms_out);
+// Strings of the current set in caller order (device uint64; either may be null).
+void caller_strings(Ctx &c, uint64_t *alpha, uint64_t *beta);
 
 // Davidson (davidson.hip)
 int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, double *coeffs,

@@ -53,6 +53,7 @@ struct ElemArgs {
     float *val32;
     double *diag;
     float *diag32;
+    const int64_t *skip;  // per row: leading entries whose values are already set (or null)
 };
 
 // One wave per row; lanes stride over the row's couplings.  Integrals in LDS
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(256) void k_elements(ElemArgs a) {
     const int nw = blockDim.x >> 6;
     for (int64_t row = (int64_t)blockIdx.x * nw + wave; row < a.ndet; row += (int64_t)gridDim.x * nw) {
         const uint32_t ai = a.sa[row], bi = a.sb[row];
-        const int64_t beg = a.rowptr[row], end = a.rowptr[row + 1];
+        const int64_t beg = a.rowptr[row] + (a.skip ? a.skip[row] : 0), end = a.rowptr[row + 1];
         for (int64_t e = beg + lane; e < end; e += 64) {
             const double v = coupling_value(eri, h, a.norb, a.desc[e], ai, bi);
             a.val[e] = v;
@@ -152,7 +153,9 @@ void build_integrals(Ctx &c, int norb, const double *h, const double *eri, doubl
     c.have_ints = true;
 }
 
-void build_elements(Ctx &c) {
+void build_elements(Ctx &c) { build_elements_after(c, nullptr); }
+
+void build_elements_after(Ctx &c, const int64_t *skip) {
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = c.stream;
     const int np = neri_packed(c.norb);
@@ -161,7 +164,7 @@ void build_elements(Ctx &c) {
     c.diag.ensure(c.ndet);
     c.diag32.ensure(c.ndet);
     ElemArgs a{c.ndet, c.norb, np, c.ecore, c.sa.p, c.sb.p, c.rowptr.p, c.desc.p, c.d_eri.p, c.d_h.p,
-               c.val.p, c.val32.p, c.diag.p, c.diag32.p};
+               c.val.p, c.val32.p, c.diag.p, c.diag32.p, skip};
     const size_t lds = sizeof(double) * ((size_t)np + (size_t)c.norb * c.norb);
     const bool use_lds = lds <= 150 * 1024;
     int dev_cus = 256;

@@ -15,6 +15,7 @@
 // packed integrals in LDS when they fit.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "slater.hpp"
@@ -284,26 +285,73 @@ __device__ inline void scan_alpha_group(const Pt2Args &a, const double *eri, con
     }
 }
 
-// One wave per candidate x = (xa, xb).  Its partners in B fall into three
-// disjoint classes, each read from one kind of group:
+// Candidate order for PT2: key (alpha << norb | beta) of each candidate
+// (0 for a malformed one; the main kernel checks every candidate itself).
+__global__ void k_pt2_keys(const uint64_t *ca, const uint64_t *cb, int64_t n, int norb, uint64_t *keys,
+                           int32_t *vals) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const uint64_t a = ca[t], b = cb[t];
+    keys[t] = ((a >> norb) | (b >> norb)) ? 0ull : ((a << norb) | b);
+    vals[t] = (int32_t)t;
+}
+
+// Groups of each candidate (in key order): its alpha group and beta group in
+// B, or -1.  One thread per candidate, so the searches overlap.
+__global__ void k_pt2_groups(const BTables B, const uint64_t *ca, const uint64_t *cb, const int32_t *order, int64_t n,
+                             int norb, int32_t *ga_of, int32_t *gb_of) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n) return;
+    const int32_t t = order[u];
+    const uint64_t a = ca[t], b = cb[t];
+    const bool ok = ((a >> norb) | (b >> norb)) == 0;
+    ga_of[u] = ok ? find_u32(B.ua, B.nua, (uint32_t)a) : -1;
+    gb_of[u] = ok ? find_u32(B.ub, B.nub, (uint32_t)b) : -1;
+}
+
+// Waves take runs of PT2_RUN consecutive candidates in key order from a
+// shared counter (every wave stops once the counter passes ncand), one
+// candidate at a time.  Its partners in B fall into three disjoint classes, each read from
+// one kind of group:
 //   same alpha string        the alpha group of xa (beta differs by 0, 1 or 2)
 //   same beta string         the beta group of xb (alpha differs by 1 or 2)
 //   one move in each spin    the alpha groups of the strings one move from xa
-//                            (from the link table when xa is an alpha string
-//                            of B, else by search), keeping beta strings one
-//                            move from xb
-// The diagonal enters through the first class when x lies in B.
-template <bool USE_LDS>
-__global__ __launch_bounds__(PT_NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_pt2(Pt2Args a) {
+//                            (link table when xa is an alpha string of B, else
+//                            searched), keeping beta strings one move from xb
+// The diagonal enters through the first class when x lies in B.  Candidates
+// of a run mostly share xa, so the bounds of its alpha groups are loaded once
+// per distinct xa and kept in the lanes (slot r of lane l: move 64 r + l;
+// SLOTS * 64 >= na (norb - na)).
+constexpr int PT2_RUN = 16;
+
+template <bool USE_LDS, int SLOTS>
+__global__ __launch_bounds__(PT_NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_pt2(
+    Pt2Args a, const int32_t *order, const int32_t *ga_of, const int32_t *gb_of, unsigned long long *next) {
     extern __shared__ double smem[];
     const double *eri, *h;
     stage_integrals<USE_LDS>(smem, a.eri, a.h, a.npack, a.norb, eri, h);
     const int lane = threadIdx.x & 63;
     const int norb = a.norb, nva = norb - a.na, nmov = a.na * nva;
     const uint32_t full = norb >= 32 ? 0xffffffffu : ((1u << norb) - 1u);
-    const int64_t nwaves = (int64_t)gridDim.x * (PT_NT / 64);
-    for (int64_t t = (int64_t)blockIdx.x * (PT_NT / 64) + (threadIdx.x >> 6); t < a.ncand; t += nwaves) {
+    uint32_t cur_a = 0;
+    bool have = false;
+    int nlink = 0;
+    int32_t lo_m[SLOTS], hi_m[SLOTS];
+    uint32_t aj_m[SLOTS];
+    int64_t u = 0, u_end = 0;
+    for (;;) {
+        if (u == u_end) {  // next run of PT2_RUN candidates from the shared counter
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(next, (unsigned long long)PT2_RUN);
+            base = __shfl(base, 0, 64);
+            if ((int64_t)base >= a.ncand) break;
+            u = (int64_t)base;
+            u_end = min(a.ncand, u + PT2_RUN);
+        }
+        const int32_t t = order[u];
         const uint64_t a64 = a.ca[t], b64 = a.cb[t];
+        const int32_t g = ga_of[u], gbx = gb_of[u];
+        ++u;
         if ((a64 >> norb) != 0 || (b64 >> norb) != 0 || __popcll(a64) != a.na || __popcll(b64) != a.nb) {
             if (lane == 0) {
                 atomicOr(a.bad, 1u);
@@ -315,47 +363,58 @@ __global__ __launch_bounds__(PT_NT) __attribute__((amdgpu_waves_per_eu(8, 8))) v
             continue;
         }
         const uint32_t xa = (uint32_t)a64, xb = (uint32_t)b64;
+        if (!have || xa != cur_a) {  // alpha groups one move from xa
+            have = true;
+            cur_a = xa;
+            nlink = g >= 0 ? a.alink_ptr[g] : nmov;
+#pragma unroll
+            for (int r = 0; r < SLOTS; ++r) {
+                const int m = 64 * r + lane;
+                int32_t gm = -1;
+                if (m < nlink) {
+                    if (g >= 0) {
+                        gm = a.alink[(int64_t)g * a.alink_max + m];
+                    } else {
+                        const uint32_t am =
+                            xa ^ (1u << nth_bit(xa, m / nva)) ^ (1u << nth_bit(~xa & full, m % nva));
+                        gm = find_u32(a.B.ua, a.B.nua, am);
+                    }
+                }
+                lo_m[r] = gm >= 0 ? a.B.ga[gm] : 0;
+                hi_m[r] = gm >= 0 ? a.B.ga[gm + 1] : 0;
+                aj_m[r] = gm >= 0 ? a.B.ua[gm] : 0u;
+            }
+        }
         const double d = diag_value(eri, h, norb, a.ecore, xa, xb);
         double acc = 0.0;
-        const int32_t g = find_u32(a.B.ua, a.B.nua, xa);
         if (g >= 0) scan_alpha_group<true>(a, eri, h, a.B.ga[g], a.B.ga[g + 1], xa, xb, xa, d, lane, acc);
-        const int32_t gbx = find_u32(a.B.ub, a.B.nub, xb);
         if (gbx >= 0) {
             const int32_t end = a.B.gb[gbx + 1];
             for (int32_t u0 = a.B.gb[gbx] + lane; u0 < end; u0 += 64 * SCAN_U) {
                 uint32_t aj[SCAN_U];
 #pragma unroll
-                for (int u = 0; u < SCAN_U; ++u) {
-                    const int32_t q = u0 + 64 * u;
-                    aj[u] = q < end ? a.B.bm_alpha[q] : xa;
+                for (int v = 0; v < SCAN_U; ++v) {
+                    const int32_t q = u0 + 64 * v;
+                    aj[v] = q < end ? a.B.bm_alpha[q] : xa;
                 }
 #pragma unroll
-                for (int u = 0; u < SCAN_U; ++u) {
-                    const int da = popc32(xa ^ aj[u]);
+                for (int v = 0; v < SCAN_U; ++v) {
+                    const int da = popc32(xa ^ aj[v]);
                     if (da != 0 && da <= 4)
-                        acc += a.cs[a.B.bperm[u0 + 64 * u]] *
-                               coupling_value(eri, h, norb, pair_desc(xa, xb, aj[u], xb), xa, xb);
+                        acc += a.cs[a.B.bperm[u0 + 64 * v]] *
+                               coupling_value(eri, h, norb, pair_desc(xa, xb, aj[v], xb), xa, xb);
                 }
             }
         }
-        const int nlink = g >= 0 ? a.alink_ptr[g] : nmov;
-        for (int m0 = 0; m0 < nlink; m0 += 64) {
-            const int m = m0 + lane;
-            int32_t gm = -1;
-            if (m < nlink) {
-                if (g >= 0) {
-                    gm = a.alink[(int64_t)g * a.alink_max + m];
-                } else {
-                    const uint32_t am = xa ^ (1u << nth_bit(xa, m / nva)) ^ (1u << nth_bit(~xa & full, m % nva));
-                    gm = find_u32(a.B.ua, a.B.nua, am);
-                }
-            }
-            uint64_t found = __ballot(gm >= 0);
+#pragma unroll
+        for (int r = 0; r < SLOTS; ++r) {
+            uint64_t found = __ballot(hi_m[r] > lo_m[r]);
             while (found) {
                 const int src = __builtin_ctzll(found);
                 found &= found - 1;
-                const int32_t gg = __shfl(gm, src, 64);
-                scan_alpha_group<false>(a, eri, h, a.B.ga[gg], a.B.ga[gg + 1], xa, xb, a.B.ua[gg], d, lane, acc);
+                const int32_t lo = __shfl(lo_m[r], src, 64), hi = __shfl(hi_m[r], src, 64);
+                const uint32_t aj = (uint32_t)__shfl((int)aj_m[r], src, 64);
+                scan_alpha_group<false>(a, eri, h, lo, hi, xa, xb, aj, d, lane, acc);
             }
         }
         acc = wave_sum_d(acc);
@@ -503,17 +562,54 @@ void pt2(Ctx &c, const double *coeffs, bool sorted, double e0, int64_t ncand, co
     HQ_CHECK(hipMemsetAsync(bad.p, 0, sizeof(unsigned), s));
     Pt2Args pa{tables_of(c), c.norb, neri_packed(c.norb), c.na, c.nb, c.alink_max, c.alink_ptr.p, c.alink.p,
                c.ecore, e0, ncand, ca, cb, csp, c.d_eri.p, c.d_h.p, numer, hxx, score, bad.p};
+    // candidates in key order, and their groups in B
+    DBuf<uint64_t> keys;
+    DBuf<int32_t> order, ga_of, gb_of;
+    keys.ensure(ncand);
+    order.ensure(ncand);
+    ga_of.ensure(ncand);
+    gb_of.ensure(ncand);
+    hipLaunchKernelGGL(k_pt2_keys, dim3(grid_for(ncand, 256)), dim3(256), 0, s, ca, cb, ncand, c.norb, keys.p,
+                       order.p);
+    HQ_LAUNCH_CHECK();
+    radix_sort_u64(s, keys.p, order.p, ncand, 2 * c.norb, c.work);
+    keys.release();
+    hipLaunchKernelGGL(k_pt2_groups, dim3(grid_for(ncand, 256)), dim3(256), 0, s, pa.B, ca, cb, order.p, ncand,
+                       c.norb, ga_of.p, gb_of.p);
+    HQ_LAUNCH_CHECK();
     const size_t lds = integral_lds(c);
     const int cus = device_cus(c);
-    const int64_t want = (ncand + PT_NT / 64 - 1) / (PT_NT / 64);
-    if (lds <= 150 * 1024) {
-        HQ_CHECK(hipFuncSetAttribute((const void *)k_pt2<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds));
-        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)cus * 2));
-        hipLaunchKernelGGL(k_pt2<true>, dim3(grid), dim3(PT_NT), lds, s, pa);
+    const bool use_lds = lds <= 150 * 1024;
+    // resident workgroups only (two per CU); they share the candidates through a counter
+    const int64_t runs = (ncand + PT2_RUN - 1) / PT2_RUN;
+    const unsigned grid =
+        (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * 2, (runs + PT_NT / 64 - 1) / (PT_NT / 64)));
+    DBuf<unsigned long long> next;
+    next.ensure(1);
+    HQ_CHECK(hipMemsetAsync(next.p, 0, sizeof(unsigned long long), s));
+    const int moves = c.na * (c.norb - c.na);
+    auto launch = [&](auto lds_tag, auto slots_tag) {
+        constexpr bool L = decltype(lds_tag)::value;
+        constexpr int S = decltype(slots_tag)::value;
+        if (L)
+            HQ_CHECK(hipFuncSetAttribute((const void *)k_pt2<L, S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds));
+        hipLaunchKernelGGL((k_pt2<L, S>), dim3(grid), dim3(PT_NT), L ? lds : 0, s, pa, order.p, ga_of.p, gb_of.p,
+                           next.p);
+    };
+    using T = std::true_type;
+    using F = std::false_type;
+    using S1 = std::integral_constant<int, 1>;
+    using S2 = std::integral_constant<int, 2>;
+    using S4 = std::integral_constant<int, 4>;
+    if (use_lds) {
+        if (moves <= 64) launch(T{}, S1{});
+        else if (moves <= 128) launch(T{}, S2{});
+        else launch(T{}, S4{});
     } else {
-        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)cus * 4));
-        hipLaunchKernelGGL(k_pt2<false>, dim3(grid), dim3(PT_NT), 0, s, pa);
+        if (moves <= 64) launch(F{}, S1{});
+        else if (moves <= 128) launch(F{}, S2{});
+        else launch(F{}, S4{});
     }
     HQ_LAUNCH_CHECK();
     unsigned hbad = 0;

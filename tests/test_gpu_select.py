@@ -268,3 +268,23 @@ def test_teacher_weights_full_size():
     log("teacher weights cas16 1e6")
     s = solver_for(ints, a, b, cfg.na, cfg.nb)
     _check_weights(s, a, b, _coeffs(len(a), 99))
+
+
+@pytest.mark.parametrize("norb,na,nb", [(18, 9, 8), (24, 12, 12)])
+def test_expand_and_pt2_large_orbital_counts(norb, na, nb):
+    """More than 64 alpha single moves (81, 144) and, at norb 24, integrals
+    read from global memory instead of LDS."""
+    log(f"expand + pt2 at norb {norb} ({na}a {nb}b)")
+    ints = W.gen_integrals(norb, norb, -2.0, -0.5, 900 + norb)
+    a, b = W.sample_determinants(norb, na, nb, 2000, 0.3, 0.0, 910 + norb)
+    s = solver_for(ints, a, b, na, nb)
+    o = oracle_for(ints, a, b, na, nb)
+    c = _coeffs(len(a), norb)
+    ra, rb = _check_expand(s, o, c, 3)
+    rng = np.random.default_rng(norb)
+    pick = rng.choice(len(ra), 300, replace=False)
+    inb = rng.choice(len(a), 100, replace=False)
+    ca = np.concatenate([ra[pick], a[inb]])
+    cb = np.concatenate([rb[pick], b[inb]])
+    e0 = float(o.pt2(c, 0.0, a[:50], b[:50])[1].min()) - 0.5
+    _check_pt2(s, o, c, e0, ca, cb)

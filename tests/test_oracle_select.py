@@ -185,3 +185,21 @@ def test_teacher_weights_brute_force():
         raw.append(pa * pb)
     raw = np.array(raw)
     assert np.allclose(w, raw / raw.sum(), rtol=1e-13, atol=0)
+
+
+def test_grow_basis_rules_hand_example():
+    """Set scores (3, 1, 2, 1), candidate scores (5, 1, 4, 4), worked by hand:
+    append k=2 -> candidates 0 then 2 (the tie 4 = 4 goes to the lower index);
+    cap 5 -> the lowest of [3,1,2,1,5,4] is set member 1 (tied with 3);
+    cap 3 -> set members 1, 3, 2 go; rebuild k=3 -> 5, 4, 4 are all
+    candidates, so every set member goes; rebuild k=5 adds set members 0, 2."""
+    bs = [3.0, 1.0, 2.0, 1.0]
+    cs = [5.0, 1.0, 4.0, 4.0]
+    assert oracle.grow_basis(bs, cs, 2) == ([0, 1, 2, 3], [0, 2])
+    assert oracle.grow_basis(bs, cs, 2, b_max=5) == ([0, 2, 3], [0, 2])
+    assert oracle.grow_basis(bs, cs, 2, b_max=3) == ([0], [0, 2])
+    assert oracle.grow_basis(bs, cs, 3, rebuild=True) == ([], [0, 2, 3])
+    kept, apps = oracle.grow_basis(bs, cs, 5, rebuild=True)
+    assert kept == [0, 2] and apps == [0, 2, 3]
+    # a capped append can also drop a just-chosen candidate
+    assert oracle.grow_basis([9.0, 8.0], [1.0, 7.0], 2, b_max=3) == ([0, 1], [1])
