@@ -153,7 +153,7 @@ def selection_pass(hq, solver, c, e0, ntop, keep, reps=3):
             "max_score": float(score[idx[0]].item()) if n else None}, (ya, yb)
 
 
-def outer_iteration(hq, solver, c, e0, ya, yb, cand_score, keep, b_max, k, tol):
+def outer_iteration(hq, solver, solver_integrals, c, e0, ya, yb, cand_score, keep, b_max, k, tol):
     """The rest of one outer iteration after scoring (Sec. 2.2, Steps 2-3 at
     t >= 2): PT2 scores of the current set (its eviction ranking), the growth
     rule (append the `keep` best candidates, cap at b_max), then the FP64
@@ -170,9 +170,28 @@ def outer_iteration(hq, solver, c, e0, ya, yb, cand_score, keep, b_max, k, tol):
     e1, _, st = solver.lowest_eigenpair(guess=c_new, tol=tol, block=k)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
-    return {"ndet_new": solver.ndet, "ms_rescore_set": (t1 - t0) * 1e3, "ms_grow_update": (t2 - t1) * 1e3,
-            "ms_update_kernels": ms_upd, "ms_warm_solve": (t3 - t2) * 1e3, "warm_iterations": st["iterations"],
-            "energy": e1, "energy_drop": e0 - e1}
+    # sigma on the patched couplings against a from-scratch build of the same set
+    def sigma_ms(s, reps=5):
+        X = torch.ones(s.ndet, k, dtype=torch.float64, device="cuda")
+        S = torch.empty_like(X)
+        s.sigma(X, out=S, sorted_order=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            s.sigma(X, out=S, sorted_order=True)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps * 1e3
+    a_n, b_n = solver.determinants()
+    fresh = hq.Hinqs(0)
+    fresh.set_integrals(*solver_integrals)
+    fresh.set_determinants(a_n, b_n, solver.na, solver.nb)
+    out = {"ndet_new": solver.ndet, "nnz_new": solver.info()["nnz"], "ms_rescore_set": (t1 - t0) * 1e3,
+           "ms_grow_update": (t2 - t1) * 1e3, "ms_update_kernels": ms_upd, "ms_warm_solve": (t3 - t2) * 1e3,
+           "warm_iterations": st["iterations"], "energy": e1, "energy_drop": e0 - e1,
+           "ms_fresh_build": fresh.info()["ms_sort"] + fresh.info()["ms_connect"] + fresh.info()["ms_elements"],
+           "ms_sigma_patched": sigma_ms(solver), "ms_sigma_fresh": sigma_ms(fresh)}
+    fresh.close()
+    return out
 
 
 def cpu_pt2_rate(o, c, e0, ya, yb, n=2000):
@@ -355,7 +374,8 @@ def main():
                                        f"of the {D}-determinant set, PT2 of every expanded determinant, "
                                        f"top {args.keep} by score")
     _, _, score = solver.pt2(last["c64"], e_sel, ya, yb)
-    out["iteration"] = dict(outer_iteration(hq, solver, last["c64"], e_sel, ya, yb, score, args.keep,
+    out["iteration"] = dict(outer_iteration(hq, solver, (ints.h, ints.eri, ints.e_core), last["c64"], e_sel,
+                                            ya, yb, score, args.keep,
                                             D + args.keep // 2, cfg.k, cfg.tol),
                             workload=f"append the {args.keep} best-scored expanded determinants, cap at "
                                      f"{D + args.keep // 2} (the lowest PT2 scores of the set and the "
