@@ -74,6 +74,16 @@ int hinqs_create(hinqs_ctx **out, int device, void *hip_stream) {
     if (!ctx) return HINQS_E_OOM;
     ctx->c.device = device;
     ctx->c.stream = (hipStream_t)hip_stream;
+    try {  // sigma row counters: zero here, and put back to zero by every launch
+        ctx->c.sigma_ctr.ensure(SIGMA_CTR_WORDS);
+    } catch (const Error &) {
+        delete ctx;
+        return HINQS_E_OOM;
+    }
+    if (hipMemset(ctx->c.sigma_ctr.p, 0, sizeof(unsigned long long) * SIGMA_CTR_WORDS) != hipSuccess) {
+        delete ctx;
+        return HINQS_E_HIP;
+    }
     *out = ctx;
     return HINQS_OK;
 }

@@ -180,11 +180,15 @@ __host__ __device__ inline int eri_index(int p, int q, int r, int s) {
 inline int npair(int norb) { return norb * (norb + 1) / 2; }
 inline int neri_packed(int norb) { int m = npair(norb); return m * (m + 1) / 2; }
 
+// Words of the sigma kernel's row counters: 32 per XCD (8 XCDs).
+constexpr int SIGMA_CTR_WORDS = 8 * 32;
+
 // Launch shape of the sigma kernel: lanes per row team, couplings in flight per
 // lane, resident workgroups per CU.
 struct SigmaCfg {
     int team = 0, unr = 0, occ = 0;
     int pipe = 0;     // 0: one step of gathers in flight per team; 1: cross-row four-stage pipeline
+    int run = 4;      // rows a team takes from its XCD's row counter at a time (pipe 0)
     double ms = 0.0;  // measured time of one launch when chosen by the tuner
 };
 
@@ -267,6 +271,8 @@ struct Ctx {
     int64_t xcd_rows[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     // tuned sigma launch shapes, [precision][log2 k]
     SigmaCfg sigma_cfg[2][5];
+    // row counters of the sigma kernel (SIGMA_CTR_WORDS; zero between launches; set up with the context)
+    DBuf<unsigned long long> sigma_ctr;
 
     // timings (ms)
     double ms_sort = 0, ms_connect = 0, ms_elements = 0;

@@ -98,6 +98,20 @@ struct XcdRows {
 // MASK (batched instances): the XCD row ranges come from device memory and the
 // rows of finished instances are skipped; a team jumps over a finished
 // instance in one step, so the cost does not grow with its size.
+// Row counters (ctr, not for MASK): instead of a fixed stride, the team
+// leader takes the XCD's next run of `run` rows from a counter, so the teams of an XCD stay
+// on neighbouring rows however unequal the rows are; with fixed strides the
+// teams drift apart and the X rows in flight no longer share the XCD's L2
+// (a trace-driven model of the gathers gives 53 % L2 hits for strides and
+// 80 % for a shared counter).  The next run is requested when a run starts,
+// so the atomic's latency hides behind the current rows; runs of several
+// rows keep the counters from becoming a hot spot in their L2 channels.  The
+// last team of an XCD to finish puts its counters back to zero for the next
+// launch.  ctr: CTR_STRIDE words per XCD, word 0 = next row, word
+// CTR_DONE = teams finished.
+constexpr int CTR_STRIDE = SIGMA_CTR_WORDS / NUM_XCD;
+constexpr int CTR_DONE = 16;
+
 template <typename T, int K, int TEAM, int UNR, bool MASK>
 __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges, SigmaMask mk, int xcd_map,
                                                        const int64_t *__restrict__ rowptr,
@@ -105,7 +119,8 @@ __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges, SigmaMask
                                                        const T *__restrict__ val,
                                                        const T *__restrict__ diag,
                                                        const T *__restrict__ X, int ldx,
-                                                       T *__restrict__ S, int lds) {
+                                                       T *__restrict__ S, int lds,
+                                                       unsigned long long *ctr, int run) {
     constexpr int VW = Vec16<T>::n;
     constexpr int LPN = (K >= VW) ? K / VW : 1;   // lanes per coupling
     constexpr int EPL = K / LPN;                   // entries of X per lane
@@ -140,11 +155,51 @@ __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges, SigmaMask
         }
         return rw;
     };
-    int64_t row = live_row(r0 + team0);
-    if (row >= r1) return;  // uniform across the team
+    const bool dyn = !MASK && ctr != nullptr;
+    unsigned long long *const myctr = dyn ? ctr + xcd * CTR_STRIDE : nullptr;
+    auto take = [&]() -> unsigned long long {  // result valid on the team leader only
+        unsigned long long v = 0;
+        if (sub == 0) v = atomicAdd(myctr, (unsigned long long)run);
+        return v;
+    };
+    auto first_row = [&](unsigned long long v) -> int64_t { return r0 + (int64_t)__shfl(v, 0, TEAM); };
+    int64_t run_end = 0;  // end of the run of rows taken last
+    auto finish = [&]() {
+        if (dyn && sub == 0) {
+            const unsigned long long d = atomicAdd(myctr + CTR_DONE, 1ull);
+            if (d + 1 == (unsigned long long)nteams) {
+                atomicExch(myctr, 0ull);
+                atomicExch(myctr + CTR_DONE, 0ull);
+            }
+        }
+    };
+    unsigned long long pend = 0;
+    int64_t row;
+    if (dyn) {
+        row = first_row(take());
+        run_end = min(row + run, r1);
+        if (row < r1) pend = take();
+    } else {
+        row = live_row(r0 + team0);
+    }
+    if (row >= r1) {  // uniform across the team
+        finish();
+        return;
+    }
     int64_t beg = uniform_if<TEAM == 64>(rowptr[row]), end = uniform_if<TEAM == 64>(rowptr[row + 1]);
     for (;;) {
-        const int64_t nrow = live_row(row + nteams);
+        int64_t nrow;
+        if (dyn) {
+            if (row + 1 < run_end) {
+                nrow = row + 1;
+            } else {
+                nrow = first_row(pend);
+                run_end = min(nrow + run, r1);
+                if (nrow < r1) pend = take();
+            }
+        } else {
+            nrow = live_row(row + nteams);
+        }
         // next row's bounds, in flight during this row (clamped, not predicated)
         const int64_t nrc = nrow < r1 ? nrow : row;
         const int64_t nbeg = rowptr[nrc], nend = rowptr[nrc + 1];
@@ -213,6 +268,7 @@ __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges, SigmaMask
         beg = uniform_if<TEAM == 64>(nbeg);
         end = uniform_if<TEAM == 64>(nend);
     }
+    finish();
 }
 
 // Cross-row pipelined variant.  A team walks its rows as one stream of steps
@@ -409,7 +465,8 @@ void launch_sigma_u(const Ctx &c, const SigmaCfg &cfg, const SigmaMask &mk, cons
                            ranges, mk, xmap, c.rowptr.p, c.col.p, val, diag, X, ldx, S, lds);
     else
         hipLaunchKernelGGL((k_sigma<T, K, TEAM, UNR, MASK>), dim3((unsigned)nblk), dim3(SIGMA_BLOCK), 0, s,
-                           ranges, mk, xmap, c.rowptr.p, c.col.p, val, diag, X, ldx, S, lds);
+                           ranges, mk, xmap, c.rowptr.p, c.col.p, val, diag, X, ldx, S, lds,
+                           MASK ? (unsigned long long *)nullptr : c.sigma_ctr.p, std::max(1, cfg.run));
     HQ_LAUNCH_CHECK();
 }
 
@@ -476,6 +533,7 @@ SigmaCfg sigma_config(const Ctx &c, int k, int precision) {
     g.unr = env_int("HINQS_SIGMA_UNR", g.unr);
     g.occ = env_int("HINQS_SIGMA_OCC", g.occ);
     g.pipe = env_int("HINQS_SIGMA_PIPE", g.pipe);
+    g.run = env_int("HINQS_SIGMA_RUN", g.run);
     return g;
 }
 
