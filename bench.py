@@ -194,7 +194,7 @@ def outer_iteration(hq, solver, solver_integrals, c, e0, ya, yb, cand_score, kee
     return out
 
 
-def cpu_pt2_rate(o, c, e0, ya, yb, n=2000):
+def cpu_pt2_rate(o, c, e0, ya, yb, n=40000):
     """The oracle's PT2 (Eq. 3) on a sample of the expanded determinants, as it stands."""
     import oracle
     m = min(n, len(ya))

@@ -208,3 +208,32 @@ def test_grow_basis_matches_oracle_rules(cas10, mode):
 
 def _strs(t):
     return t.cpu().numpy().view(np.uint64)
+
+
+def test_update_large_orbital_count_and_rule_errors():
+    """norb 20 (integrals read from global memory, 100 alpha single moves):
+    an update against the oracle; then the growth-rule argument checks."""
+    norb, na, nb = 20, 10, 9
+    log(f"update at norb {norb}")
+    ints = W.gen_integrals(norb, norb, -2.0, -0.5, 555)
+    a, b = W.sample_determinants(norb, na, nb, 1500, 0.3, 0.0, 556)
+    o = oracle_for(ints, a, b, na, nb)
+    c = _coeffs(len(a), 7)
+    ea, eb, _ = o.expand(c, 2)
+    rng = np.random.default_rng(8)
+    pick = rng.choice(len(ea), 400, replace=False)
+    evict = rng.choice(len(a), 100, replace=False).astype(np.int32)
+    s = solver_for(ints, a, b, na, nb)
+    s.update_determinants(ea[pick], eb[pick], evict=evict)
+    na_, nb_, _ = _new_set(a, b, evict, ea[pick], eb[pick])
+    _check_set(s, oracle_for(ints, na_, nb_, na, nb), np.arange(len(na_)))
+    cs = torch.from_numpy(_scores(20, 3)).cuda()
+    with pytest.raises(hq.HinqsError) as ex:      # a capped append needs the set's scores
+        s.grow_basis(ea[:20], eb[:20], cs, 10, b_max=len(na_))
+    assert ex.value.name == "INVALID_ARG"
+    bad = cs.clone()
+    bad[3] = float("nan")
+    with pytest.raises(hq.HinqsError) as ex:
+        s.grow_basis(ea[:20], eb[:20], bad, 10)
+    assert ex.value.name == "NONFINITE"
+    assert s.ndet == len(na_)
