@@ -488,6 +488,22 @@ int hinqs_grow_basis(hinqs_ctx *ctx, int mode, int64_t ncand, const uint64_t *ca
 int hinqs_get_determinants(hinqs_ctx *ctx, uint64_t *alpha, uint64_t *beta);
 
 /*
+ * Product-space closure of the set (the backends named in paper Sec. 2.2,
+ * Step 3, diagonalize on the alpha x beta product of the distinct strings of
+ * B; this library diagonalizes on B itself): every determinant
+ * (a, b) with a among the distinct alpha strings of B and b among its
+ * distinct beta strings that is not already in B, in ascending (alpha, beta)
+ * order.  *count (host) receives how many there are
+ * (n_alpha_strings * n_beta_strings - ndet); the first min(capacity, *count)
+ * are written to out_alpha / out_beta (device uint64; may be NULL when
+ * capacity is 0).  Appending them with hinqs_update_determinants gives the
+ * product space.
+ * Errors: NOT_READY, INVALID_ARG, HIP.
+ */
+int hinqs_product_closure(hinqs_ctx *ctx, int64_t capacity, uint64_t *out_alpha, uint64_t *out_beta,
+                          int64_t *count);
+
+/*
  * Host-only helper (no device work): descriptor of the pair x_i <- x_j as
  * the coupling enumerator encodes it, or 0 if the pair differs by more than
  * two electrons or not at all.  Used to check the sign rules on the CPU.

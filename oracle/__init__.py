@@ -304,3 +304,14 @@ def grow_basis(basis_score, cand_score, k, b_max=0, rebuild=False):
         kept = [i for i in range(nb) if i not in low]
         apps = [t for j, t in enumerate(apps) if nb + j not in low]
     return kept, apps
+
+
+def product_closure(alpha, beta):
+    """The determinants of (distinct alpha strings) x (distinct beta strings)
+    not in the set, ascending (alpha, beta): the product space the backends
+    of Sec. 2.2 Step 3 diagonalize on, minus the set itself."""
+    have = set(zip((int(x) for x in alpha), (int(y) for y in beta)))
+    ua = sorted(set(int(x) for x in alpha))
+    ub = sorted(set(int(y) for y in beta))
+    out = [(x, y) for x in ua for y in ub if (x, y) not in have]
+    return (np.array([p[0] for p in out], dtype=np.uint64), np.array([p[1] for p in out], dtype=np.uint64))

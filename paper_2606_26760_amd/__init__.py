@@ -47,7 +47,7 @@ EXPORTED = ["hinqs_opts_default", "hinqs_create", "hinqs_destroy", "hinqs_last_e
             "hinqs_autotune", "hinqs_batch_clear", "hinqs_batch_add", "hinqs_batch_info",
             "hinqs_batch_lowest_eigenpair", "hinqs_expand", "hinqs_pt2", "hinqs_top_k",
             "hinqs_teacher_weights", "hinqs_distinct_strings", "hinqs_update_determinants",
-            "hinqs_grow_basis", "hinqs_get_determinants"]
+            "hinqs_grow_basis", "hinqs_get_determinants", "hinqs_product_closure"]
 
 
 class HinqsError(RuntimeError):
@@ -144,6 +144,7 @@ def load_library() -> ctypes.CDLL:
             "hinqs_update_determinants": (i32, [P, i64, P, i64, P, P, P, P, i32, P]),
             "hinqs_grow_basis": (i32, [P, i32, i64, P, P, P, i64, P, i64, P, P, P, P, P]),
             "hinqs_get_determinants": (i32, [P, P, P]),
+            "hinqs_product_closure": (i32, [P, i64, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -576,6 +577,18 @@ class Hinqs:
         b = torch.empty(self.ndet, dtype=torch.int64, device=self.device)
         self._check(self._lib.hinqs_get_determinants(self._h, self._ptr(a), self._ptr(b)))
         return a, b
+
+    def product_closure(self):
+        """(alpha, beta) int64 device tensors of the product-space determinants
+        missing from the set, ascending."""
+        torch = _torch()
+        n = ctypes.c_int64(0)
+        self._check(self._lib.hinqs_product_closure(self._h, 0, None, None, ctypes.byref(n)))
+        a = torch.empty(max(n.value, 1), dtype=torch.int64, device=self.device)
+        b = torch.empty(max(n.value, 1), dtype=torch.int64, device=self.device)
+        self._check(self._lib.hinqs_product_closure(self._h, n.value, self._ptr(a), self._ptr(b),
+                                                    ctypes.byref(n)))
+        return a[:n.value], b[:n.value]
 
     def info(self):
         inf = Info()

@@ -463,6 +463,18 @@ int hinqs_get_determinants(hinqs_ctx *ctx, uint64_t *alpha, uint64_t *beta) {
     });
 }
 
+int hinqs_product_closure(hinqs_ctx *ctx, int64_t capacity, uint64_t *out_alpha, uint64_t *out_beta,
+                          int64_t *count) {
+    return guarded(ctx, [&](Ctx &c) {
+        if (!c.have_dets) throw Error(HINQS_E_NOT_READY, "determinants are not set");
+        if (!count) throw Error(HINQS_E_INVALID_ARG, "null count");
+        if (capacity < 0 || (capacity > 0 && (!out_alpha || !out_beta)))
+            throw Error(HINQS_E_INVALID_ARG, "capacity needs output arrays");
+        *count = product_closure(c, capacity, out_alpha, out_beta);
+        return HINQS_OK;
+    });
+}
+
 uint32_t hinqs_pair_descriptor(uint64_t alpha_i, uint64_t beta_i, uint64_t alpha_j, uint64_t beta_j) {
     return pair_desc((uint32_t)alpha_i, (uint32_t)beta_i, (uint32_t)alpha_j, (uint32_t)beta_j);
 }

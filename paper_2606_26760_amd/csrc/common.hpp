@@ -339,6 +339,10 @@ int64_t expand(Ctx &c, const double *coeffs, bool sorted, int64_t ntop, int64_t 
 void pt2(Ctx &c, const double *coeffs, bool sorted, double e0, int64_t ncand, const uint64_t *ca,
          const uint64_t *cb, double *numer, double *hxx, double *score);
 
+// Determinants of (distinct alpha strings) x (distinct beta strings) that are
+// not in the set, ascending; the first cap are written; returns how many.
+int64_t product_closure(Ctx &c, int64_t cap, uint64_t *out_a, uint64_t *out_b);
+
 // Teacher weights (weights.hip): c in caller order unless `sorted`.
 void teacher_weights(Ctx &c, const double *coeffs, bool sorted, double *w, double *p_alpha, double *p_beta);
 void distinct_strings(Ctx &c, uint64_t *alpha, uint64_t *beta);

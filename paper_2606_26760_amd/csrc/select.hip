@@ -621,3 +621,73 @@ void pt2(Ctx &c, const double *coeffs, bool sorted, double e0, int64_t ncand, co
 }
 
 }  // namespace hinqs
+
+// ------------------------------------------------------------ product space
+namespace hinqs {
+namespace {
+
+// missing[g] = number of distinct beta strings absent from alpha group g.
+__global__ void k_missing_counts(const int32_t *ga, int32_t nua, int32_t nub, int64_t *missing) {
+    const int32_t g = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (g < nua) missing[g] = (int64_t)nub - (ga[g + 1] - ga[g]);
+}
+
+// One wave per alpha group: the distinct beta strings absent from the group,
+// ascending, written as (alpha, beta) pairs from off[g] (first `cap` only).
+__global__ void k_missing_list(const uint32_t *ua, const uint32_t *ub, const uint32_t *sb, const int32_t *ga,
+                               int32_t nua, int32_t nub, const int64_t *off, int64_t cap, uint64_t *oa,
+                               uint64_t *ob) {
+    const int lane = threadIdx.x & 63;
+    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (g >= nua) return;
+    const int32_t lo = ga[g], n = ga[g + 1] - lo;
+    int64_t pos = off[g];
+    for (int32_t t0 = 0; t0 < nub; t0 += 64) {
+        const int32_t t = t0 + lane;
+        bool miss = false;
+        uint32_t b = 0;
+        if (t < nub) {
+            b = ub[t];
+            int32_t l = 0, h = n;  // is b among the group's beta strings?
+            while (l < h) {
+                const int32_t m = (l + h) >> 1;
+                if (sb[lo + m] < b)
+                    l = m + 1;
+                else
+                    h = m;
+            }
+            miss = !(l < n && sb[lo + l] == b);
+        }
+        const uint64_t m = __ballot(miss);
+        if (miss) {
+            const int64_t k = pos + __popcll(m & ((1ull << lane) - 1ull));
+            if (k < cap) {
+                oa[k] = ua[g];
+                ob[k] = b;
+            }
+        }
+        pos += __popcll(m);
+    }
+}
+
+}  // namespace
+
+int64_t product_closure(Ctx &c, int64_t cap, uint64_t *out_a, uint64_t *out_b) {
+    hipStream_t s = c.stream;
+    const int64_t total = (int64_t)c.nua * c.nub - c.ndet;
+    if (cap <= 0 || total <= 0) return total;
+    DBuf<int64_t> miss, off;
+    miss.ensure(c.nua + 1);
+    off.ensure(c.nua + 1);
+    HQ_CHECK(hipMemsetAsync(miss.p + c.nua, 0, sizeof(int64_t), s));
+    hipLaunchKernelGGL(k_missing_counts, dim3(grid_for(c.nua, 256)), dim3(256), 0, s, c.ga.p, c.nua, c.nub, miss.p);
+    HQ_LAUNCH_CHECK();
+    exclusive_scan_i64(s, miss.p, off.p, c.nua + 1, c.work);
+    hipLaunchKernelGGL(k_missing_list, dim3(grid_for((int64_t)c.nua * 64, 256)), dim3(256), 0, s, c.ua.p, c.ub.p,
+                       c.sb.p, c.ga.p, c.nua, c.nub, off.p, cap, out_a, out_b);
+    HQ_LAUNCH_CHECK();
+    HQ_CHECK(hipStreamSynchronize(s));
+    return total;
+}
+
+}  // namespace hinqs

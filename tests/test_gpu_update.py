@@ -237,3 +237,32 @@ def test_update_large_orbital_count_and_rule_errors():
         s.grow_basis(ea[:20], eb[:20], bad, 10)
     assert ex.value.name == "NONFINITE"
     assert s.ndet == len(na_)
+
+
+def test_product_closure_and_its_energy():
+    """The closure list equals the oracle's; appended with an update, the
+    lowest eigenvalue on the product space matches the oracle's dense value
+    and lies at or below the value on the set (variational)."""
+    norb, na, nb = 8, 4, 4
+    log("product-space closure")
+    ints = W.gen_integrals(norb, norb, -2.0, -0.5, 71)
+    a, b = W.sample_determinants(norb, na, nb, 400, 0.3, 0.0, 72)
+    s = solver_for(ints, a, b, na, nb)
+    ca, cb = s.product_closure()
+    ra, rb = oracle.product_closure(a, b)
+    assert np.array_equal(_strs(ca), ra) and np.array_equal(_strs(cb), rb)
+    e_b, _, _ = s.lowest_eigenpair(tol=1e-9)
+    s.update_determinants(ca, cb)
+    pa, pb = np.concatenate([a, ra]), np.concatenate([b, rb])
+    e_ref, _ = oracle_for(ints, pa, pb, na, nb).lowest_eigenpair()
+    e_p, _, _ = s.lowest_eigenpair(tol=1e-9)
+    assert abs(e_p - e_ref) <= 1e-10 and e_p <= e_b + 1e-12
+    assert len(s.product_closure()[0]) == 0
+    # the 20,000-determinant set: the closure is the rest of the full space
+    ints, a, b, cfg = W.config_inputs(1)
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    ca, cb = s.product_closure()
+    ra, rb = oracle.product_closure(a, b)
+    inf = s.info()
+    assert np.array_equal(_strs(ca), ra) and np.array_equal(_strs(cb), rb)
+    assert len(ra) == inf["n_alpha_strings"] * inf["n_beta_strings"] - len(a)

@@ -203,3 +203,18 @@ def test_grow_basis_rules_hand_example():
     assert kept == [0, 2] and apps == [0, 2, 3]
     # a capped append can also drop a just-chosen candidate
     assert oracle.grow_basis([9.0, 8.0], [1.0, 7.0], 2, b_max=3) == ([0, 1], [1])
+
+
+def test_product_closure_definition():
+    """{(a1,b1), (a2,b2)} closes to the two cross pairs; the full space closes
+    to nothing; in general |closure| = |UA| |UB| - |B|."""
+    a = np.array([3, 5], dtype=np.uint64)
+    b = np.array([6, 9], dtype=np.uint64)
+    ca, cb = oracle.product_closure(a, b)
+    assert list(zip(ca.tolist(), cb.tolist())) == [(3, 9), (5, 6)]
+    fa, fb = W.full_space(5, 2, 2)
+    assert len(oracle.product_closure(fa, fb)[0]) == 0
+    rng = np.random.default_rng(2)
+    pick = rng.choice(len(fa), 30, replace=False)
+    ca, cb = oracle.product_closure(fa[pick], fb[pick])
+    assert len(ca) == len(set(fa[pick].tolist())) * len(set(fb[pick].tolist())) - 30
