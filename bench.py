@@ -77,7 +77,7 @@ def sigma_counter_run(hq, ints, alpha, beta, cfg, reps):
     s = hq.Hinqs(0)
     s.set_integrals(ints.h, ints.eri, ints.e_core)
     s.set_determinants(alpha, beta, cfg.na, cfg.nb)
-    shape, _ = s.autotune(cfg.k, hq.HINQS_FP64)  # the launch shape the step's FP64 solves use
+    # the default launch shape, the one the step's FP64 solves use
     X = torch.randn(len(alpha), cfg.k, dtype=torch.float64, device="cuda")
     S = torch.empty_like(X)
     for _ in range(max(1, reps)):
@@ -88,7 +88,7 @@ def sigma_counter_run(hq, ints, alpha, beta, cfg, reps):
         torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
     print(json.dumps({"mode": "sigma", "ndet": len(alpha), "nnz": s.info()["nnz"], "launches": reps,
-                      "shape": shape}))
+                      "shape": "default"}))
 
 
 def batch_inputs(n=64):
@@ -268,10 +268,10 @@ def main():
         solver.set_integrals(ints.h, ints.eri, ints.e_core)
         solver.set_determinants(a_d, b_d, cfg.na, cfg.nb)
         t1 = time.perf_counter()
-        e64, c64, st64 = solver.lowest_eigenpair(tol=cfg.tol, block=cfg.k, autotune=True)
+        e64, c64, st64 = solver.lowest_eigenpair(tol=cfg.tol, block=cfg.k)
         last["c64"] = c64
         t2 = time.perf_counter()
-        em, cm, stm = solver.lowest_eigenpair(tol=cfg.tol, block=cfg.k, mixed=True, autotune=True)
+        em, cm, stm = solver.lowest_eigenpair(tol=cfg.tol, block=cfg.k, mixed=True)
         t3 = time.perf_counter()
         d1, d2 = solver.rdm12(c64)
         stream.synchronize()

@@ -868,11 +868,6 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     const int maxit = o.max_iter > 0 ? o.max_iter : 200;
     const bool use_graph = !(o.flags & HINQS_NO_GRAPH);
     const bool sorted = (o.flags & HINQS_SORTED_ORDER) != 0;
-    if (!B.g.sigma_ctr.p) {  // sigma row counters: zero now, kept at zero by every launch
-        B.g.sigma_ctr.ensure(SIGMA_CTR_WORDS);
-        HQ_CHECK(hipMemsetAsync(B.g.sigma_ctr.p, 0, sizeof(unsigned long long) * SIGMA_CTR_WORDS, c.stream));
-        HQ_CHECK(hipStreamSynchronize(c.stream));
-    }
     if (o.flags & HINQS_AUTOTUNE) autotune_sigma(B.g, KK, HINQS_FP64);
     const SigmaCfg scfg = sigma_config(B.g, KK, HINQS_FP64);
 

@@ -98,7 +98,7 @@ struct XcdRows {
 // MASK (batched instances): the XCD row ranges come from device memory and the
 // rows of finished instances are skipped; a team jumps over a finished
 // instance in one step, so the cost does not grow with its size.
-// Row counters (ctr, null for the fixed-stride walk): instead of a fixed stride, the team
+// Row counters (ctr, not for MASK): instead of a fixed stride, the team
 // leader takes the XCD's next run of `run` rows from a counter, so the teams of an XCD stay
 // on neighbouring rows however unequal the rows are; with fixed strides the
 // teams drift apart and the X rows in flight no longer share the XCD's L2
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges, SigmaMask
         }
         return rw;
     };
-    const bool dyn = ctr != nullptr;
+    const bool dyn = !MASK && ctr != nullptr;
     unsigned long long *const myctr = dyn ? ctr + xcd * CTR_STRIDE : nullptr;
     auto take = [&]() -> unsigned long long {  // result valid on the team leader only
         unsigned long long v = 0;
@@ -163,9 +163,9 @@ __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges, SigmaMask
         return v;
     };
     auto first_row = [&](unsigned long long v) -> int64_t { return r0 + (int64_t)__shfl(v, 0, TEAM); };
+    int64_t run_end = 0;  // end of the run of rows taken last
     auto finish = [&]() {
         if (dyn && sub == 0) {
-            __threadfence();  // this team's counter updates land before it counts as done
             const unsigned long long d = atomicAdd(myctr + CTR_DONE, 1ull);
             if (d + 1 == (unsigned long long)nteams) {
                 atomicExch(myctr, 0ull);
@@ -173,43 +173,12 @@ __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges, SigmaMask
             }
         }
     };
-    // Dynamic rows: run_end ends the run taken last, pend holds the take of
-    // the next run (issued when a run starts).  advance(rw) returns the first
-    // row to process at or after rw: inside the run, skipping rows of finished
-    // instances (MASK), else from the next run; >= r1 when none is left, with
-    // no take outstanding.  A run that starts in a finished instance which
-    // outlasts it pushes the counter past that instance, so the teams leave a
-    // finished instance after a few takes, whatever its size.
-    int64_t run_end = 0;
     unsigned long long pend = 0;
-    auto advance = [&](int64_t rw) -> int64_t {
-        for (;;) {
-            if constexpr (MASK) {
-                while (rw < run_end) {
-                    if (rw >= inst_end) {
-                        const int32_t b = mk.row_inst[rw];
-                        inst_end = mk.inst_row[b + 1];
-                        inst_done = mk.done[b] != 0;
-                    }
-                    if (!inst_done) return rw;
-                    rw = inst_end;
-                }
-                if (inst_done && inst_end > run_end && sub == 0)
-                    atomicMax(myctr, (unsigned long long)(min(inst_end, r1) - r0));
-            } else {
-                if (rw < run_end) return rw;
-            }
-            const int64_t nr = first_row(pend);
-            if (nr >= r1) return nr;
-            run_end = min(nr + run, r1);
-            pend = take();
-            rw = nr;
-        }
-    };
     int64_t row;
     if (dyn) {
-        pend = take();
-        row = advance(0);
+        row = first_row(take());
+        run_end = min(row + run, r1);
+        if (row < r1) pend = take();
     } else {
         row = live_row(r0 + team0);
     }
@@ -221,7 +190,13 @@ __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges, SigmaMask
     for (;;) {
         int64_t nrow;
         if (dyn) {
-            nrow = advance(row + 1);
+            if (row + 1 < run_end) {
+                nrow = row + 1;
+            } else {
+                nrow = first_row(pend);
+                run_end = min(nrow + run, r1);
+                if (nrow < r1) pend = take();
+            }
         } else {
             nrow = live_row(row + nteams);
         }
@@ -491,7 +466,7 @@ void launch_sigma_u(const Ctx &c, const SigmaCfg &cfg, const SigmaMask &mk, cons
     else
         hipLaunchKernelGGL((k_sigma<T, K, TEAM, UNR, MASK>), dim3((unsigned)nblk), dim3(SIGMA_BLOCK), 0, s,
                            ranges, mk, xmap, c.rowptr.p, c.col.p, val, diag, X, ldx, S, lds,
-                           c.sigma_ctr.p, std::max(1, cfg.run));
+                           MASK ? (unsigned long long *)nullptr : c.sigma_ctr.p, std::max(1, cfg.run));
     HQ_LAUNCH_CHECK();
 }
 
