@@ -279,6 +279,17 @@ struct Ctx {
 
     // workspace shared by calls
     DBuf<char> work;
+    // temporaries of building a set (kept between builds, so rebuilding, or
+    // building the instances of a batch one after another, allocates rarely)
+    struct BuildScratch {
+        DBuf<uint64_t> up_a, up_b, keys;
+        DBuf<uint32_t> da, db, sbm;
+        DBuf<int32_t> vals, flag, scan, dup, gidx;
+        DBuf<unsigned long long> bad;
+        DBuf<int64_t> counts;
+        DBuf<double> eri_full;
+        DBuf<char> sort;
+    } bs;
 
     // independent instances solved together (hinqs_batch_*)
     std::shared_ptr<BatchState> batch;
@@ -306,6 +317,10 @@ void exclusive_scan_i32(hipStream_t s, const int32_t *in, int32_t *out, int64_t 
 // Stable LSD radix sort of `keys` (nbits significant low bits) carrying `vals`.
 void radix_sort_u64(hipStream_t s, uint64_t *keys, int32_t *vals, int64_t n, int nbits,
                     DBuf<char> &tmp);
+// The same with the sort's own buffers in `own` (kept by the caller; no
+// synchronization at the end).
+void radix_sort_u64(hipStream_t s, uint64_t *keys, int32_t *vals, int64_t n, int nbits, DBuf<char> &tmp,
+                    DBuf<char> &own);
 
 // Sigma (sigma.hip): S = H X in sorted order with leading dimensions.
 void sigma_sorted(Ctx &c, int k, const void *X, int ldx, void *S, int lds, int precision,

@@ -164,7 +164,7 @@ void build_connectivity(Ctx &c) {
     ConnArgs a{n,          c.sa.p,        c.sb.p,    c.aidx.p,      c.bidx.p,
                c.ga.p,     c.gb.p,        c.bperm.p, c.bm_alpha.p,  c.alink_ptr.p,
                c.alink.p,  c.alink_info.p, c.alink_max};
-    DBuf<int64_t> counts;
+    auto &counts = c.bs.counts;
     counts.ensure(n + 1);
     dim3 g(grid_for(n, 256)), b(256);
     hipLaunchKernelGGL(k_connect<false>, g, b, 0, s, a, counts.p, (const int64_t *)nullptr,

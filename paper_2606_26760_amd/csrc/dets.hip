@@ -222,7 +222,7 @@ void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint6
     c.have_dets = false;
     c.have_elements = false;
     hipStream_t s = c.stream;
-    DBuf<uint64_t> up_a, up_b;
+    auto &up_a = c.bs.up_a, &up_b = c.bs.up_b;
     const uint64_t *da64 = alpha, *db64 = beta;
     if (!on_device) {
         up_a.ensure(ndet);
@@ -232,10 +232,10 @@ void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint6
         da64 = up_a.p;
         db64 = up_b.p;
     }
-    DBuf<uint32_t> da, db;
+    auto &da = c.bs.da, &db = c.bs.db;
     da.ensure(ndet);
     db.ensure(ndet);
-    DBuf<unsigned long long> bad;
+    auto &bad = c.bs.bad;
     bad.ensure(2);
     unsigned long long init[2] = {~0ull, 0ull};
     HQ_CHECK(hipMemcpyAsync(bad.p, init, sizeof(init), hipMemcpyHostToDevice, s));
@@ -255,9 +255,8 @@ void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint6
     c.na = na;
     c.nb = nb;
 
-    DBuf<uint64_t> keys;
-    DBuf<int32_t> vals, flag, scan;
-    DBuf<int32_t> dup;
+    auto &keys = c.bs.keys;
+    auto &vals = c.bs.vals, &flag = c.bs.flag, &scan = c.bs.scan, &dup = c.bs.dup;
     keys.ensure(ndet);
     vals.ensure(ndet);
     flag.ensure(ndet);
@@ -267,7 +266,7 @@ void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint6
     dim3 g(grid_for(ndet, 256)), b(256);
     hipLaunchKernelGGL(k_make_keys, g, b, 0, s, da.p, db.p, ndet, norb, keys.p, vals.p);
     HQ_LAUNCH_CHECK();
-    radix_sort_u64(s, keys.p, vals.p, ndet, 2 * norb, c.work);
+    radix_sort_u64(s, keys.p, vals.p, ndet, 2 * norb, c.work, c.bs.sort);
 
     c.sa.ensure(ndet);
     c.sb.ensure(ndet);
@@ -299,8 +298,8 @@ void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint6
     // ---- beta-major listing: keys (beta << norb | alpha), values = sorted position
     hipLaunchKernelGGL(k_make_keys, g, b, 0, s, c.sb.p, c.sa.p, ndet, norb, keys.p, vals.p);
     HQ_LAUNCH_CHECK();
-    radix_sort_u64(s, keys.p, vals.p, ndet, 2 * norb, c.work);
-    DBuf<uint32_t> sbm;
+    radix_sort_u64(s, keys.p, vals.p, ndet, 2 * norb, c.work, c.bs.sort);
+    auto &sbm = c.bs.sbm;
     sbm.ensure(ndet);
     c.bperm.ensure(ndet);
     c.bm_alpha.ensure(ndet);
@@ -314,7 +313,7 @@ void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint6
     c.nub = last[0] + last[1];
     c.ub.ensure(c.nub);
     c.gb.ensure(c.nub + 1);
-    DBuf<int32_t> gidx_bm;
+    auto &gidx_bm = c.bs.gidx;
     gidx_bm.ensure(ndet);
     hipLaunchKernelGGL(k_groups, g, b, 0, s, sbm.p, flag.p, scan.p, ndet, gidx_bm.p, c.ub.p, c.gb.p);
     HQ_LAUNCH_CHECK();

@@ -140,7 +140,7 @@ void build_integrals(Ctx &c, int norb, const double *h, const double *eri, doubl
     hipStream_t s = c.stream;
     c.d_h.ensure(n2);
     HQ_CHECK(hipMemcpyAsync(c.d_h.p, h, sizeof(double) * n2, hipMemcpyHostToDevice, s));
-    DBuf<double> full;
+    auto &full = c.bs.eri_full;
     full.ensure(n4);
     HQ_CHECK(hipMemcpyAsync(full.p, eri, sizeof(double) * n4, hipMemcpyHostToDevice, s));
     const int np = neri_packed(norb);

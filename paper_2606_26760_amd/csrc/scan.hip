@@ -208,6 +208,13 @@ void exclusive_scan_i32(hipStream_t s, const int32_t *in, int32_t *out, int64_t 
 
 void radix_sort_u64(hipStream_t s, uint64_t *keys, int32_t *vals, int64_t n, int nbits,
                     DBuf<char> &tmp) {
+    DBuf<char> own;
+    radix_sort_u64(s, keys, vals, n, nbits, tmp, own);
+    HQ_CHECK(hipStreamSynchronize(s));  // `own` is released on return
+}
+
+void radix_sort_u64(hipStream_t s, uint64_t *keys, int32_t *vals, int64_t n, int nbits, DBuf<char> &tmp,
+                    DBuf<char> &own) {
     if (n <= 1) return;
     if (n >= (int64_t)1 << 31) throw Error(HINQS_E_UNSUPPORTED, "radix sort limited to 2^31 items");
     const int ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
@@ -218,7 +225,6 @@ void radix_sort_u64(hipStream_t s, uint64_t *keys, int32_t *vals, int64_t n, int
     size_t off_keys = (off_offsets + sizeof(int32_t) * ncount + 255) & ~(size_t)255;
     size_t off_vals = off_keys + sizeof(uint64_t) * n;
     size_t total = off_vals + sizeof(int32_t) * n + 256;
-    DBuf<char> own;
     own.ensure(total);
     int32_t *counts = (int32_t *)(own.p + off_counts);
     int32_t *offsets = (int32_t *)(own.p + off_offsets);
@@ -244,7 +250,6 @@ void radix_sort_u64(hipStream_t s, uint64_t *keys, int32_t *vals, int64_t n, int
         HQ_CHECK(hipMemcpyAsync(keys, kin, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
         HQ_CHECK(hipMemcpyAsync(vals, vin, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
     }
-    HQ_CHECK(hipStreamSynchronize(s));  // `own` is released on return
 }
 
 }  // namespace hinqs
