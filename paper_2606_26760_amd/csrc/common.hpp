@@ -290,6 +290,20 @@ struct Ctx {
         DBuf<double> eri_full;
         DBuf<char> sort;
     } bs;
+    // Davidson workspace (basis, images, staging), kept between solves
+    struct DavidsonWork {
+        DBuf<double> Vb, Wb, T, Wn, small, partial, nrm, argv, xfin, signbuf;
+        DBuf<float> X32, S32;
+        DBuf<int32_t> guess_idx;
+        DBuf<int64_t> argi;
+        double *pinned = nullptr;  // host staging ring (hipHostMalloc)
+        DavidsonWork() = default;
+        DavidsonWork(const DavidsonWork &) = delete;
+        DavidsonWork &operator=(const DavidsonWork &) = delete;
+        ~DavidsonWork() {
+            if (pinned) (void)hipHostFree(pinned);
+        }
+    } dw;
 
     // independent instances solved together (hinqs_batch_*)
     std::shared_ptr<BatchState> batch;

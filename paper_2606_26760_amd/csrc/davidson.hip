@@ -535,13 +535,14 @@ struct Solver {
     int K;        // block size (compile-time kernel variant)
     int mmax;     // largest subspace
     int nblocks;  // column blocks of V and W
-    DBuf<double> Vb, Wb, T, Wn, small, partial, nrm;
+    // workspace kept in the context between solves
+    DBuf<double> &Vb, &Wb, &T, &Wn, &small, &partial, &nrm;
     Mat V{}, W{}, Tm{}, Wnm{};
-    DBuf<float> X32, S32;
-    DBuf<int32_t> guess_idx;
-    DBuf<double> argv;
-    DBuf<int64_t> argi;
-    DBuf<double> xfin, signbuf;
+    DBuf<float> &X32, &S32;
+    DBuf<int32_t> &guess_idx;
+    DBuf<double> &argv;
+    DBuf<int64_t> &argi;
+    DBuf<double> &xfin, &signbuf;
     int nblk_gram = 1;
     std::vector<hipEvent_t> evs;  // start/stop pairs around every sigma product, read at the end
     double ms_sigma = 0.0;
@@ -552,7 +553,11 @@ struct Solver {
     double *pinned = nullptr;
     int upload_count = 0;
 
-    Solver(Ctx &cc, int k, int m_max) : c(cc), s(cc.stream), D(cc.ndet), K(k), mmax(m_max) {
+    Solver(Ctx &cc, int k, int m_max)
+        : c(cc), s(cc.stream), D(cc.ndet), K(k), mmax(m_max), Vb(cc.dw.Vb), Wb(cc.dw.Wb), T(cc.dw.T),
+          Wn(cc.dw.Wn), small(cc.dw.small), partial(cc.dw.partial), nrm(cc.dw.nrm), X32(cc.dw.X32),
+          S32(cc.dw.S32), guess_idx(cc.dw.guess_idx), argv(cc.dw.argv), argi(cc.dw.argi), xfin(cc.dw.xfin),
+          signbuf(cc.dw.signbuf) {
         nblocks = (mmax + K - 1) / K;
         const size_t bsz = (size_t)D * K;
         Vb.ensure(bsz * nblocks);
@@ -571,13 +576,13 @@ struct Solver {
         HQ_CHECK(hipMemsetAsync(Wb.p, 0, sizeof(double) * bsz * nblocks, s));
         HQ_CHECK(hipMemsetAsync(T.p, 0, sizeof(double) * bsz, s));
         HQ_CHECK(hipMemsetAsync(Wn.p, 0, sizeof(double) * bsz, s));
-        HQ_CHECK(hipHostMalloc((void **)&pinned, sizeof(double) * SLOTS * SLOT_DOUBLES, hipHostMallocDefault));
+        if (!c.dw.pinned)
+            HQ_CHECK(hipHostMalloc((void **)&c.dw.pinned, sizeof(double) * SLOTS * SLOT_DOUBLES,
+                                   hipHostMallocDefault));
+        pinned = c.dw.pinned;
     }
     ~Solver() {
-        if (pinned) {
-            (void)hipStreamSynchronize(s);
-            (void)hipHostFree(pinned);
-        }
+        (void)hipStreamSynchronize(s);  // the staging ring is free for the next solve
         for (auto e : evs) (void)hipEventDestroy(e);
     }
 
