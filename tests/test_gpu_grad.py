@@ -19,7 +19,6 @@ import itertools
 import numpy as np
 import pytest
 
-import oracle
 import workloads as W
 from tests.gpu_helpers import log, oracle_for, solver_for
 
