@@ -3,17 +3,18 @@
 // nonzero <x_i|H|x_j> (Slater-Condon rules; paper Sec. 2.2, Step 3 builds
 // [H_B]_ij over exactly these pairs).
 //
-// One thread per row (sorted order).  The three classes are found without an
-// O(|B|^2) scan:
+// The three classes are found without an O(|B|^2) scan:
 //   alpha-only moves   x_j shares beta_i: scan the beta group of beta_i;
 //   beta-only moves    x_j shares alpha_i: scan the alpha group of alpha_i;
 //   alpha+beta moves   alpha_j is a single move of alpha_i present in B (alpha
 //                      link table): scan that alpha group for beta strings one
 //                      move away.
 // Each candidate is tested with XOR + popcount; the sign comes from masked
-// popcounts (common.hpp).  Neighbouring threads usually share alpha_i and so
-// walk the same groups in lock step, which turns the string loads into
-// broadcasts.  A counting pass sizes each row; a fill pass writes (col, desc).
+// popcounts (common.hpp).  The alpha-only class runs one thread per entry of
+// the beta-major listing and the other two one thread per sorted row, so in
+// both kernels neighbouring threads share the string whose groups they walk,
+// which turns the string loads into broadcasts.  A counting pass sizes each
+// row; a fill pass writes (col, desc), alpha-only entries first.
 #include <chrono>
 
 #include "common.hpp"
@@ -32,16 +33,21 @@ struct ConnArgs {
     int alink_max;
 };
 
+// Alpha-only moves (x_j shares beta_i), one thread per entry of the
+// beta-major listing: neighbouring threads share beta_i and scan the same
+// beta group in lock step (broadcast loads), where one thread per sorted row
+// would scan a different beta group on every lane.  Counting pass: n1[i];
+// filling pass: the row's first n1[i] entries.
 template <bool FILL>
-__global__ __launch_bounds__(256) void k_connect(ConnArgs a, int64_t *counts, const int64_t *rowptr,
-                                                 int32_t *col, uint32_t *desc) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.ndet) return;
-    const uint32_t ai = a.sa[i], bi = a.sb[i];
-    const int32_t ag = a.aidx[i], bg = a.bidx[i];
+__global__ __launch_bounds__(256) void k_connect_beta(ConnArgs a, int32_t *n1, const int64_t *rowptr,
+                                                      int32_t *col, uint32_t *desc) {
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t0 >= a.ndet) return;
+    const int32_t i = a.bperm[t0];
+    const uint32_t ai = a.bm_alpha[t0];
+    const int32_t bg = a.bidx[i];
     int64_t out = FILL ? rowptr[i] : 0;
-    int64_t n = 0;
-    // alpha-only: determinants with the same beta string
+    int32_t n = 0;
     for (int32_t t = a.gb[bg], e = a.gb[bg + 1]; t < e; ++t) {
         const uint32_t aj = a.bm_alpha[t];
         const int d = popc32(ai ^ aj);
@@ -54,6 +60,22 @@ __global__ __launch_bounds__(256) void k_connect(ConnArgs a, int64_t *counts, co
             ++n;
         }
     }
+    if (!FILL) n1[i] = n;
+}
+
+// Beta-only and alpha+beta moves, one thread per sorted row (neighbouring
+// rows share alpha_i, so their group scans are broadcast loads).  Counting
+// pass: counts[i] = n1[i] + these; filling pass: after the row's n1[i]
+// alpha-only entries.
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_connect(ConnArgs a, const int32_t *n1, int64_t *counts,
+                                                 const int64_t *rowptr, int32_t *col, uint32_t *desc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.ndet) return;
+    const uint32_t ai = a.sa[i], bi = a.sb[i];
+    const int32_t ag = a.aidx[i];
+    int64_t out = FILL ? rowptr[i] + n1[i] : 0;
+    int64_t n = 0;
     // beta-only: determinants with the same alpha string
     for (int32_t j = a.ga[ag], e = a.ga[ag + 1]; j < e; ++j) {
         const uint32_t bj = a.sb[j];
@@ -86,7 +108,7 @@ __global__ __launch_bounds__(256) void k_connect(ConnArgs a, int64_t *counts, co
             }
         }
     }
-    if (!FILL) counts[i] = n;
+    if (!FILL) counts[i] = n1[i] + n;
 }
 
 // bounds[x] = first row whose couplings start at or after x * total / 8 (x = 0..8).
@@ -165,9 +187,14 @@ void build_connectivity(Ctx &c) {
                c.ga.p,     c.gb.p,        c.bperm.p, c.bm_alpha.p,  c.alink_ptr.p,
                c.alink.p,  c.alink_info.p, c.alink_max};
     auto &counts = c.bs.counts;
+    auto &n1 = c.bs.gidx;  // alpha-only couplings per row (free once the tables are built)
     counts.ensure(n + 1);
+    n1.ensure(n);
     dim3 g(grid_for(n, 256)), b(256);
-    hipLaunchKernelGGL(k_connect<false>, g, b, 0, s, a, counts.p, (const int64_t *)nullptr,
+    hipLaunchKernelGGL(k_connect_beta<false>, g, b, 0, s, a, n1.p, (const int64_t *)nullptr, (int32_t *)nullptr,
+                       (uint32_t *)nullptr);
+    HQ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_connect<false>, g, b, 0, s, a, (const int32_t *)n1.p, counts.p, (const int64_t *)nullptr,
                        (int32_t *)nullptr, (uint32_t *)nullptr);
     HQ_LAUNCH_CHECK();
     HQ_CHECK(hipMemsetAsync(counts.p + n, 0, sizeof(int64_t), s));
@@ -180,8 +207,10 @@ void build_connectivity(Ctx &c) {
     c.nnz = nnz;
     c.col.ensure(nnz);
     c.desc.ensure(nnz);
-    hipLaunchKernelGGL(k_connect<true>, g, b, 0, s, a, (int64_t *)nullptr, c.rowptr.p, c.col.p,
-                       c.desc.p);
+    hipLaunchKernelGGL(k_connect_beta<true>, g, b, 0, s, a, (int32_t *)nullptr, c.rowptr.p, c.col.p, c.desc.p);
+    HQ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_connect<true>, g, b, 0, s, a, (const int32_t *)n1.p, (int64_t *)nullptr, c.rowptr.p,
+                       c.col.p, c.desc.p);
     HQ_LAUNCH_CHECK();
     compute_xcd_rows(c);
     for (auto &row : c.sigma_cfg)
