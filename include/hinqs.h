@@ -8,6 +8,11 @@
  * [H_B]_ij = <x_i|H|x_j> (Sec. 2.2, Step 3), applies it to blocks of vectors
  * and finds its lowest eigenpair with a Davidson eigensolver (Step 3), which
  * yields E_0 and Psi_0 as a linear combination of the determinants of B.
+ * Around that solve it provides the selection steps of the same section:
+ * the classical expansion of B (Eq. 2), PT2 scores of candidates (Eq. 3),
+ * stable top-k ranking, incremental updates of B with the growth rules of
+ * Step 2, the product-space closure of B, and the spin-marginal teacher
+ * weights of Psi_0 (Step 4, Eqs. 5-6).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
