@@ -1172,7 +1172,7 @@ int batch_add(Ctx &c, int norb, const double *h, const double *eri, double ecore
         } grow;
         build_integrals(p, norb, h, eri, ecore);
         build_determinants(p, ndet, alpha, beta, na, nb, false);
-        build_connectivity(p);
+        build_connectivity(p, false);
         build_elements(p);
     }
     // append to the concatenated arrays

@@ -315,7 +315,9 @@ struct Ctx {
 void build_integrals(Ctx &c, int norb, const double *h, const double *eri, double ecore);
 void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint64_t *beta, int na,
                         int nb, bool on_device);
-void build_connectivity(Ctx &c);
+// xcd_rows: also split the rows over the XCDs for sigma (a host read; not
+// needed for a set that is only an instance of a batch being assembled).
+void build_connectivity(Ctx &c, bool xcd_rows = true);
 void build_elements(Ctx &c);
 // Values of the entries of each row after its first skip[row] (whose values
 // are already in place), and every diagonal element.

@@ -179,7 +179,7 @@ void compute_xcd_rows(Ctx &c) {
     HQ_CHECK(hipStreamSynchronize(s));
 }
 
-void build_connectivity(Ctx &c) {
+void build_connectivity(Ctx &c, bool xcd_rows) {
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = c.stream;
     const int64_t n = c.ndet;
@@ -212,7 +212,7 @@ void build_connectivity(Ctx &c) {
     hipLaunchKernelGGL(k_connect<true>, g, b, 0, s, a, (const int32_t *)n1.p, (int64_t *)nullptr, c.rowptr.p,
                        c.col.p, c.desc.p);
     HQ_LAUNCH_CHECK();
-    compute_xcd_rows(c);
+    if (xcd_rows) compute_xcd_rows(c);
     for (auto &row : c.sigma_cfg)
         for (auto &g : row) g = SigmaCfg{};
     c.ms_connect =
