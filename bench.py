@@ -20,7 +20,9 @@ value = H.X elements applied by the sigma products of the step
         parts) / step time.
 The roofline object covers the FP64 sigma kernel: algorithmic bytes per launch
 (12 nnz + 16 k ndet + 16 ndet + 8) over its average launch time, taken from
-HIP events recorded around each launch on the library's stream.
+HIP events recorded around each launch on the library's stream; sigma_kernel
+adds the counter-measured traffic rate (profiles/sigma_traffic.json) and a
+measured device-to-device copy rate as the practical HBM ceiling.
 cpu_baseline times the CPU oracle's matrix-free sigma on a bounded row sample.
 
 After the timed steps, the "select" object times one pass of the selection
@@ -205,6 +207,24 @@ def cpu_pt2_rate(o, c, e0, ya, yb, n=40000):
             "sample": f"first {m} expanded determinants, {dt:.2f} s"}
 
 
+def copy_peak_gbs(nbytes=2 << 30, reps=10):
+    """Device-to-device copy rate (bytes read + written per second, GB/s) of
+    a 2 GiB buffer: the practical HBM ceiling next to the 8 TB/s spec."""
+    import torch
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2 * nbytes / t / 1e9
+
+
 def recorded_traffic():
     """HBM bytes per FP64 sigma launch from the committed counter summary, or None
     when the sigma kernel source has changed since the counters were taken."""
@@ -313,6 +333,7 @@ def main():
     k = cfg.k
     alg_bytes = 12 * nnz + 16 * k * D + 8 * (D + 1) + 8 * D
     achieved = alg_bytes / t_launch / 1e9
+    traffic = recorded_traffic()
     med = lambda xs: float(np.median(xs))
     out = {
         "metric": METRIC,
@@ -335,10 +356,14 @@ def main():
                    "ndet": D, "nnz": nnz, "block": k, "tol": cfg.tol,
                    "batch_instances": 0 if insts is None else len(insts)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_sigma (FP64 block sigma, k=8)",
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": t_launch * 1e3},
-        "sigma_kernel": {"elements_per_s": (nnz + D) * k / t_launch, "launches": n_sig},
+        "sigma_kernel": {"elements_per_s": (nnz + D) * k / t_launch, "rows_per_s": D * k / t_launch,
+                         "launches": n_sig,
+                         "traffic_gbs": None if traffic is None else traffic / t_launch / 1e9,
+                         "traffic_frac": None if traffic is None else traffic / t_launch / 1e9 / HBM_PEAK_GBS,
+                         "copy_peak_gbs": copy_peak_gbs()},
         "solve_ms": {"fp64": med([r[0]["fp64"] for r in res]) * 1e3,
                      "mixed": med([r[0]["mixed"] for r in res]) * 1e3},
         "build_ms": med([r[0]["build"] for r in res]) * 1e3,
