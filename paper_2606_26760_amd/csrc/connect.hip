@@ -23,6 +23,12 @@ namespace hinqs {
 
 namespace {
 
+// Group scans test SCAN_W candidates without branching, then emit the hits of
+// that step from a bit mask: the emission code (descriptor and two stores)
+// then runs about once per step instead of on every candidate where some lane
+// of the wave happens to hit.  Entries keep their order.
+constexpr int SCAN_W = 8;
+
 struct ConnArgs {
     int64_t ndet;
     const uint32_t *sa, *sb;
@@ -48,16 +54,23 @@ __global__ __launch_bounds__(256) void k_connect_beta(ConnArgs a, int32_t *n1, c
     const int32_t bg = a.bidx[i];
     int64_t out = FILL ? rowptr[i] : 0;
     int32_t n = 0;
-    for (int32_t t = a.gb[bg], e = a.gb[bg + 1]; t < e; ++t) {
-        const uint32_t aj = a.bm_alpha[t];
-        const int d = popc32(ai ^ aj);
-        if (d == 2 || d == 4) {
-            if (FILL) {
+    for (int32_t t0 = a.gb[bg], e = a.gb[bg + 1]; t0 < e; t0 += SCAN_W) {
+        uint32_t m = 0;
+#pragma unroll
+        for (int u = 0; u < SCAN_W; ++u) {
+            const uint32_t aj = t0 + u < e ? a.bm_alpha[t0 + u] : ai;
+            const int d = popc32(ai ^ aj);
+            m |= (d == 2 || d == 4) ? 1u << u : 0u;
+        }
+        if (FILL) {
+            for (; m; m &= m - 1) {
+                const int32_t t = t0 + lowbit(m);
                 col[out] = a.bperm[t];
-                desc[out] = same_spin_desc(ai, aj, HINQS_EXC_1A, HINQS_EXC_2AA);
+                desc[out] = same_spin_desc(ai, a.bm_alpha[t], HINQS_EXC_1A, HINQS_EXC_2AA);
                 ++out;
             }
-            ++n;
+        } else {
+            n += popc32(m);
         }
     }
     if (!FILL) n1[i] = n;
@@ -77,16 +90,23 @@ __global__ __launch_bounds__(256) void k_connect(ConnArgs a, const int32_t *n1, 
     int64_t out = FILL ? rowptr[i] + n1[i] : 0;
     int64_t n = 0;
     // beta-only: determinants with the same alpha string
-    for (int32_t j = a.ga[ag], e = a.ga[ag + 1]; j < e; ++j) {
-        const uint32_t bj = a.sb[j];
-        const int d = popc32(bi ^ bj);
-        if (d == 2 || d == 4) {
-            if (FILL) {
+    for (int32_t j0 = a.ga[ag], e = a.ga[ag + 1]; j0 < e; j0 += SCAN_W) {
+        uint32_t m = 0;
+#pragma unroll
+        for (int u = 0; u < SCAN_W; ++u) {
+            const uint32_t bj = j0 + u < e ? a.sb[j0 + u] : bi;
+            const int d = popc32(bi ^ bj);
+            m |= (d == 2 || d == 4) ? 1u << u : 0u;
+        }
+        if (FILL) {
+            for (; m; m &= m - 1) {
+                const int32_t j = j0 + lowbit(m);
                 col[out] = j;
-                desc[out] = same_spin_desc(bi, bj, HINQS_EXC_1B, HINQS_EXC_2BB);
+                desc[out] = same_spin_desc(bi, a.sb[j], HINQS_EXC_1B, HINQS_EXC_2BB);
                 ++out;
             }
-            ++n;
+        } else {
+            n += popc32(m);
         }
     }
     // alpha + beta: alpha string one move away, beta string one move away
@@ -96,15 +116,22 @@ __global__ __launch_bounds__(256) void k_connect(ConnArgs a, const int32_t *n1, 
         const uint32_t info = a.alink_info[lbase + l];
         const int ha = info & 31, pa = (info >> 5) & 31;
         const uint32_t npar = (info >> 10) & 1u;
-        for (int32_t j = a.ga[tgt], e = a.ga[tgt + 1]; j < e; ++j) {
-            const uint32_t bj = a.sb[j];
-            if (popc32(bi ^ bj) == 2) {
-                if (FILL) {
+        for (int32_t j0 = a.ga[tgt], e = a.ga[tgt + 1]; j0 < e; j0 += SCAN_W) {
+            uint32_t m = 0;
+#pragma unroll
+            for (int u = 0; u < SCAN_W; ++u) {
+                const uint32_t bj = j0 + u < e ? a.sb[j0 + u] : bi;
+                m |= popc32(bi ^ bj) == 2 ? 1u << u : 0u;
+            }
+            if (FILL) {
+                for (; m; m &= m - 1) {
+                    const int32_t j = j0 + lowbit(m);
                     col[out] = j;
-                    desc[out] = ab_desc(ha, pa, npar, bi, bj);
+                    desc[out] = ab_desc(ha, pa, npar, bi, a.sb[j]);
                     ++out;
                 }
-                ++n;
+            } else {
+                n += popc32(m);
             }
         }
     }
