@@ -93,6 +93,9 @@ __host__ __device__ inline int lowbit(uint32_t x) {  // index of lowest set bit,
 #endif
 }
 
+// Candidates tested per step of a group scan before the hits are emitted.
+constexpr int SCAN_W = 8;
+
 __host__ __device__ inline int highbit(uint32_t x) {  // index of highest set bit, x != 0
 #ifdef __HIP_DEVICE_COMPILE__
     return 31 - __clz(x);

@@ -27,8 +27,6 @@ namespace {
 // that step from a bit mask: the emission code (descriptor and two stores)
 // then runs about once per step instead of on every candidate where some lane
 // of the wave happens to hit.  Entries keep their order.
-constexpr int SCAN_W = 8;
-
 struct ConnArgs {
     int64_t ndet;
     const uint32_t *sa, *sb;

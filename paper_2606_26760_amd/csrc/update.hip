@@ -147,48 +147,70 @@ __global__ __launch_bounds__(256) void k_cross(CrossArgs a, int64_t *cnt, int64_
     }
     const uint32_t ai = a.sa[r], bi = a.sb[r];
     const int32_t gbA = a.bsame[a.bidx[r]];
+    // group scans: SCAN_W candidates tested branch-free, hits emitted from the mask
     if (gbA >= 0) {  // same beta string, alpha one or two moves away
-        for (int32_t u = a.gb_a[gbA], e = a.gb_a[gbA + 1]; u < e; ++u) {
-            const uint32_t aj = a.bm_alpha_a[u];
-            const int d = popc32(ai ^ aj);
-            if (d == 2 || d == 4) {
-                if (FILL) {
+        for (int32_t u0 = a.gb_a[gbA], e = a.gb_a[gbA + 1]; u0 < e; u0 += SCAN_W) {
+            uint32_t m = 0;
+#pragma unroll
+            for (int v = 0; v < SCAN_W; ++v) {
+                const uint32_t aj = u0 + v < e ? a.bm_alpha_a[u0 + v] : ai;
+                const int d = popc32(ai ^ aj);
+                m |= (d == 2 || d == 4) ? 1u << v : 0u;
+            }
+            if (FILL) {
+                for (; m; m &= m - 1) {
+                    const int32_t u = u0 + lowbit(m);
                     col[out] = a.amap[a.bperm_a[u]];
-                    desc[out] = pair_desc(ai, bi, aj, bi);
+                    desc[out] = pair_desc(ai, bi, a.bm_alpha_a[u], bi);
                     ++out;
                 }
-                ++n;
+            } else {
+                n += popc32(m);
             }
         }
     }
     const int32_t ag = a.aidx[r];
     const int32_t gaA = a.asame[ag];
     if (gaA >= 0) {  // same alpha string, beta one or two moves away
-        for (int32_t j = a.ga_a[gaA], e = a.ga_a[gaA + 1]; j < e; ++j) {
-            const uint32_t bj = a.sb_a[j];
-            const int d = popc32(bi ^ bj);
-            if (d == 2 || d == 4) {
-                if (FILL) {
+        for (int32_t j0 = a.ga_a[gaA], e = a.ga_a[gaA + 1]; j0 < e; j0 += SCAN_W) {
+            uint32_t m = 0;
+#pragma unroll
+            for (int v = 0; v < SCAN_W; ++v) {
+                const uint32_t bj = j0 + v < e ? a.sb_a[j0 + v] : bi;
+                const int d = popc32(bi ^ bj);
+                m |= (d == 2 || d == 4) ? 1u << v : 0u;
+            }
+            if (FILL) {
+                for (; m; m &= m - 1) {
+                    const int32_t j = j0 + lowbit(m);
                     col[out] = a.amap[j];
-                    desc[out] = pair_desc(ai, bi, ai, bj);
+                    desc[out] = pair_desc(ai, bi, ai, a.sb_a[j]);
                     ++out;
                 }
-                ++n;
+            } else {
+                n += popc32(m);
             }
         }
     }
     for (int32_t l = 0, le = a.xcnt[ag]; l < le; ++l) {  // one move in each spin
         const int32_t tg = a.xlink[(int64_t)ag * a.maxl + l];
         const uint32_t aj = a.ua_a[tg];
-        for (int32_t j = a.ga_a[tg], e = a.ga_a[tg + 1]; j < e; ++j) {
-            const uint32_t bj = a.sb_a[j];
-            if (popc32(bi ^ bj) == 2) {
-                if (FILL) {
+        for (int32_t j0 = a.ga_a[tg], e = a.ga_a[tg + 1]; j0 < e; j0 += SCAN_W) {
+            uint32_t m = 0;
+#pragma unroll
+            for (int v = 0; v < SCAN_W; ++v) {
+                const uint32_t bj = j0 + v < e ? a.sb_a[j0 + v] : bi;
+                m |= popc32(bi ^ bj) == 2 ? 1u << v : 0u;
+            }
+            if (FILL) {
+                for (; m; m &= m - 1) {
+                    const int32_t j = j0 + lowbit(m);
                     col[out] = a.amap[j];
-                    desc[out] = pair_desc(ai, bi, aj, bj);
+                    desc[out] = pair_desc(ai, bi, aj, a.sb_a[j]);
                     ++out;
                 }
-                ++n;
+            } else {
+                n += popc32(m);
             }
         }
     }
