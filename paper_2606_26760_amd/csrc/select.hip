@@ -269,18 +269,24 @@ __device__ inline void scan_alpha_group(const Pt2Args &a, const double *eri, con
             const int32_t j = j0 + 64 * u;
             bj[u] = j < hi ? a.B.sb[j] : ~xb;
         }
+        uint32_t m = 0, m0 = 0;  // entries needing a coupling value / the diagonal
 #pragma unroll
         for (int u = 0; u < SCAN_U; ++u) {
-            const int32_t j = j0 + 64 * u;
             const int db = popc32(xb ^ bj[u]);
             if (SAME_ALPHA) {
-                if (db == 0)
-                    acc += a.cs[j] * d;
-                else if (db <= 4)
-                    acc += a.cs[j] * coupling_value(eri, h, a.norb, pair_desc(xa, xb, aj, bj[u]), xa, xb);
-            } else if (db == 2) {
-                acc += a.cs[j] * coupling_value(eri, h, a.norb, pair_desc(xa, xb, aj, bj[u]), xa, xb);
+                m0 |= db == 0 ? 1u << u : 0u;
+                m |= (db != 0 && db <= 4) ? 1u << u : 0u;
+            } else {
+                m |= db == 2 ? 1u << u : 0u;
             }
+        }
+        // the hits in ascending order, so every lane sums its entries in group order
+        for (uint32_t mm = m | m0; mm; mm &= mm - 1) {
+            const int u = lowbit(mm);
+            const int32_t j = j0 + 64 * u;
+            const double v =
+                (m0 >> u) & 1u ? d : coupling_value(eri, h, a.norb, pair_desc(xa, xb, aj, a.B.sb[j]), xa, xb);
+            acc += a.cs[j] * v;
         }
     }
 }
@@ -397,12 +403,16 @@ __global__ __launch_bounds__(PT_NT) __attribute__((amdgpu_waves_per_eu(8, 8))) v
                     const int32_t q = u0 + 64 * v;
                     aj[v] = q < end ? a.B.bm_alpha[q] : xa;
                 }
+                uint32_t m = 0;
 #pragma unroll
                 for (int v = 0; v < SCAN_U; ++v) {
                     const int da = popc32(xa ^ aj[v]);
-                    if (da != 0 && da <= 4)
-                        acc += a.cs[a.B.bperm[u0 + 64 * v]] *
-                               coupling_value(eri, h, norb, pair_desc(xa, xb, aj[v], xb), xa, xb);
+                    m |= (da != 0 && da <= 4) ? 1u << v : 0u;
+                }
+                for (; m; m &= m - 1) {
+                    const int32_t q = u0 + 64 * lowbit(m);
+                    acc += a.cs[a.B.bperm[q]] *
+                           coupling_value(eri, h, norb, pair_desc(xa, xb, a.B.bm_alpha[q], xb), xa, xb);
                 }
             }
         }
