@@ -252,7 +252,7 @@ struct Pt2Args {
     unsigned *bad;
 };
 
-constexpr int SCAN_U = 4;  // group entries in flight per lane
+constexpr int SCAN_U = 8;  // group entries in flight per lane
 
 // acc += c_j <x|H|x_j> over the rows j in [lo, hi) of one alpha group (alpha
 // string aj) whose beta string differs from xb by a number of electrons in
