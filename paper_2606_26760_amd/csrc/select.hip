@@ -291,6 +291,33 @@ __device__ inline void scan_alpha_group(const Pt2Args &a, const double *eri, con
     }
 }
 
+// Linked alpha groups of at most PT2_GL * SCAN_U rows are scanned 64 / PT2_GL
+// at a time, PT2_GL lanes each and in a single step, so the chain of
+// dependent loads per candidate runs over a few batches of groups instead of
+// every group one after another.
+constexpr int PT2_GL = 16;
+constexpr int PT2_SMALL = PT2_GL * SCAN_U;
+
+// acc += c_j <x|H|x_j> over the rows j in [lo, hi) (at most PT2_SMALL of them)
+// of one alpha group (alpha string aj) whose beta string is one electron from
+// xb; sl is this lane's index among the PT2_GL lanes sharing the group.
+__device__ inline void scan_small_group(const Pt2Args &a, const double *eri, const double *h, int32_t lo,
+                                        int32_t hi, uint32_t xa, uint32_t xb, uint32_t aj, int sl, double &acc) {
+    uint32_t bj[SCAN_U];
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+        const int32_t j = lo + sl + PT2_GL * u;
+        bj[u] = j < hi ? a.B.sb[j] : ~xb;
+    }
+    uint32_t m = 0;
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) m |= popc32(xb ^ bj[u]) == 2 ? 1u << u : 0u;
+    for (; m; m &= m - 1) {
+        const int32_t j = lo + sl + PT2_GL * lowbit(m);
+        acc += a.cs[j] * coupling_value(eri, h, a.norb, pair_desc(xa, xb, aj, a.B.sb[j]), xa, xb);
+    }
+}
+
 // Candidate order for PT2: key (alpha << norb | beta) of each candidate
 // (0 for a malformed one; the main kernel checks every candidate itself).
 __global__ void k_pt2_keys(const uint64_t *ca, const uint64_t *cb, int64_t n, int norb, uint64_t *keys,
@@ -418,13 +445,30 @@ __global__ __launch_bounds__(PT_NT) __attribute__((amdgpu_waves_per_eu(8, 8))) v
         }
 #pragma unroll
         for (int r = 0; r < SLOTS; ++r) {
-            uint64_t found = __ballot(hi_m[r] > lo_m[r]);
+            const int32_t sz = hi_m[r] - lo_m[r];
+            uint64_t found = __ballot(sz > PT2_SMALL);  // large groups: the whole wave, one at a time
             while (found) {
                 const int src = __builtin_ctzll(found);
                 found &= found - 1;
                 const int32_t lo = __shfl(lo_m[r], src, 64), hi = __shfl(hi_m[r], src, 64);
                 const uint32_t aj = (uint32_t)__shfl((int)aj_m[r], src, 64);
                 scan_alpha_group<false>(a, eri, h, lo, hi, xa, xb, aj, d, lane, acc);
+            }
+            found = __ballot(sz > 0 && sz <= PT2_SMALL);  // small groups: 64 / PT2_GL at a time
+            while (found) {
+                int src = -1;
+#pragma unroll
+                for (int k = 0; k < 64 / PT2_GL; ++k) {
+                    if (found) {
+                        const int f = __builtin_ctzll(found);
+                        found &= found - 1;
+                        if (k == lane / PT2_GL) src = f;
+                    }
+                }
+                const int sidx = src < 0 ? 0 : src;
+                const int32_t lo = __shfl(lo_m[r], sidx, 64), hi = __shfl(hi_m[r], sidx, 64);
+                const uint32_t aj = (uint32_t)__shfl((int)aj_m[r], sidx, 64);
+                scan_small_group(a, eri, h, lo, src < 0 ? lo : hi, xa, xb, aj, lane % PT2_GL, acc);
             }
         }
         acc = wave_sum_d(acc);
