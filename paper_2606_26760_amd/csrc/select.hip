@@ -295,7 +295,7 @@ __device__ inline void scan_alpha_group(const Pt2Args &a, const double *eri, con
 // at a time, PT2_GL lanes each and in a single step, so the chain of
 // dependent loads per candidate runs over a few batches of groups instead of
 // every group one after another.
-constexpr int PT2_GL = 16;
+constexpr int PT2_GL = 32;
 constexpr int PT2_SMALL = PT2_GL * SCAN_U;
 
 // acc += c_j <x|H|x_j> over the rows j in [lo, hi) (at most PT2_SMALL of them)
