@@ -16,9 +16,13 @@
 //     rdm2[p,k,k,q], rdm2[k,q,p,k] with a minus sign)  (LDS, norb^3)
 //   * doubles:  up to four rdm2 entries each, atomically added into one of
 //     NCOPY global copies chosen by workgroup, to spread contention.
-// A final kernel assembles rdm1/rdm2 from the tables and sums the copies in
-// a fixed order.  The floating-point atomics make the result reproducible
-// to rounding, not bitwise.
+// The coupling set is symmetric and the vector real, so the coupling (j <- i)
+// contributes to the index-transposed entries exactly what (i <- j) does
+// (rdm2[p,q,r,s] -> rdm2[q,p,s,r], rdm1[p,q] -> rdm1[q,p], Sc/Sx[p][q][k] ->
+// [q][p][k]): only entries with j < i are visited, and the assembly adds the
+// transposes.  A final kernel assembles rdm1/rdm2 from the tables and sums
+// the copies in a fixed order.  The floating-point atomics make the result
+// reproducible to rounding, not bitwise.
 #include "common.hpp"
 
 namespace hinqs {
@@ -87,7 +91,9 @@ __global__ __launch_bounds__(256) void k_rdm(RdmArgs a) {
         }
         const int64_t beg = a.rowptr[row], end = a.rowptr[row + 1];
         for (int64_t e = beg + lane; e < end; e += 64) {
-            const double cj = a.c[a.col[e]];
+            const int32_t j = a.col[e];
+            if (j > row) continue;  // its mirror (row <- j) is the transpose
+            const double cj = a.c[j];
             const uint32_t d = a.desc[e];
             double w = ci * cj;
             if (w == 0.0) continue;
@@ -134,16 +140,17 @@ __global__ void k_rdm_assemble(int norb, const double *g2c, const double *tabc, 
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n4) return;
     const int s = (int)(t % n), r = (int)((t / n) % n), q = (int)((t / n2) % n), p = (int)(t / n3);
+    const int64_t tt = ((int64_t)(q * n + p) * n + s) * n + r;  // transpose (q, p, s, r)
     double v = 0.0;
-    for (int cpy = 0; cpy < NCOPY; ++cpy) v += g2c[(int64_t)cpy * n4 + t];
+    for (int cpy = 0; cpy < NCOPY; ++cpy) v += g2c[(int64_t)cpy * n4 + t] + g2c[(int64_t)cpy * n4 + tt];
     double sc1 = 0, sc2 = 0, sx1 = 0, sx2 = 0, ps = 0, pab = 0, pba = 0, pex = 0;
     for (int cpy = 0; cpy < NCOPY; ++cpy) {
         const double *tb = tabc + (int64_t)cpy * ntab;
         const double *Sc = tb, *Sx = tb + n3, *Ps = tb + 2 * n3 + n2, *Pab = Ps + n2;
-        if (r == s) sc1 += Sc[(p * n + q) * n + r];
-        if (p == q) sc2 += Sc[(r * n + s) * n + p];
-        if (q == r) sx1 += Sx[(p * n + s) * n + q];
-        if (p == s) sx2 += Sx[(r * n + q) * n + p];
+        if (r == s) sc1 += Sc[(p * n + q) * n + r] + Sc[(q * n + p) * n + r];
+        if (p == q) sc2 += Sc[(r * n + s) * n + p] + Sc[(s * n + r) * n + p];
+        if (q == r) sx1 += Sx[(p * n + s) * n + q] + Sx[(s * n + p) * n + q];
+        if (p == s) sx2 += Sx[(r * n + q) * n + p] + Sx[(q * n + r) * n + p];
         if (p == q && r == s) {
             if (p != r) ps += Ps[p * n + r];
             pab += Pab[p * n + r];
@@ -158,7 +165,7 @@ __global__ void k_rdm_assemble(int norb, const double *g2c, const double *tabc, 
         double g = 0.0;
         for (int cpy = 0; cpy < NCOPY; ++cpy) {
             const double *tb = tabc + (int64_t)cpy * ntab;
-            g += tb[2 * n3 + pp * n + qq];
+            g += tb[2 * n3 + pp * n + qq] + tb[2 * n3 + qq * n + pp];
             if (pp == qq) g += tb[2 * n3 + 3 * n2 + pp];
         }
         rdm1[t] = g;
