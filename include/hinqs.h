@@ -62,7 +62,8 @@ extern "C" {
 #define HINQS_FP32   1
 /* Davidson precision modes */
 #define HINQS_SOLVE_FP64   0   /* every sigma product in FP64 */
-#define HINQS_SOLVE_MIXED  1   /* FP32 sigma until the residual stalls, then FP64 refinement */
+#define HINQS_SOLVE_MIXED  1   /* FP32 sigma until the residual is below mixed_switch or stalls near
+                                  the FP32 rounding floor, then FP64 refinement */
 
 /* flags */
 #define HINQS_SORTED_ORDER 1   /* vectors are in the library's internal sorted order */

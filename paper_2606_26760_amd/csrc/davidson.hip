@@ -22,8 +22,10 @@
 // which keeps the convergence of the unrestarted method far better than a
 // restart on the Ritz vectors alone.
 // MIXED precision: FP32 sigma products while the residual is above a switch
-// threshold (or stalls), then a restart on the Ritz vectors, W recomputed
-// with FP64 sigma, and FP64 iterations to the requested tolerance.
+// threshold (or until it stalls for three iterations below 1e-4 |theta|, near
+// the FP32 rounding floor; or for eight anywhere), then a restart on the Ritz
+// vectors, W recomputed with FP64 sigma, and FP64 iterations to the requested
+// tolerance.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -908,6 +910,7 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
     double res0 = INFINITY;
     double best_res_fp32 = INFINITY;
     int stall = 0;
+    bool force_switch = false;
     bool converged = false;
     std::vector<double> y0;
     int nroots_eff = std::min(kroots, m);
@@ -962,7 +965,13 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
         if (fp32) {
             if (res0 < best_res_fp32 * 0.7) { best_res_fp32 = res0; stall = 0; }
             else ++stall;
-            if (res0 <= std::max(o.mixed_switch, o.tol) || stall >= 3 || m >= D) do_switch = true;
+            // three iterations without progress mean the FP32 floor only once the
+            // residual is small next to |theta|: far above it, Davidson residuals
+            // also rise for a few iterations after a restart
+            const bool near_floor = res0 < 1e-4 * std::max(1.0, std::fabs(theta[0]));
+            if (res0 <= std::max(o.mixed_switch, o.tol) || (stall >= 3 && near_floor) || stall >= 8 ||
+                force_switch || m >= D)
+                do_switch = true;
         }
         if (do_switch) {
             // basis := current Ritz vectors; images recomputed with FP64 products
@@ -1032,8 +1041,7 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
         int kept = S.orthonormalize(m, K, tscale.data());
         if (kept == 0) {
             if (!fp32) break;  // no new direction: report the current Ritz pair, not converged
-            best_res_fp32 = 0.0;  // FP32 images cannot resolve further directions: refine in FP64
-            stall = 3;
+            force_switch = true;  // FP32 images cannot resolve further directions: refine in FP64
             --iters;
             if (it_fp32 > 0) --it_fp32;
             continue;
