@@ -53,7 +53,9 @@ constexpr int GRAM_UNROLL = 4;
 // GRAM_UNROLL steps are issued before their MFMAs to keep loads in flight.
 template <int MT>
 __global__ __launch_bounds__(GRAM_BLOCK) void k_gram(int64_t nrows, Mat A, int ma, Mat B, int nb,
-                                                     int64_t rows_per_wave, double *__restrict__ partial) {
+                                                     int64_t rows_per_wave, double *__restrict__ partial,
+                                                     const int *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t gw = (int64_t)blockIdx.x * (GRAM_BLOCK / 64) + wave;
     const int64_t r0 = gw * rows_per_wave;
@@ -101,7 +103,9 @@ __global__ __launch_bounds__(GRAM_BLOCK) void k_gram(int64_t nrows, Mat A, int m
 
 // out[e] = sum_blk partial[blk][e]: one workgroup per output, fixed-shape tree.
 __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restrict__ partial, int nblk,
-                                                         int n, double *__restrict__ out) {
+                                                         int n, double *__restrict__ out,
+                                                         const int *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     __shared__ double red[256];
     const int e = blockIdx.x;
     double s = 0.0;
@@ -148,11 +152,30 @@ __global__ __launch_bounds__(256) void k_ritz(int64_t nrows, int m, Mat V, Mat W
     }
 }
 
+// gate[0] = 1 when the projection T -= V (V^T T) needs a second pass: some
+// column q (tn2[q] = ||T_q||^2 > 0 before the first pass) kept less than half
+// of its norm, ||T_q||^2 - ||(V^T T)_q||^2 < ||T_q||^2 / 4 (NaN counts as
+// less); else 0.  C is the first pass's m x nc product V^T T; one wave.
+__global__ void k_proj_gate(const double *__restrict__ C, int m, int nc, const double *__restrict__ tn2,
+                            int *__restrict__ gate) {
+    const int q = threadIdx.x;
+    bool need = false;
+    if (q < nc && tn2[q] > 0.0) {
+        double c2 = 0.0;
+        for (int a = 0; a < m; ++a) c2 += C[a * nc + q] * C[a * nc + q];
+        need = !(tn2[q] - c2 >= 0.25 * tn2[q]);
+    }
+    const bool any = __ballot(need) != 0ull;
+    if (threadIdx.x == 0) *gate = any ? 1 : 0;
+}
+
 // Out(i, c) = beta * Out(i, c) + alpha * sum_{j<m} A(i, j) B[j][c] (tsmm_row),
 // c < nc <= NC, m <= 96, A.kb == KB; B is m x nc row-major.  Out may alias A.
 template <int KB, int NC>
 __global__ __launch_bounds__(256) void k_tsmm(int64_t nrows, int m, Mat A, const double *__restrict__ B, int nc,
-                                              double alpha, double beta, Mat Out) {
+                                              double alpha, double beta, Mat Out,
+                                              const int *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     using L = RowLanes<KB>;
     constexpr int RPB = 256 / L::LPN;
     __shared__ double sB[96 * NC];
@@ -316,7 +339,7 @@ int gram_blocks_for(int64_t nrows) {
 // G (ma x nb) = A^T B over nrows rows: MFMA partials per block, then a
 // fixed-order reduction.  partial must hold nblk * ma * nb doubles.
 void launch_gram(hipStream_t s, int64_t nrows, int nblk, Mat A, int ma, Mat B, int nb, double *partial,
-                 double *out) {
+                 double *out, const int *gate = nullptr) {
     if (nb > 16 || ma > 96 || ma < 1 || nb < 1) throw Error(HINQS_E_UNSUPPORTED, "Gram block shape");
     int64_t waves = (int64_t)nblk * (GRAM_BLOCK / 64);
     int64_t rpw = (nrows + waves - 1) / waves;
@@ -324,16 +347,16 @@ void launch_gram(hipStream_t s, int64_t nrows, int nblk, Mat A, int ma, Mat B, i
     const int mt = (ma + 15) / 16;
     dim3 g(nblk), b(GRAM_BLOCK);
     switch (mt) {
-        case 1: hipLaunchKernelGGL(k_gram<1>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial); break;
-        case 2: hipLaunchKernelGGL(k_gram<2>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial); break;
-        case 3: hipLaunchKernelGGL(k_gram<3>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial); break;
-        case 4: hipLaunchKernelGGL(k_gram<4>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial); break;
-        case 5: hipLaunchKernelGGL(k_gram<5>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial); break;
-        default: hipLaunchKernelGGL(k_gram<6>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial); break;
+        case 1: hipLaunchKernelGGL(k_gram<1>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial, gate); break;
+        case 2: hipLaunchKernelGGL(k_gram<2>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial, gate); break;
+        case 3: hipLaunchKernelGGL(k_gram<3>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial, gate); break;
+        case 4: hipLaunchKernelGGL(k_gram<4>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial, gate); break;
+        case 5: hipLaunchKernelGGL(k_gram<5>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial, gate); break;
+        default: hipLaunchKernelGGL(k_gram<6>, g, b, 0, s, nrows, A, ma, B, nb, rpw, partial, gate); break;
     }
     HQ_LAUNCH_CHECK();
     const int n = ma * nb;
-    hipLaunchKernelGGL(k_reduce_partials, dim3(n), dim3(256), 0, s, partial, nblk, n, out);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(n), dim3(256), 0, s, partial, nblk, n, out, gate);
     HQ_LAUNCH_CHECK();
 }
 
@@ -591,9 +614,10 @@ struct Solver {
     // small.p regions: [0, 96*96) gram outputs / Y, [96*96, 2*96*96) coefficient uploads
     double *scratch_a() { return small.p; }
     double *scratch_b() { return small.p + 96 * 96; }
+    double *scratch_c() { return small.p + 2 * 96 * 96; }  // [0, 16) column norms, [64] gate flag
 
-    void gram(Mat A, int ma, Mat B, int nb, double *out) {
-        launch_gram(s, D, nblk_gram, A, ma, B, nb, partial.p, out);
+    void gram(Mat A, int ma, Mat B, int nb, double *out, const int *gate = nullptr) {
+        launch_gram(s, D, nblk_gram, A, ma, B, nb, partial.p, out, gate);
     }
 
     std::vector<double> gram_host(Mat A, int ma, Mat B, int nb) {
@@ -606,32 +630,33 @@ struct Solver {
 
     // Out[:, 0:nc] = beta Out + alpha A[:, 0:m] Bs (m x nc row-major, device);
     // A has K columns per block.
-    void tsmm(Mat A, int m, const double *Bs, int nc, double alpha, double beta, Mat Out) {
+    void tsmm(Mat A, int m, const double *Bs, int nc, double alpha, double beta, Mat Out,
+              const int *gate = nullptr) {
         if (m <= 0 || nc <= 0) return;
         if (nc > 32) throw Error(HINQS_E_UNSUPPORTED, "tsmm width");
         if (m > 96) throw Error(HINQS_E_UNSUPPORTED, "tsmm depth");
         if (A.kb != K) throw Error(HINQS_E_UNSUPPORTED, "tsmm column block");
         switch (K) {
-            case 1: tsmm_k<1>(A, m, Bs, nc, alpha, beta, Out); break;
-            case 2: tsmm_k<2>(A, m, Bs, nc, alpha, beta, Out); break;
-            case 4: tsmm_k<4>(A, m, Bs, nc, alpha, beta, Out); break;
-            case 8: tsmm_k<8>(A, m, Bs, nc, alpha, beta, Out); break;
-            default: tsmm_k<16>(A, m, Bs, nc, alpha, beta, Out); break;
+            case 1: tsmm_k<1>(A, m, Bs, nc, alpha, beta, Out, gate); break;
+            case 2: tsmm_k<2>(A, m, Bs, nc, alpha, beta, Out, gate); break;
+            case 4: tsmm_k<4>(A, m, Bs, nc, alpha, beta, Out, gate); break;
+            case 8: tsmm_k<8>(A, m, Bs, nc, alpha, beta, Out, gate); break;
+            default: tsmm_k<16>(A, m, Bs, nc, alpha, beta, Out, gate); break;
         }
     }
     template <int KB>
-    void tsmm_k(Mat A, int m, const double *Bs, int nc, double alpha, double beta, Mat Out) {
+    void tsmm_k(Mat A, int m, const double *Bs, int nc, double alpha, double beta, Mat Out, const int *gate) {
         constexpr int RPB = 256 / RowLanes<KB>::LPN;
         const unsigned grid = (unsigned)std::min<int64_t>((D + RPB - 1) / RPB, 2048);
         const int NC = nc <= 1 ? 1 : nc <= 2 ? 2 : nc <= 4 ? 4 : nc <= 8 ? 8 : nc <= 16 ? 16 : 32;
         dim3 g(grid), b(256);
         switch (NC) {
-            case 1: hipLaunchKernelGGL((k_tsmm<KB, 1>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
-            case 2: hipLaunchKernelGGL((k_tsmm<KB, 2>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
-            case 4: hipLaunchKernelGGL((k_tsmm<KB, 4>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
-            case 8: hipLaunchKernelGGL((k_tsmm<KB, 8>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
-            case 16: hipLaunchKernelGGL((k_tsmm<KB, 16>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
-            default: hipLaunchKernelGGL((k_tsmm<KB, 32>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out); break;
+            case 1: hipLaunchKernelGGL((k_tsmm<KB, 1>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate); break;
+            case 2: hipLaunchKernelGGL((k_tsmm<KB, 2>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate); break;
+            case 4: hipLaunchKernelGGL((k_tsmm<KB, 4>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate); break;
+            case 8: hipLaunchKernelGGL((k_tsmm<KB, 8>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate); break;
+            case 16: hipLaunchKernelGGL((k_tsmm<KB, 16>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate); break;
+            default: hipLaunchKernelGGL((k_tsmm<KB, 32>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate); break;
         }
         HQ_LAUNCH_CHECK();
     }
@@ -698,8 +723,11 @@ struct Solver {
     // from T^T T.  Scaling to unit columns is folded into the first transform,
     // so the drop thresholds are relative: a direction is dropped when less
     // than 1e-7 of it lies outside span(V) and the other new directions.
-    //   round 0: two projection passes (CGS2), then symmetric
-    //            orthonormalization of S T^T T S (eigenvalues > 1e-14 kept);
+    //   round 0: a projection pass, a second one only when the first left
+    //            less than half of some column's norm (decided on the device:
+    //            one classical pass then leaves T orthogonal to V to a few
+    //            ulps), then symmetric orthonormalization of S T^T T S
+    //            (eigenvalues > 1e-14 kept);
     //   round 1: only when round 0 kept an eigenvalue below 1e-2 (its inverse
     //            square root amplified what was left of span(V)): one more
     //            projection pass and orthonormalization (eigenvalues > 1e-4).
@@ -725,9 +753,19 @@ struct Solver {
         for (int round = 0; round < 2; ++round) {
             if (round == 1 && wmin >= 1e-2) break;
             if (m > 0) {
-                for (int pass = 0; pass < (round == 0 ? 2 : 1); ++pass) {
-                    gram(V, m, Tm, kept, C);
-                    tsmm(V, m, C, kept, -1.0, 1.0, Tm);
+                gram(V, m, Tm, kept, C);
+                tsmm(V, m, C, kept, -1.0, 1.0, Tm);
+                if (round == 0) {  // the second pass runs only when the device gate asks for it
+                    std::vector<double> tn2(K, 0.0);
+                    for (int q = 0; q < kept; ++q)
+                        if (sc[q] > 0.0) tn2[q] = 1.0 / (sc[q] * sc[q]);
+                    upload_small(tn2, scratch_c());
+                    int *gate = reinterpret_cast<int *>(scratch_c() + 64);
+                    hipLaunchKernelGGL(k_proj_gate, dim3(1), dim3(64), 0, s, (const double *)C, m, kept,
+                                       (const double *)scratch_c(), gate);
+                    HQ_LAUNCH_CHECK();
+                    gram(V, m, Tm, kept, C, gate);
+                    tsmm(V, m, C, kept, -1.0, 1.0, Tm, gate);
                 }
             }
             std::vector<double> g = gram_host(Tm, kept, Tm, kept);
@@ -944,7 +982,7 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
             default: launch_ritz<16>(S, m, Yd, thd, o.precond_floor, nroots_eff, grid); break;
         }
         hipLaunchKernelGGL(k_reduce_partials, dim3(2 * K), dim3(256), 0, s, S.partial.p, (int)grid, 2 * K,
-                           S.nrm.p);
+                           S.nrm.p, (const int *)nullptr);
         HQ_LAUNCH_CHECK();
         std::vector<double> rt(2 * K);
         HQ_CHECK(hipMemcpyAsync(rt.data(), S.nrm.p, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, s));
