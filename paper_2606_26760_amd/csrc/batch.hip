@@ -74,6 +74,7 @@ struct BDev {
     const int32_t *inst_chunk;  // chunks of instance b: inst_chunk[b] .. inst_chunk[b+1]
     int32_t *done;              // 0 running, 1 converged, 2 no new direction
     int32_t *skip1;             // done, or the second orthonormalization round is not needed
+    int32_t *skip2;             // done, or the first projection pass left every column at least half its norm
     int32_t *iters, *mfin, *valid;  // valid: [b][MS] basis columns in use
     double *G;                  // [b][MS][MS] V^T H V
     double *Y;                  // [b][MS][KB] Ritz coefficients of the current basis
@@ -488,7 +489,10 @@ template <int KK>
 __global__ __launch_bounds__(NT) void k_bpost_first(BDev st, int m, double tol, const double *__restrict__ rpart,
                                                     const double *__restrict__ gpart) {
     const int b = blockIdx.x;
-    if (st.done[b]) return;
+    if (st.done[b]) {
+        if (threadIdx.x == 0) st.skip2[b] = 1;
+        return;
+    }
     __shared__ double rn2[KK];
     __shared__ double g1[MS * KK];
     const int tid = threadIdx.x;
@@ -501,6 +505,7 @@ __global__ __launch_bounds__(NT) void k_bpost_first(BDev st, int m, double tol, 
         st.iters[b] += 1;
         st.resid[b] = r0;
         st.skip1[b] = r0 <= tol ? 1 : 0;
+        st.skip2[b] = 1;
         if (r0 <= tol) {
             st.done[b] = 1;
             st.energy[b] = st.theta[b * KB];
@@ -508,10 +513,21 @@ __global__ __launch_bounds__(NT) void k_bpost_first(BDev st, int m, double tol, 
         }
     }
     if (r0 <= tol) return;
-    if (tid < KK) {
-        const double rq = sqrt(fmax(0.0, rn2[tid]));
-        const double nq = g1[(m + tid) * KK + tid];
-        st.scl[b * KB + tid] = (rq > tol && nq > 0.0 && isfinite(nq)) ? 1.0 / sqrt(nq) : 0.0;
+    if (tid < 64) {  // wave 0: column scales, and whether the projection needs a second pass
+        bool need = false;
+        if (tid < KK) {
+            const double rq = sqrt(fmax(0.0, rn2[tid]));
+            const double nq = g1[(m + tid) * KK + tid];
+            const bool keep = rq > tol && nq > 0.0 && isfinite(nq);
+            st.scl[b * KB + tid] = keep ? 1.0 / sqrt(nq) : 0.0;
+            if (keep) {  // ||T_q||^2 - ||(V^T T)_q||^2 < ||T_q||^2 / 4 (NaN counts as less)
+                double c2 = 0.0;
+                for (int a = 0; a < m; ++a) c2 += g1[a * KK + tid] * g1[a * KK + tid];
+                need = !(nq - c2 >= 0.25 * nq);
+            }
+        }
+        const bool any = __ballot(need) != 0ull;
+        if (tid == 0) st.skip2[b] = any ? 0 : 1;
     }
     double *Cb = st.C + (int64_t)b * MS * KB;
     for (int e = tid; e < m * KK; e += NT) Cb[(e / KK) * KB + e % KK] = g1[e];
@@ -905,7 +921,7 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     rpart.ensure((size_t)nch * RSTRIDE);
     const size_t n_state = (size_t)nb * (MS * MS + MS * KB + KB + MS * 2 * KB + MS * KB + KB * KB + KB + 2);
     state.ensure(n_state);
-    istate.ensure((size_t)nb * (4 + MS));
+    istate.ensure((size_t)nb * (5 + MS));
     d_ndone.ensure(1);
     ranges.ensure(9);
     d_chunks.ensure(nch);
@@ -919,7 +935,7 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     HQ_CHECK(hipMemsetAsync(Vb.p, 0, sizeof(double) * bsz * nblocks, s));
     HQ_CHECK(hipMemsetAsync(Wb.p, 0, sizeof(double) * bsz * nblocks, s));
     HQ_CHECK(hipMemsetAsync(state.p, 0, sizeof(double) * n_state, s));
-    HQ_CHECK(hipMemsetAsync(istate.p, 0, sizeof(int32_t) * nb * (4 + MS), s));
+    HQ_CHECK(hipMemsetAsync(istate.p, 0, sizeof(int32_t) * nb * (5 + MS), s));
     BDev st{};
     st.nb = nb;
     st.inst_chunk = d_inst_chunk.p;
@@ -928,6 +944,7 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     st.mfin = st.iters + nb;
     st.skip1 = st.mfin + nb;
     st.valid = st.skip1 + nb;  // nb * MS
+    st.skip2 = st.valid + (size_t)nb * MS;
     {
         double *p = state.p;
         st.G = p;      p += (size_t)nb * MS * MS;
@@ -987,7 +1004,7 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     hipLaunchKernelGGL(k_binit, gin, b256, 0, s, KK, B.inst_row.p, g.diag.p, Vb.p);
     HQ_LAUNCH_CHECK();
     sigma(V.p, W.p);
-    const int32_t *dn = st.done, *g1 = st.skip1;
+    const int32_t *dn = st.done, *g1 = st.skip1, *g2 = st.skip2;
     gram(V, KK, W, gpart_u.p, dn);
 
     // ---- one iteration at subspace size m (m - KK columns old, KK new);
@@ -1006,16 +1023,18 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
         hipLaunchKernelGGL(k_britz<KK>, gch, b256, 0, s, dch, st, mp, V, W, (const double *)g.diag.p, floor_, T.p,
                            rpart.p);
         HQ_LAUNCH_CHECK();
-        // CGS2 against the basis, with T^T T from the first product
+        // projection against the basis, with T^T T from the first product; a
+        // second pass only for instances whose first pass left some column
+        // less than half its norm
         gram(V, mp + KK, T, gpart.p, dn);
         hipLaunchKernelGGL(k_bpost_first<KK>, gin, dim3(NT), 0, s, st, mp, tol, (const double *)rpart.p,
                            (const double *)gpart.p);
         HQ_LAUNCH_CHECK();
         tsmm(V, mp, st.C, MS * KB, KB, NK{}, -1.0, 1.0, T, dn);
-        gram(V, mp, T, gpart.p, dn);
-        hipLaunchKernelGGL(k_bpost_proj<KK>, gin, dim3(NT), 0, s, st, dn, mp, (const double *)gpart.p);
+        gram(V, mp, T, gpart.p, g2);
+        hipLaunchKernelGGL(k_bpost_proj<KK>, gin, dim3(NT), 0, s, st, g2, mp, (const double *)gpart.p);
         HQ_LAUNCH_CHECK();
-        tsmm(V, mp, st.C, MS * KB, KB, NK{}, -1.0, 1.0, T, dn);
+        tsmm(V, mp, st.C, MS * KB, KB, NK{}, -1.0, 1.0, T, g2);
         // symmetric orthonormalization within the block (unit columns first)
         const Mat Tm{T.p, KK, (int64_t)bsz};
         gram(Tm, KK, Tm, gpart.p, dn);
