@@ -105,6 +105,8 @@ typedef struct hinqs_stats {
     double ms_total;           /* wall time of the call */
     double ms_sigma;           /* time inside sigma kernels (HIP events) */
     int64_t nnz;               /* stored off-diagonal couplings */
+    int    second_passes;      /* iterations whose projection against the basis needed a second
+                                  pass (a new direction kept < 1/2 of its norm in the first) */
 } hinqs_stats;
 
 typedef struct hinqs_info {

@@ -69,7 +69,7 @@ class Stats(ctypes.Structure):
                 ("sigma_blocks", ctypes.c_int), ("sigma_columns", ctypes.c_int),
                 ("restarts", ctypes.c_int),
                 ("residual", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("ms_sigma", ctypes.c_double), ("nnz", ctypes.c_int64)]
+                ("ms_sigma", ctypes.c_double), ("nnz", ctypes.c_int64), ("second_passes", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -157,7 +157,7 @@ __global__ __launch_bounds__(256) void k_ritz(int64_t nrows, int m, Mat V, Mat W
 // of its norm, ||T_q||^2 - ||(V^T T)_q||^2 < ||T_q||^2 / 4 (NaN counts as
 // less); else 0.  C is the first pass's m x nc product V^T T; one wave.
 __global__ void k_proj_gate(const double *__restrict__ C, int m, int nc, const double *__restrict__ tn2,
-                            int *__restrict__ gate) {
+                            int *__restrict__ gate, int *__restrict__ count) {
     const int q = threadIdx.x;
     bool need = false;
     if (q < nc && tn2[q] > 0.0) {
@@ -166,7 +166,10 @@ __global__ void k_proj_gate(const double *__restrict__ C, int m, int nc, const d
         need = !(tn2[q] - c2 >= 0.25 * tn2[q]);
     }
     const bool any = __ballot(need) != 0ull;
-    if (threadIdx.x == 0) *gate = any ? 1 : 0;
+    if (threadIdx.x == 0) {
+        *gate = any ? 1 : 0;
+        *count += any ? 1 : 0;  // second passes run in this solve
+    }
 }
 
 // Out(i, c) = beta * Out(i, c) + alpha * sum_{j<m} A(i, j) B[j][c] (tsmm_row),
@@ -615,6 +618,7 @@ struct Solver {
     double *scratch_a() { return small.p; }
     double *scratch_b() { return small.p + 96 * 96; }
     double *scratch_c() { return small.p + 2 * 96 * 96; }  // [0, 16) column norms, [64] gate flag
+    int *pass2_count() { return reinterpret_cast<int *>(scratch_c() + 65); }
 
     void gram(Mat A, int ma, Mat B, int nb, double *out, const int *gate = nullptr) {
         launch_gram(s, D, nblk_gram, A, ma, B, nb, partial.p, out, gate);
@@ -762,7 +766,7 @@ struct Solver {
                     upload_small(tn2, scratch_c());
                     int *gate = reinterpret_cast<int *>(scratch_c() + 64);
                     hipLaunchKernelGGL(k_proj_gate, dim3(1), dim3(64), 0, s, (const double *)C, m, kept,
-                                       (const double *)scratch_c(), gate);
+                                       (const double *)scratch_c(), gate, pass2_count());
                     HQ_LAUNCH_CHECK();
                     gram(V, m, Tm, kept, C, gate);
                     tsmm(V, m, C, kept, -1.0, 1.0, Tm, gate);
@@ -863,6 +867,7 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
         if (o.precision == HINQS_SOLVE_MIXED) autotune_sigma(c, K, HINQS_FP32);
     }
     Solver S(c, K, mmax);
+    HQ_CHECK(hipMemsetAsync(S.pass2_count(), 0, sizeof(int), S.s));
     hipStream_t s = c.stream;
     bool fp32 = (o.precision == HINQS_SOLVE_MIXED);
     int it_fp32 = 0, restarts = 0, iters = 0;
@@ -1104,6 +1109,10 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
         S.collect_sigma_times();
         st->ms_sigma = S.ms_sigma;
         st->nnz = c.nnz;
+        int np2 = 0;
+        HQ_CHECK(hipMemcpyAsync(&np2, S.pass2_count(), sizeof(int), hipMemcpyDeviceToHost, S.s));
+        HQ_CHECK(hipStreamSynchronize(S.s));
+        st->second_passes = np2;
         st->ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return converged ? HINQS_OK : HINQS_E_NOT_CONVERGED;

@@ -205,6 +205,27 @@ def test_eigenpair_small_sets_and_tiny_spaces():
                 assert abs(np.dot(c.cpu().numpy(), c_ref)) >= 1 - 1e-10
 
 
+def test_second_projection_pass_both_ways():
+    """The second pass against the basis runs only when a new direction kept
+    less than half its norm in the first; both outcomes reach the oracle."""
+    runs = 0
+    for nd, blocks in ((100, (4, 8, 16)), (300, (8, 16))):
+        ints, a, b, cfg = W.config_inputs(1, ndet=nd)
+        s = solver_for(ints, a, b, cfg.na, cfg.nb)
+        e_ref, _ = oracle_for(ints, a, b, cfg.na, cfg.nb).lowest_eigenpair()
+        for k in blocks:
+            e, _, st = s.lowest_eigenpair(tol=1e-9, block=k)
+            log(f"  ndet {nd} block {k}: {st['iterations']} iterations, {st['second_passes']} second passes")
+            assert abs(e - e_ref) <= 1e-10
+            runs += st["second_passes"]
+    assert runs >= 1  # small spaces: corrections fall largely inside the basis
+    ints, a, b, cfg = W.config_inputs(1)
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    e, _, st = s.lowest_eigenpair(tol=1e-8, block=8)
+    log(f"  cas10 20000: {st['iterations']} iterations, {st['second_passes']} second passes")
+    assert st["second_passes"] < st["iterations"]
+
+
 def test_warm_start_converges_immediately():
     ints, a, b, cfg = W.config_inputs(1, ndet=5000)
     s = solver_for(ints, a, b, cfg.na, cfg.nb)
