@@ -29,7 +29,7 @@ namespace {
 // of the wave happens to hit.  Entries keep their order.
 struct ConnArgs {
     int64_t ndet;
-    const uint32_t *sa, *sb;
+    const uint32_t *sb;
     const int32_t *aidx, *bidx, *ga, *gb, *bperm;
     const uint32_t *bm_alpha;
     const int32_t *alink_cnt, *alink;
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_connect(ConnArgs a, const int32_t *n1, 
                                                  const int64_t *rowptr, int32_t *col, uint32_t *desc) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.ndet) return;
-    const uint32_t ai = a.sa[i], bi = a.sb[i];
+    const uint32_t bi = a.sb[i];
     const int32_t ag = a.aidx[i];
     int64_t out = FILL ? rowptr[i] + n1[i] : 0;
     int64_t n = 0;
@@ -208,7 +208,7 @@ void build_connectivity(Ctx &c, bool xcd_rows) {
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = c.stream;
     const int64_t n = c.ndet;
-    ConnArgs a{n,          c.sa.p,        c.sb.p,    c.aidx.p,      c.bidx.p,
+    ConnArgs a{n,          c.sb.p,        c.aidx.p,  c.bidx.p,
                c.ga.p,     c.gb.p,        c.bperm.p, c.bm_alpha.p,  c.alink_ptr.p,
                c.alink.p,  c.alink_info.p, c.alink_max};
     auto &counts = c.bs.counts;

@@ -385,7 +385,7 @@ __global__ __launch_bounds__(PT_NT) __attribute__((amdgpu_waves_per_eu(8, 8))) v
         const uint64_t a64 = a.ca[t], b64 = a.cb[t];
         const int32_t g = ga_of[u], gbx = gb_of[u];
         ++u;
-        if ((a64 >> norb) != 0 || (b64 >> norb) != 0 || __popcll(a64) != a.na || __popcll(b64) != a.nb) {
+        if ((a64 >> norb) != 0 || (b64 >> norb) != 0 || (int)__popcll(a64) != a.na || (int)__popcll(b64) != a.nb) {
             if (lane == 0) {
                 atomicOr(a.bad, 1u);
                 const double nan = __longlong_as_double(0x7ff8000000000000ll);
