@@ -14,8 +14,11 @@
 //     the two determinants share (Coulomb-like terms rdm2[p,q,k,k] and
 //     rdm2[k,k,p,q]); Sx[p][q][k] += w for the same-spin ones (exchange-like
 //     rdm2[p,k,k,q], rdm2[k,q,p,k] with a minus sign)  (LDS, norb^3)
-//   * doubles:  up to four rdm2 entries each, atomically added into one of
-//     NCOPY global copies chosen by workgroup, to spread contention.
+//   * doubles:  rdm2 entries atomically added into one of NCOPY global copies
+//     chosen by workgroup, to spread contention.  A double adds the same
+//     weight to rdm2[p,q,r,s] and to its pair swap rdm2[r,s,p,q], so only the
+//     first of each such pair is accumulated (one entry for an alpha-beta
+//     double, two for a same-spin one) and the assembly adds the swap.
 // The coupling set is symmetric and the vector real, so the coupling (j <- i)
 // contributes to the index-transposed entries exactly what (i <- j) does
 // (rdm2[p,q,r,s] -> rdm2[q,p,s,r], rdm1[p,q] -> rdm1[q,p], Sc/Sx[p][q][k] ->
@@ -115,13 +118,10 @@ __global__ __launch_bounds__(256) void k_rdm(RdmArgs a) {
                     atomicAdd(&Sc[(p * n + q) * n + k], w);
                 }
             } else if (type == HINQS_EXC_2AB) {
-                G2(p1, h1, p2, h2, w);
-                G2(p2, h2, p1, h1, w);
+                G2(p1, h1, p2, h2, w);  // + pair swap (p2, h2, p1, h1) at assembly
             } else {
-                G2(p1, h1, p2, h2, w);
-                G2(p2, h2, p1, h1, w);
-                G2(p1, h2, p2, h1, -w);
-                G2(p2, h1, p1, h2, -w);
+                G2(p1, h1, p2, h2, w);  // + (p2, h2, p1, h1)
+                G2(p1, h2, p2, h1, -w);  // + (p2, h1, p1, h2)
             }
         }
     }
@@ -141,8 +141,13 @@ __global__ void k_rdm_assemble(int norb, const double *g2c, const double *tabc, 
     if (t >= n4) return;
     const int s = (int)(t % n), r = (int)((t / n) % n), q = (int)((t / n2) % n), p = (int)(t / n3);
     const int64_t tt = ((int64_t)(q * n + p) * n + s) * n + r;  // transpose (q, p, s, r)
+    const int64_t tp = ((int64_t)(r * n + s) * n + p) * n + q;  // pair swap (r, s, p, q)
+    const int64_t tq = ((int64_t)(s * n + r) * n + q) * n + p;  // both (s, r, q, p)
     double v = 0.0;
-    for (int cpy = 0; cpy < NCOPY; ++cpy) v += g2c[(int64_t)cpy * n4 + t] + g2c[(int64_t)cpy * n4 + tt];
+    for (int cpy = 0; cpy < NCOPY; ++cpy) {
+        const double *g = g2c + (int64_t)cpy * n4;
+        v += (g[t] + g[tt]) + (g[tp] + g[tq]);
+    }
     double sc1 = 0, sc2 = 0, sx1 = 0, sx2 = 0, ps = 0, pab = 0, pba = 0, pex = 0;
     for (int cpy = 0; cpy < NCOPY; ++cpy) {
         const double *tb = tabc + (int64_t)cpy * ntab;
