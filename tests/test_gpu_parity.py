@@ -254,7 +254,9 @@ def test_mixed_precision_matches_fp64():
     em, cm, stm = s.lowest_eigenpair(tol=1e-8, mixed=True)
     log(f"  fp64 E={e64!r} {st64}\n  mixed E={em!r} {stm}")
     assert abs(em - e64) <= 1e-8
-    assert stm["iterations_fp32"] >= 1
+    # the FP32 phase runs until the residual nears the FP32 floor, not until the
+    # first rise after a restart: most iterations use FP32 products
+    assert 2 * stm["iterations_fp32"] >= stm["iterations"]
     assert abs(torch.dot(c64, cm).item()) >= 1 - 1e-8
 
 
