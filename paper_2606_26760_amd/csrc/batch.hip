@@ -73,7 +73,6 @@ struct BDev {
     int nb;
     const int32_t *inst_chunk;  // chunks of instance b: inst_chunk[b] .. inst_chunk[b+1]
     int32_t *done;              // 0 running, 1 converged, 2 no new direction
-    int32_t *skip1;             // done, or the second orthonormalization round is not needed
     int32_t *skip2;             // done, or the first projection pass left every column at least half its norm
     int32_t *iters, *mfin, *valid;  // valid: [b][MS] basis columns in use
     double *G;                  // [b][MS][MS] V^T H V
@@ -504,7 +503,6 @@ __global__ __launch_bounds__(NT) void k_bpost_first(BDev st, int m, double tol, 
     if (tid == 0) {
         st.iters[b] += 1;
         st.resid[b] = r0;
-        st.skip1[b] = r0 <= tol ? 1 : 0;
         st.skip2[b] = 1;
         if (r0 <= tol) {
             st.done[b] = 1;
@@ -545,16 +543,15 @@ __global__ __launch_bounds__(NT) void k_bpost_proj(BDev st, const int32_t *__res
 }
 
 // Symmetric orthonormalization of the new block T from g = T^T T: with
-// S = diag(scl) in the first round (unit columns, dropped roots zero) and
-// S = I in the second, S g S = Z diag(w) Z^T and T <- T S Z_k w_k^(-1/2) over
-// the eigenvalues w_k > thresh, largest first.  No kept direction: the
-// instance stops (its current Ritz pair is the result).  The new basis
-// columns are marked valid; the first round skips the second when every
-// kept eigenvalue is >= 1e-2 (the transform amplified what was left of
-// span(V) at most tenfold).
+// S = diag(scl) (unit columns, dropped roots zero), S g S = Z diag(w) Z^T and
+// T <- T S Z_k w_k^(-1/2) over the eigenvalues w_k > ORTH_DROP, largest
+// first (the transform amplifies what is left of span(V) at most tenfold, so
+// one round suffices).  No kept direction: the instance stops (its current
+// Ritz pair is the result).  The new basis columns are marked valid.
 template <int KK>
-__global__ __launch_bounds__(NT) void k_bpost_orth(BDev st, const int32_t *__restrict__ gate, int m, int round,
-                                                   double thresh, const double *__restrict__ gpart) {
+__global__ __launch_bounds__(NT) void k_bpost_orth(BDev st, const int32_t *__restrict__ gate, int m,
+                                                   const double *__restrict__ gpart) {
+    constexpr double thresh = ORTH_DROP;
     const int b = blockIdx.x;
     if (gate[b]) return;
     constexpr int LD = KK + 1;
@@ -563,7 +560,7 @@ __global__ __launch_bounds__(NT) void k_bpost_orth(BDev st, const int32_t *__res
     __shared__ int pp[KK], pq[KK], nk_s;
     const int tid = threadIdx.x;
     const int c0 = st.inst_chunk[b], c1 = st.inst_chunk[b + 1];
-    if (tid < KK) sc[tid] = round == 0 ? st.scl[b * KB + tid] : 1.0;
+    if (tid < KK) sc[tid] = st.scl[b * KB + tid];
     for (int e = tid; e < KK * KK; e += NT) ZT[(e / KK) * LD + e % KK] = chunk_sum(gpart, PSTRIDE, c0, c1, e);
     __syncthreads();
     for (int e = tid; e < KK * KK; e += NT) {
@@ -603,14 +600,6 @@ __global__ __launch_bounds__(NT) void k_bpost_orth(BDev st, const int32_t *__res
             st.done[b] = 2;
             st.energy[b] = st.theta[b * KB];
             st.mfin[b] = m;
-        }
-        if (round == 0) {
-            double wmin = INFINITY;
-            for (int j = 0; j < KK; ++j) {
-                const double w = A[j * LD + j];
-                if (isfinite(w) && w > thresh) wmin = fmin(wmin, w);
-            }
-            st.skip1[b] = (nk == 0 || wmin >= 1e-2) ? 1 : 0;
         }
     }
     if (tid < KK) st.valid[b * MS + m + tid] = tid < nk ? 1 : 0;
@@ -921,7 +910,7 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     rpart.ensure((size_t)nch * RSTRIDE);
     const size_t n_state = (size_t)nb * (MS * MS + MS * KB + KB + MS * 2 * KB + MS * KB + KB * KB + KB + 2);
     state.ensure(n_state);
-    istate.ensure((size_t)nb * (5 + MS));
+    istate.ensure((size_t)nb * (4 + MS));
     d_ndone.ensure(1);
     ranges.ensure(9);
     d_chunks.ensure(nch);
@@ -935,15 +924,14 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     HQ_CHECK(hipMemsetAsync(Vb.p, 0, sizeof(double) * bsz * nblocks, s));
     HQ_CHECK(hipMemsetAsync(Wb.p, 0, sizeof(double) * bsz * nblocks, s));
     HQ_CHECK(hipMemsetAsync(state.p, 0, sizeof(double) * n_state, s));
-    HQ_CHECK(hipMemsetAsync(istate.p, 0, sizeof(int32_t) * nb * (5 + MS), s));
+    HQ_CHECK(hipMemsetAsync(istate.p, 0, sizeof(int32_t) * nb * (4 + MS), s));
     BDev st{};
     st.nb = nb;
     st.inst_chunk = d_inst_chunk.p;
     st.done = istate.p;
     st.iters = st.done + nb;
     st.mfin = st.iters + nb;
-    st.skip1 = st.mfin + nb;
-    st.valid = st.skip1 + nb;  // nb * MS
+    st.valid = st.mfin + nb;  // nb * MS
     st.skip2 = st.valid + (size_t)nb * MS;
     {
         double *p = state.p;
@@ -1004,7 +992,7 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     hipLaunchKernelGGL(k_binit, gin, b256, 0, s, KK, B.inst_row.p, g.diag.p, Vb.p);
     HQ_LAUNCH_CHECK();
     sigma(V.p, W.p);
-    const int32_t *dn = st.done, *g1 = st.skip1, *g2 = st.skip2;
+    const int32_t *dn = st.done, *g2 = st.skip2;
     gram(V, KK, W, gpart_u.p, dn);
 
     // ---- one iteration at subspace size m (m - KK columns old, KK new);
@@ -1038,19 +1026,9 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
         // symmetric orthonormalization within the block (unit columns first)
         const Mat Tm{T.p, KK, (int64_t)bsz};
         gram(Tm, KK, Tm, gpart.p, dn);
-        hipLaunchKernelGGL(k_bpost_orth<KK>, gin, dim3(NT), 0, s, st, dn, mp, 0, 1e-14, (const double *)gpart.p);
+        hipLaunchKernelGGL(k_bpost_orth<KK>, gin, dim3(NT), 0, s, st, dn, mp, (const double *)gpart.p);
         HQ_LAUNCH_CHECK();
         tsmm(Tm, KK, st.Z, KB * KB, KB, NK{}, 1.0, 0.0, Tm, dn);
-        // when the transform amplified a small remainder: one more projection
-        // and orthonormalization (instances that do not need it are skipped)
-        gram(V, mp, T, gpart.p, g1);
-        hipLaunchKernelGGL(k_bpost_proj<KK>, gin, dim3(NT), 0, s, st, g1, mp, (const double *)gpart.p);
-        HQ_LAUNCH_CHECK();
-        tsmm(V, mp, st.C, MS * KB, KB, NK{}, -1.0, 1.0, T, g1);
-        gram(Tm, KK, Tm, gpart.p, g1);
-        hipLaunchKernelGGL(k_bpost_orth<KK>, gin, dim3(NT), 0, s, st, g1, mp, 1, 1e-4, (const double *)gpart.p);
-        HQ_LAUNCH_CHECK();
-        tsmm(Tm, KK, st.Z, KB * KB, KB, NK{}, 1.0, 0.0, Tm, g1);
         // images and the new columns of G
         const Mat Wn = W.cols(mp);
         sigma(T.p, Wn.p);

@@ -96,6 +96,12 @@ __host__ __device__ inline int lowbit(uint32_t x) {  // index of lowest set bit,
 // Candidates tested per step of a group scan before the hits are emitted.
 constexpr int SCAN_W = 8;
 
+// Davidson: a new direction is kept when the eigenvalue of its unit-scaled
+// block Gram exceeds this (more than a tenth of its norm lies outside the
+// span of the basis and of the other new directions), so the orthonormalizing
+// transform amplifies rounding at most tenfold and needs no second round.
+constexpr double ORTH_DROP = 1e-2;
+
 __host__ __device__ inline int highbit(uint32_t x) {  // index of highest set bit, x != 0
 #ifdef __HIP_DEVICE_COMPILE__
     return 31 - __clz(x);

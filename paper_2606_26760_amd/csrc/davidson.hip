@@ -10,10 +10,12 @@
 // the caches, and its output Wn is appended to W afterwards.
 //
 // Per iteration:
-//   Rayleigh-Ritz on G = V^T W         host cyclic Jacobi (m <= 96)
+//   Rayleigh-Ritz on G = V^T W         host Householder + implicit QL (cyclic
+//                                      Jacobi if QL does not converge), m <= 96
 //   T = (W y - theta V y) / (theta - H_ii)   fused Ritz/residual/preconditioner
-//   CGS2 of T against V, then symmetric orthonormalization of T (eigen-
-//   decomposition of T^T T; nearly dependent directions dropped)
+//   classical Gram-Schmidt of T against V (a second pass only when the first
+//   removed most of a column), then symmetric orthonormalization of T
+//   (eigendecomposition of T^T T; nearly dependent directions dropped)
 //   Wn = H T                           sigma kernel
 //   G[:, new] = V^T Wn                 FP64 MFMA (v_mfma_f64_16x16x4f64) partials
 //                                      reduced in a fixed order (deterministic)
@@ -724,17 +726,14 @@ struct Solver {
     // the number of kept directions, left in T[:, 0:kept] (other columns
     // zeroed).  scale[q] (host, K entries) is 1/||T[:, q]|| for the columns to
     // keep and 0 for those to discard; nullptr = the first n columns, scales
-    // from T^T T.  Scaling to unit columns is folded into the first transform,
-    // so the drop thresholds are relative: a direction is dropped when less
-    // than 1e-7 of it lies outside span(V) and the other new directions.
-    //   round 0: a projection pass, a second one only when the first left
-    //            less than half of some column's norm (decided on the device:
-    //            one classical pass then leaves T orthogonal to V to a few
-    //            ulps), then symmetric orthonormalization of S T^T T S
-    //            (eigenvalues > 1e-14 kept);
-    //   round 1: only when round 0 kept an eigenvalue below 1e-2 (its inverse
-    //            square root amplified what was left of span(V)): one more
-    //            projection pass and orthonormalization (eigenvalues > 1e-4).
+    // from T^T T.  One projection pass against V, a second only when the first
+    // left less than half of some column's norm (decided on the device), so T
+    // is orthogonal to V to a few ulps; then symmetric orthonormalization of
+    // S T^T T S (S = diag(scale), unit columns): eigen-directions with
+    // eigenvalue <= ORTH_DROP, i.e. with less than a tenth of their norm
+    // outside span(V) and the other new directions, are dropped.  The
+    // transform T S Z w^(-1/2) therefore amplifies what is left of span(V)
+    // and the rounding of T^T T at most tenfold, and T needs no second round.
     int orthonormalize(int m, int n, const double *scale) {
         double *C = scratch_a();   // m x K
         double *Zd = scratch_b();  // K x K
@@ -748,58 +747,47 @@ struct Solver {
                 if (std::isfinite(d) && d > 0.0) sc[q] = 1.0 / std::sqrt(d);
             }
         }
-        int cols = 0;  // columns that may hold a direction
+        int kept = 0;  // columns that may hold a direction
         for (int q = 0; q < K; ++q)
-            if (sc[q] > 0.0) cols = q + 1;
-        if (cols == 0) return 0;
-        int kept = cols;
-        double wmin = 0.0;
-        for (int round = 0; round < 2; ++round) {
-            if (round == 1 && wmin >= 1e-2) break;
-            if (m > 0) {
-                gram(V, m, Tm, kept, C);
-                tsmm(V, m, C, kept, -1.0, 1.0, Tm);
-                if (round == 0) {  // the second pass runs only when the device gate asks for it
-                    std::vector<double> tn2(K, 0.0);
-                    for (int q = 0; q < kept; ++q)
-                        if (sc[q] > 0.0) tn2[q] = 1.0 / (sc[q] * sc[q]);
-                    upload_small(tn2, scratch_c());
-                    int *gate = reinterpret_cast<int *>(scratch_c() + 64);
-                    hipLaunchKernelGGL(k_proj_gate, dim3(1), dim3(64), 0, s, (const double *)C, m, kept,
-                                       (const double *)scratch_c(), gate, pass2_count());
-                    HQ_LAUNCH_CHECK();
-                    gram(V, m, Tm, kept, C, gate);
-                    tsmm(V, m, C, kept, -1.0, 1.0, Tm, gate);
-                }
-            }
-            std::vector<double> g = gram_host(Tm, kept, Tm, kept);
-            for (int a = 0; a < kept; ++a)
-                for (int b = a; b < kept; ++b) {
-                    const double sa = round == 0 ? sc[a] : 1.0, sb = round == 0 ? sc[b] : 1.0;
-                    const double v = sa * sb * 0.5 * (g[(size_t)a * kept + b] + g[(size_t)b * kept + a]);
-                    g[(size_t)a * kept + b] = g[(size_t)b * kept + a] = v;
-                }
-            std::vector<double> w, Z;
-            small_sym_eig(kept, g, w, Z);
-            const double thresh = round == 0 ? 1e-14 : 1e-4;
-            std::vector<int> keep;
-            for (int j = kept - 1; j >= 0; --j)  // largest first
-                if (std::isfinite(w[j]) && w[j] > thresh) keep.push_back(j);
-            const int nk = (int)keep.size();
-            if (nk == 0) return 0;
-            wmin = w[keep.back()];
-            // K x K transform: rows >= kept and columns >= nk are zero, so the
-            // unused columns of T are cleared as well
-            std::vector<double> Zk((size_t)K * K, 0.0);
-            for (int a = 0; a < kept; ++a)
-                for (int q = 0; q < nk; ++q)
-                    Zk[(size_t)a * K + q] =
-                        (round == 0 ? sc[a] : 1.0) * Z[(size_t)a * kept + keep[q]] / std::sqrt(w[keep[q]]);
-            upload_small(Zk, Zd);
-            tsmm(Tm, K, Zd, K, 1.0, 0.0, Tm);
-            kept = nk;
+            if (sc[q] > 0.0) kept = q + 1;
+        if (kept == 0) return 0;
+        if (m > 0) {
+            gram(V, m, Tm, kept, C);
+            tsmm(V, m, C, kept, -1.0, 1.0, Tm);
+            // the second pass runs only when the device gate asks for it
+            std::vector<double> tn2(K, 0.0);
+            for (int q = 0; q < kept; ++q)
+                if (sc[q] > 0.0) tn2[q] = 1.0 / (sc[q] * sc[q]);
+            upload_small(tn2, scratch_c());
+            int *gate = reinterpret_cast<int *>(scratch_c() + 64);
+            hipLaunchKernelGGL(k_proj_gate, dim3(1), dim3(64), 0, s, (const double *)C, m, kept,
+                               (const double *)scratch_c(), gate, pass2_count());
+            HQ_LAUNCH_CHECK();
+            gram(V, m, Tm, kept, C, gate);
+            tsmm(V, m, C, kept, -1.0, 1.0, Tm, gate);
         }
-        return kept;
+        std::vector<double> g = gram_host(Tm, kept, Tm, kept);
+        for (int a = 0; a < kept; ++a)
+            for (int b = a; b < kept; ++b) {
+                const double v = sc[a] * sc[b] * 0.5 * (g[(size_t)a * kept + b] + g[(size_t)b * kept + a]);
+                g[(size_t)a * kept + b] = g[(size_t)b * kept + a] = v;
+            }
+        std::vector<double> w, Z;
+        small_sym_eig(kept, g, w, Z);
+        std::vector<int> keep;
+        for (int j = kept - 1; j >= 0; --j)  // largest first
+            if (std::isfinite(w[j]) && w[j] > ORTH_DROP) keep.push_back(j);
+        const int nk = (int)keep.size();
+        if (nk == 0) return 0;
+        // K x K transform: rows >= kept and columns >= nk are zero, so the
+        // unused columns of T are cleared as well
+        std::vector<double> Zk((size_t)K * K, 0.0);
+        for (int a = 0; a < kept; ++a)
+            for (int q = 0; q < nk; ++q)
+                Zk[(size_t)a * K + q] = sc[a] * Z[(size_t)a * kept + keep[q]] / std::sqrt(w[keep[q]]);
+        upload_small(Zk, Zd);
+        tsmm(Tm, K, Zd, K, 1.0, 0.0, Tm);
+        return nk;
     }
 
     void lowest_diag_indices(int n, int32_t *dev_idx) {
