@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) void k_cross(CrossArgs a, int64_t *cnt, int64_
                 for (; m; m &= m - 1) {
                     const int32_t u = u0 + lowbit(m);
                     col[out] = a.amap[a.bperm_a[u]];
-                    desc[out] = pair_desc(ai, bi, a.bm_alpha_a[u], bi);
+                    desc[out] = same_spin_desc(ai, a.bm_alpha_a[u], HINQS_EXC_1A, HINQS_EXC_2AA);
                     ++out;
                 }
             } else {
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void k_cross(CrossArgs a, int64_t *cnt, int64_
                 for (; m; m &= m - 1) {
                     const int32_t j = j0 + lowbit(m);
                     col[out] = a.amap[j];
-                    desc[out] = pair_desc(ai, bi, ai, a.sb_a[j]);
+                    desc[out] = same_spin_desc(bi, a.sb_a[j], HINQS_EXC_1B, HINQS_EXC_2BB);
                     ++out;
                 }
             } else {
@@ -195,6 +195,8 @@ __global__ __launch_bounds__(256) void k_cross(CrossArgs a, int64_t *cnt, int64_
     for (int32_t l = 0, le = a.xcnt[ag]; l < le; ++l) {  // one move in each spin
         const int32_t tg = a.xlink[(int64_t)ag * a.maxl + l];
         const uint32_t aj = a.ua_a[tg];
+        const int ha = lowbit(aj & ~ai), pa = lowbit(ai & ~aj);  // the alpha move of this group
+        const uint32_t npar = single_parity(aj, ha, pa);
         for (int32_t j0 = a.ga_a[tg], e = a.ga_a[tg + 1]; j0 < e; j0 += SCAN_W) {
             uint32_t m = 0;
 #pragma unroll
@@ -206,7 +208,7 @@ __global__ __launch_bounds__(256) void k_cross(CrossArgs a, int64_t *cnt, int64_
                 for (; m; m &= m - 1) {
                     const int32_t j = j0 + lowbit(m);
                     col[out] = a.amap[j];
-                    desc[out] = pair_desc(ai, bi, aj, a.sb_a[j]);
+                    desc[out] = ab_desc(ha, pa, npar, bi, a.sb_a[j]);
                     ++out;
                 }
             } else {
