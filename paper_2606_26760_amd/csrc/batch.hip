@@ -322,9 +322,22 @@ __global__ __launch_bounds__(256) void k_britz(const Chunk *__restrict__ chunks,
 
 // Sum of the chunk partials of instance b, element e (fixed order).
 __device__ inline double chunk_sum(const double *__restrict__ part, int stride, int c0, int c1, int e) {
-    double s = 0.0;
-    for (int ch = c0; ch < c1; ++ch) s += part[(int64_t)ch * stride + e];
-    return s;
+    // eight independent loads in flight (a plain loop waits for each load in
+    // turn); fixed order, so the sum is reproducible
+    constexpr int U = 8;
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = 0.0;
+    int ch = c0;
+    for (; ch + U <= c1; ch += U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = part[(int64_t)(ch + u) * stride + e];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] += v[u];
+    }
+    for (; ch < c1; ++ch) acc[0] += part[(int64_t)ch * stride + e];
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 }
 
 constexpr int RR_LD = MS + 1;
@@ -359,11 +372,11 @@ __global__ __launch_bounds__(NT) void k_brr(BDev st, int m, int restart, const d
     const int base = m - KK;
     const int c0 = st.inst_chunk[b], c1 = st.inst_chunk[b + 1];
     for (int e = tid; e < m * KK; e += NT) gn[e] = chunk_sum(gpart, PSTRIDE, c0, c1, e);
-    if (tid == 0) {
-        int n = 0;
-        for (int j = 0; j < m; ++j)
-            if (st.valid[b * MS + j]) vidx[n++] = j;
-        misc[0] = n;
+    if (tid < 64) {  // valid columns, ascending, by one wave (m <= MS = 64)
+        const bool ok = tid < m && st.valid[b * MS + tid] != 0;
+        const uint64_t bal = __ballot(ok);
+        if (ok) vidx[__popcll(bal & ((1ull << tid) - 1ull))] = tid;
+        if (tid == 0) misc[0] = __popcll(bal);
     }
     __syncthreads();
     const int nv = misc[0];
