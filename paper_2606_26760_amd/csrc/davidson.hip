@@ -423,8 +423,10 @@ void jacobi_eig(int n, std::vector<double> A, std::vector<double> &w, std::vecto
 // needs more than 60 QL iterations (the caller then falls back to Jacobi).
 bool tridiag_ql_eig(int n, std::vector<double> A, std::vector<double> &w, std::vector<double> &Z) {
     auto a = [&](int i, int j) -> double & { return A[(size_t)i * n + j]; };
-    std::vector<double> Q((size_t)n * n, 0.0), v(n), pv(n), d(n), e(n, 0.0);
-    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+    // QT holds Q transposed (row j = column j of Q), so the updates below run
+    // along contiguous rows
+    std::vector<double> QT((size_t)n * n, 0.0), v(n), pv(n), d(n), e(n, 0.0), tq(n);
+    for (int i = 0; i < n; ++i) QT[(size_t)i * n + i] = 1.0;
     // Householder: A <- H A H column by column, Q <- Q H
     for (int k = 0; k + 2 < n; ++k) {
         double alpha = 0.0;
@@ -451,12 +453,18 @@ bool tridiag_ql_eig(int n, std::vector<double> A, std::vector<double> &w, std::v
         for (int i = k; i < n; ++i) pv[i] -= kk * v[i];
         for (int i = k; i < n; ++i)
             for (int j = k; j < n; ++j) a(i, j) -= v[i] * pv[j] + pv[i] * v[j];
-        // Q <- Q (I - beta v v^T)
-        for (int i = 0; i < n; ++i) {
-            double t = 0.0;
-            for (int j = k + 1; j < n; ++j) t += Q[(size_t)i * n + j] * v[j];
-            t *= beta;
-            for (int j = k + 1; j < n; ++j) Q[(size_t)i * n + j] -= t * v[j];
+        // Q <- Q (I - beta v v^T): t_i = beta sum_j Q[i][j] v[j], Q[i][j] -= t_i v[j]
+        for (int i = 0; i < n; ++i) tq[i] = 0.0;
+        for (int j = k + 1; j < n; ++j) {
+            const double *qj = &QT[(size_t)j * n];
+            const double vj = v[j];
+            for (int i = 0; i < n; ++i) tq[i] += qj[i] * vj;
+        }
+        for (int i = 0; i < n; ++i) tq[i] *= beta;
+        for (int j = k + 1; j < n; ++j) {
+            double *qj = &QT[(size_t)j * n];
+            const double vj = v[j];
+            for (int i = 0; i < n; ++i) qj[i] -= tq[i] * vj;
         }
     }
     for (int i = 0; i < n; ++i) d[i] = a(i, i);
@@ -493,11 +501,11 @@ bool tridiag_ql_eig(int n, std::vector<double> A, std::vector<double> &w, std::v
                     p = s * r;
                     d[i + 1] = g + p;
                     g = c * r - b;
+                    double *zi = &QT[(size_t)i * n], *zi1 = &QT[(size_t)(i + 1) * n];
                     for (int k = 0; k < n; ++k) {
-                        double *zk = &Q[(size_t)k * n];
-                        f = zk[i + 1];
-                        zk[i + 1] = s * zk[i] + c * f;
-                        zk[i] = c * zk[i] - s * f;
+                        const double fk = zi1[k];
+                        zi1[k] = s * zi[k] + c * fk;
+                        zi[k] = c * zi[k] - s * fk;
                     }
                 }
                 if (r == 0.0 && i >= l) continue;
@@ -516,7 +524,8 @@ bool tridiag_ql_eig(int n, std::vector<double> A, std::vector<double> &w, std::v
     Z.assign((size_t)n * n, 0.0);
     for (int c = 0; c < n; ++c) {
         w[c] = d[ord[c]];
-        for (int k = 0; k < n; ++k) Z[(size_t)k * n + c] = Q[(size_t)k * n + ord[c]];
+        const double *qc = &QT[(size_t)ord[c] * n];
+        for (int k = 0; k < n; ++k) Z[(size_t)k * n + c] = qc[k];
     }
     return true;
 }
