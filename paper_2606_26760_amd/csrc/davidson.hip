@@ -480,14 +480,17 @@ bool tridiag_ql_eig(int n, std::vector<double> A, std::vector<double> &w, std::v
             if (m != l) {
                 if (++iter > 60) return false;
                 double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-                double r = std::hypot(g, 1.0);
+                double r = std::sqrt(g * g + 1.0);
                 g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? std::fabs(r) : -std::fabs(r)));
                 double s = 1.0, c = 1.0, p = 0.0;
                 int i;
                 for (i = m - 1; i >= l; --i) {
                     double f = s * e[i];
                     const double b = c * e[i];
-                    r = std::hypot(f, g);
+                    // plain sqrt instead of hypot: the entries of these Gram matrices
+                    // are far from overflow, and a norm that underflows to zero takes
+                    // the exact-zero branch below
+                    r = std::sqrt(f * f + g * g);
                     e[i + 1] = r;
                     if (r == 0.0) {
                         d[i + 1] -= p;
