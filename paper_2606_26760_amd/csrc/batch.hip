@@ -87,14 +87,15 @@ struct BDev {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// Sum over a workgroup of NT threads; every thread receives the same value.
+// Sum over a workgroup of B threads; every thread receives the same value.
+template <int B = NT>
 __device__ double block_sum(double v, double *red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = 0.0;
-    for (int w = 0; w < NT / 64; ++w) s += red[w];
+    for (int w = 0; w < B / 64; ++w) s += red[w];
     return s;
 }
 
@@ -108,49 +109,40 @@ __device__ double wave_sum(double v) {
 // leading dimension LD, n <= MAXN <= 64).  Rotations follow a round-robin
 // pairing: each round pairs every index once, the n/2 disjoint rotations are
 // computed from the current matrix and applied together (columns, then
-// rows); the (pair, index) decomposition of each thread's elements is
-// computed once, so a round costs only LDS traffic and one rotation per
+// rows); each thread steps through its elements' (pair, index) positions
+// by a fixed stride, so a round costs only LDS traffic and one rotation per
 // pair.  Sweeps stop when the off-diagonal mass falls below 1e-32 of the
 // Frobenius norm.  On return A's diagonal holds the eigenvalues and row j of
 // ZT the eigenvector belonging to A[j][j].
-template <int LD, int MAXN>
+template <int LD, int MAXN, int B = NT>
 __device__ void block_jacobi(int n, double *A, double *ZT, int *pp, int *pq, double *pc, double *ps,
                              double *red) {
-    constexpr int MAXE = ((MAXN + 1) / 2 * MAXN + NT - 1) / NT;  // elements per thread and phase
+    constexpr int MAXE = ((MAXN + 1) / 2 * MAXN + B - 1) / B;  // elements per thread and phase
     const int tid = threadIdx.x;
-    for (int e = tid; e < n * n; e += NT) {
+    for (int e = tid; e < n * n; e += B) {
         const int i = e / n, j = e % n;
         ZT[i * LD + j] = i == j ? 1.0 : 0.0;
     }
     double f = 0.0;
-    for (int e = tid; e < n * n; e += NT) {
+    for (int e = tid; e < n * n; e += B) {
         const double x = A[(e / n) * LD + e % n];
         f += x * x;
     }
-    const double fro = block_sum(f, red);
+    const double fro = block_sum<B>(f, red);
     if (n < 2) return;
     const int ne = n + (n & 1), np = ne / 2, nr = ne - 1;
-    const int nel = np * n;
-    // (pair, index) of every element this thread updates, fixed for the whole
-    // solve: column phase pairs vary fastest (neighbouring threads hit
-    // different banks), row phase indices vary fastest (contiguous rows)
-    int ck[MAXE], cj[MAXE], rk[MAXE], rj[MAXE];
-#pragma unroll
-    for (int u = 0; u < MAXE; ++u) {
-        const int e = tid + u * NT;
-        const bool ok = e < nel;
-        ck[u] = ok ? e % np : -1;
-        cj[u] = ok ? e / np : 0;
-        rk[u] = ok ? e / n : -1;
-        rj[u] = ok ? e % n : 0;
-    }
+    // element e = tid + u B of a phase: column phase (pair e % np, row e / np,
+    // so neighbouring threads hit different banks), row phase (pair e / n,
+    // column e % n, contiguous rows); both advance by B per slot
+    const int ck0 = tid % np, cj0 = tid / np, cstep_k = B % np, cstep_j = B / np;
+    const int rj0 = tid % n, rk0 = tid / n, rstep_j = B % n, rstep_k = B / n;
     for (int sweep = 0; sweep < 50; ++sweep) {
         double o = 0.0;
-        for (int e = tid; e < n * n; e += NT) {
+        for (int e = tid; e < n * n; e += B) {
             const int i = e / n, j = e % n;
             if (i < j) o += A[i * LD + j] * A[i * LD + j];
         }
-        const double off = block_sum(o, red);
+        const double off = block_sum<B>(o, red);
         if (off == 0.0 || off <= 1e-32 * fro) break;
         for (int r = 0; r < nr; ++r) {
             if (tid < np) {
@@ -181,30 +173,40 @@ __device__ void block_jacobi(int n, double *A, double *ZT, int *pp, int *pq, dou
                 ps[tid] = s;
             }
             __syncthreads();
-#pragma unroll
-            for (int u = 0; u < MAXE; ++u) {  // columns p, q
-                if (ck[u] < 0) continue;
-                const int q = pq[ck[u]];
-                if (q < 0) continue;
-                const int o1 = cj[u] * LD + pp[ck[u]], o2 = cj[u] * LD + q;
-                const double c = pc[ck[u]], s = ps[ck[u]];
-                const double x1 = A[o1], x2 = A[o2];
-                A[o1] = c * x1 - s * x2;
-                A[o2] = s * x1 + c * x2;
+            for (int u = 0, k = ck0, j = cj0; u < MAXE && j < n; ++u) {  // columns p, q
+                const int q = pq[k];
+                if (q >= 0) {
+                    const int o1 = j * LD + pp[k], o2 = j * LD + q;
+                    const double c = pc[k], s = ps[k];
+                    const double x1 = A[o1], x2 = A[o2];
+                    A[o1] = c * x1 - s * x2;
+                    A[o2] = s * x1 + c * x2;
+                }
+                k += cstep_k;
+                j += cstep_j;
+                if (k >= np) {
+                    k -= np;
+                    ++j;
+                }
             }
             __syncthreads();
-#pragma unroll
-            for (int u = 0; u < MAXE; ++u) {  // rows p, q and the eigenvector rows
-                if (rk[u] < 0) continue;
-                const int q = pq[rk[u]];
-                if (q < 0) continue;
-                const int o1 = pp[rk[u]] * LD + rj[u], o2 = q * LD + rj[u];
-                const double c = pc[rk[u]], s = ps[rk[u]];
-                const double x1 = A[o1], x2 = A[o2], z1 = ZT[o1], z2 = ZT[o2];
-                A[o1] = c * x1 - s * x2;
-                A[o2] = s * x1 + c * x2;
-                ZT[o1] = c * z1 - s * z2;
-                ZT[o2] = s * z1 + c * z2;
+            for (int u = 0, k = rk0, j = rj0; u < MAXE && k < np; ++u) {  // rows p, q and eigenvector rows
+                const int q = pq[k];
+                if (q >= 0) {
+                    const int o1 = pp[k] * LD + j, o2 = q * LD + j;
+                    const double c = pc[k], s = ps[k];
+                    const double x1 = A[o1], x2 = A[o2], z1 = ZT[o1], z2 = ZT[o2];
+                    A[o1] = c * x1 - s * x2;
+                    A[o2] = s * x1 + c * x2;
+                    ZT[o1] = c * z1 - s * z2;
+                    ZT[o2] = s * z1 + c * z2;
+                }
+                j += rstep_j;
+                k += rstep_k;
+                if (j >= n) {
+                    j -= n;
+                    ++k;
+                }
             }
             __syncthreads();
         }
@@ -341,7 +343,12 @@ __device__ inline double chunk_sum(const double *__restrict__ part, int stride, 
 }
 
 constexpr int RR_LD = MS + 1;
-constexpr size_t RR_LDS_BYTES = sizeof(double) * (2 * MS * RR_LD + 2 * MS * KB + 2 * KB * KB + KB + NT / 64 + MS) +
+// Threads of the Rayleigh-Ritz kernel: its Jacobi rounds are bound by LDS
+// traffic and latency, so a full 16-wave workgroup per instance beats fewer
+// waves despite the barriers (at m = 48: 1024 threads 0.55 ms, 256 threads
+// 0.82 ms, one wave 3.0 ms).
+constexpr int RR_NT = 1024;
+constexpr size_t RR_LDS_BYTES = sizeof(double) * (2 * MS * RR_LD + 2 * MS * KB + 2 * KB * KB + KB + RR_NT / 64 + MS) +
                                 sizeof(int) * (2 * MS + 2 * MS);
 
 // Rayleigh-Ritz of instance b at subspace size m: the last K columns of
@@ -351,7 +358,7 @@ constexpr size_t RR_LDS_BYTES = sizeof(double) * (2 * MS * RR_LD + 2 * MS * KB +
 // the current and the previous Ritz vectors (GD+k); Q (for the tall update),
 // Q^T G Q, Q^T Y and the validity of the new columns are written.
 template <int KK>
-__global__ __launch_bounds__(NT) void k_brr(BDev st, int m, int restart, const double *__restrict__ gpart) {
+__global__ __launch_bounds__(RR_NT) void k_brr(BDev st, int m, int restart, const double *__restrict__ gpart) {
     const int b = blockIdx.x;
     if (st.done[b]) return;
     extern __shared__ double lds[];
@@ -361,8 +368,8 @@ __global__ __launch_bounds__(NT) void k_brr(BDev st, int m, int restart, const d
     double *Yn = gn + MS * KB;             // MS x KK
     double *Y2 = Yn + MS * KB;             // 2KK x KK
     double *th = Y2 + 2 * KB * KB;         // KK
-    double *red = th + KB;                 // NT/64
-    double *pc = red + NT / 64;            // MS/2
+    double *red = th + KB;                 // RR_NT/64
+    double *pc = red + RR_NT / 64;            // MS/2
     double *ps = pc + MS / 2;              // MS/2
     int *pp = (int *)(ps + MS / 2);        // MS/2
     int *pq = pp + MS / 2;                 // MS/2
@@ -371,7 +378,7 @@ __global__ __launch_bounds__(NT) void k_brr(BDev st, int m, int restart, const d
     const int tid = threadIdx.x;
     const int base = m - KK;
     const int c0 = st.inst_chunk[b], c1 = st.inst_chunk[b + 1];
-    for (int e = tid; e < m * KK; e += NT) gn[e] = chunk_sum(gpart, PSTRIDE, c0, c1, e);
+    for (int e = tid; e < m * KK; e += RR_NT) gn[e] = chunk_sum(gpart, PSTRIDE, c0, c1, e);
     if (tid < 64) {  // valid columns, ascending, by one wave (m <= MS = 64)
         const bool ok = tid < m && st.valid[b * MS + tid] != 0;
         const uint64_t bal = __ballot(ok);
@@ -388,18 +395,18 @@ __global__ __launch_bounds__(NT) void k_brr(BDev st, int m, int restart, const d
         if (c < base) return gn[c * KK + (r - base)];
         return 0.5 * (gn[r * KK + (c - base)] + gn[c * KK + (r - base)]);
     };
-    for (int e = tid; e < nv * nv; e += NT) {
+    for (int e = tid; e < nv * nv; e += RR_NT) {
         const int i = e / nv, j = e % nv;
         A[i * RR_LD + j] = gval(vidx[i], vidx[j]);
     }
     __syncthreads();
-    block_jacobi<RR_LD, MS>(nv, A, ZT, pp, pq, pc, ps, red);
+    block_jacobi<RR_LD, MS, RR_NT>(nv, A, ZT, pp, pq, pc, ps, red);
     __syncthreads();
-    for (int e = tid; e < MS * KK; e += NT) Yn[e] = 0.0;
+    for (int e = tid; e < MS * KK; e += RR_NT) Yn[e] = 0.0;
     if (tid < KK) th[tid] = 0.0;
     __syncthreads();
     // lowest KK eigenpairs in ascending order (ties: lower index first)
-    for (int j = tid; j < nv; j += NT) {
+    for (int j = tid; j < nv; j += RR_NT) {
         const double d = A[j * RR_LD + j];
         int rank = 0;
         for (int i = 0; i < nv; ++i) {
@@ -415,11 +422,11 @@ __global__ __launch_bounds__(NT) void k_brr(BDev st, int m, int restart, const d
     double *Yb = st.Y + (int64_t)b * MS * KB;
     if (tid < KB) st.theta[b * KB + tid] = tid < KK ? th[tid] : 0.0;
     if (!restart) {
-        for (int e = tid; e < MS * KB; e += NT) {
+        for (int e = tid; e < MS * KB; e += RR_NT) {
             const int a = e / KB, q = e % KB;
             Yb[e] = (a < m && q < KK) ? Yn[a * KK + q] : 0.0;
         }
-        for (int e = tid; e < m * KK; e += NT) {
+        for (int e = tid; e < m * KK; e += RR_NT) {
             const int r = e / KK, c = base + e % KK;
             const double v = gval(r, c);
             Gb[r * MS + c] = v;
@@ -432,7 +439,7 @@ __global__ __launch_bounds__(NT) void k_brr(BDev st, int m, int restart, const d
     double *Qs = A;            // m x Q2
     double *GQ = A + MS * Q2;  // m x Q2
     double *Gs = ZT;           // m x m, leading dimension RR_LD
-    for (int e = tid; e < m * m; e += NT) {
+    for (int e = tid; e < m * m; e += RR_NT) {
         const int r = e / m, c = e % m;
         Gs[r * RR_LD + c] = gval(r, c);
     }
@@ -463,20 +470,20 @@ __global__ __launch_bounds__(NT) void k_brr(BDev st, int m, int restart, const d
     }
     __syncthreads();
     const unsigned kept = (unsigned)misc[1];
-    for (int e = tid; e < Q2 * KK; e += NT) {  // Ritz coefficients in the new basis
+    for (int e = tid; e < Q2 * KK; e += RR_NT) {  // Ritz coefficients in the new basis
         const int i = e / KK, q = e % KK;
         double s = 0.0;
         for (int a = 0; a < m; ++a) s += Qs[a * Q2 + i] * Yn[a * KK + q];
         Y2[e] = s;
     }
-    for (int e = tid; e < m * Q2; e += NT) {
+    for (int e = tid; e < m * Q2; e += RR_NT) {
         const int r = e / Q2, j = e % Q2;
         double s = 0.0;
         for (int c = 0; c < m; ++c) s += Gs[r * RR_LD + c] * Qs[c * Q2 + j];
         GQ[e] = s;
     }
     __syncthreads();
-    for (int e = tid; e < Q2 * Q2; e += NT) {
+    for (int e = tid; e < Q2 * Q2; e += RR_NT) {
         const int i = e / Q2, j = e % Q2;
         double s1 = 0.0, s2 = 0.0;
         for (int a = 0; a < m; ++a) {
@@ -486,9 +493,9 @@ __global__ __launch_bounds__(NT) void k_brr(BDev st, int m, int restart, const d
         Gb[i * MS + j] = 0.5 * (s1 + s2);
     }
     double *Qb = st.Q + (int64_t)b * MS * 2 * KB;
-    for (int e = tid; e < m * Q2; e += NT) Qb[e] = Qs[e];
-    for (int c = tid; c < MS; c += NT) st.valid[b * MS + c] = (c < Q2 && ((kept >> c) & 1u)) ? 1 : 0;
-    for (int e = tid; e < MS * KB; e += NT) {
+    for (int e = tid; e < m * Q2; e += RR_NT) Qb[e] = Qs[e];
+    for (int c = tid; c < MS; c += RR_NT) st.valid[b * MS + c] = (c < Q2 && ((kept >> c) & 1u)) ? 1 : 0;
+    for (int e = tid; e < MS * KB; e += RR_NT) {
         const int a = e / KB, q = e % KB;
         Yb[e] = (a < Q2 && q < KK) ? Y2[a * KK + q] : 0.0;
     }
@@ -1014,7 +1021,7 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     auto phase = [&](int m) -> int {
         const int restart = (m == mmax) ? 1 : 0;
         const int mp = restart ? 2 * KK : m;
-        hipLaunchKernelGGL(k_brr<KK>, gin, dim3(NT), RR_LDS_BYTES, s, st, m, restart, (const double *)gpart_u.p);
+        hipLaunchKernelGGL(k_brr<KK>, gin, dim3(RR_NT), RR_LDS_BYTES, s, st, m, restart, (const double *)gpart_u.p);
         HQ_LAUNCH_CHECK();
         if (restart) {
             tsmm(V, m, st.Q, MS * 2 * KB, 2 * KK, N2K{}, 1.0, 0.0, V, dn);
