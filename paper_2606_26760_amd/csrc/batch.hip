@@ -682,44 +682,67 @@ __global__ void k_bvalid_init(int nb, int K, int32_t *valid) {
 // Initial block of instance b: unit vectors at its K lowest diagonal elements
 // (lexicographic (value, row) order), written into V's first column block
 // (which is zero on entry).
-__global__ __launch_bounds__(256) void k_binit(int K, const int64_t *__restrict__ inst_row,
-                                               const double *__restrict__ diag, double *__restrict__ V0) {
+template <int KK>
+__global__ __launch_bounds__(256) void k_binit(const int64_t *__restrict__ inst_row, const double *__restrict__ diag,
+                                               double *__restrict__ V0) {
+    // one pass: each thread keeps the KK smallest (value, row) pairs of its
+    // strided rows in ascending order, then KK block-wide minima pop them
     const int b = blockIdx.x, tid = threadIdx.x;
     const int64_t r0 = inst_row[b], r1 = inst_row[b + 1];
-    __shared__ int64_t chosen[KB];
+    __shared__ int64_t chosen[KK];
     __shared__ double sv[256];
     __shared__ int64_t si[256];
-    for (int r = 0; r < K; ++r) {
-        double best = INFINITY;
-        int64_t bi = INT64_MAX;
-        for (int64_t i = r0 + tid; i < r1; i += 256) {
-            bool skip = false;
-            for (int e = 0; e < r; ++e) skip |= chosen[e] == i;
-            if (skip) continue;
-            const double v = diag[i];
-            if (v < best || (v == best && i < bi)) {
-                best = v;
-                bi = i;
+    __shared__ int owner;
+    auto less = [](double v, int64_t i, double w, int64_t j) { return v < w || (v == w && i < j); };
+    double tv[KK];
+    int64_t ti[KK];
+#pragma unroll
+    for (int u = 0; u < KK; ++u) {
+        tv[u] = INFINITY;
+        ti[u] = INT64_MAX;
+    }
+    for (int64_t i = r0 + tid; i < r1; i += 256) {
+        const double v = diag[i];
+        if (!less(v, i, tv[KK - 1], ti[KK - 1])) continue;
+#pragma unroll
+        for (int u = KK - 1; u >= 0; --u) {  // insert, shifting larger entries down
+            if (less(v, i, tv[u], ti[u])) {
+                if (u == 0 || !less(v, i, tv[u - 1], ti[u - 1])) {
+                    tv[u] = v;
+                    ti[u] = i;
+                } else {
+                    tv[u] = tv[u - 1];
+                    ti[u] = ti[u - 1];
+                }
             }
         }
-        sv[tid] = best;
-        si[tid] = bi;
+    }
+    for (int r = 0; r < KK; ++r) {
+        sv[tid] = tv[0];
+        si[tid] = ti[0];
         __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (tid < s) {
-                const double v = sv[tid + s];
-                const int64_t j = si[tid + s];
-                if (v < sv[tid] || (v == sv[tid] && j < si[tid])) {
-                    sv[tid] = v;
-                    si[tid] = j;
-                }
+        for (int st = 128; st > 0; st >>= 1) {
+            if (tid < st && less(sv[tid + st], si[tid + st], sv[tid], si[tid])) {
+                sv[tid] = sv[tid + st];
+                si[tid] = si[tid + st];
             }
             __syncthreads();
         }
         if (tid == 0) chosen[r] = si[0];
+        if (ti[0] == si[0] && si[0] != INT64_MAX) owner = tid;  // rows are distinct: one owner
+        __syncthreads();
+        if (si[0] != INT64_MAX && tid == owner) {  // pop the head
+#pragma unroll
+            for (int u = 0; u + 1 < KK; ++u) {
+                tv[u] = tv[u + 1];
+                ti[u] = ti[u + 1];
+            }
+            tv[KK - 1] = INFINITY;
+            ti[KK - 1] = INT64_MAX;
+        }
         __syncthreads();
     }
-    if (tid < K && chosen[tid] >= r0 && chosen[tid] < r1) V0[chosen[tid] * K + tid] = 1.0;
+    if (tid < KK && chosen[tid] >= r0 && chosen[tid] < r1) V0[chosen[tid] * KK + tid] = 1.0;
 }
 
 // Final vector of every instance: x = V y_0 over the instance's final
@@ -1009,7 +1032,7 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     };
 
     // ---- initial block (unit vectors at the lowest diagonal elements), its images and G
-    hipLaunchKernelGGL(k_binit, gin, b256, 0, s, KK, B.inst_row.p, g.diag.p, Vb.p);
+    hipLaunchKernelGGL(k_binit<KK>, gin, b256, 0, s, (const int64_t *)B.inst_row.p, (const double *)g.diag.p, Vb.p);
     HQ_LAUNCH_CHECK();
     sigma(V.p, W.p);
     const int32_t *dn = st.done, *g2 = st.skip2;
