@@ -627,38 +627,61 @@ __global__ __launch_bounds__(NT) void k_bpost_orth(BDev st, const int32_t *__res
 
 // Coupling-balanced XCD row ranges over the instances still running: range x
 // starts at the first row whose running-coupling prefix reaches x/8 of the
-// total.  One thread per bound.
+// total.  One wave: the instances' coupling counts are read 64 at a time and
+// summed with shuffles, lane x (1..7) finds the instance where its target is
+// crossed from the chunk's prefix sums, then binary-searches the row in it.
 __global__ void k_bbalance(int nb, const int64_t *__restrict__ inst_row, const int64_t *__restrict__ rowptr,
                            const int32_t *__restrict__ done, int64_t *__restrict__ ranges) {
-    const int x = threadIdx.x;
-    if (x > 8) return;
+    const int lane = threadIdx.x;  // 64 threads
     const int64_t N = inst_row[nb];
-    if (x == 0 || x == 8) {
-        ranges[x] = x == 0 ? 0 : N;
-        return;
-    }
+    auto count = [&](int b) -> int64_t {
+        return (b < nb && !done[b]) ? rowptr[inst_row[b + 1]] - rowptr[inst_row[b]] : 0;
+    };
     int64_t tot = 0;
-    for (int b = 0; b < nb; ++b)
-        if (!done[b]) tot += rowptr[inst_row[b + 1]] - rowptr[inst_row[b]];
-    const int64_t t = tot / 8 * x + (tot % 8) * x / 8;
-    int64_t acc = 0;
-    for (int b = 0; b < nb; ++b) {
-        if (done[b]) continue;
-        const int64_t z0 = rowptr[inst_row[b]], nz = rowptr[inst_row[b + 1]] - z0;
-        if (acc + nz > t) {
-            int64_t lo = inst_row[b], hi = inst_row[b + 1];
-            const int64_t want = t - acc + z0;
+    for (int b0 = 0; b0 < nb; b0 += 64) {
+        int64_t v = count(b0 + lane);
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        tot += v;
+    }
+    const int64_t t = tot / 8 * lane + (tot % 8) * lane / 8;  // used by lanes 1..7
+    int bsel = -1;
+    int64_t before = 0, acc = 0;
+    for (int b0 = 0; b0 < nb; b0 += 64) {
+        const int64_t nz = count(b0 + lane);
+        int64_t incl = nz;  // inclusive prefix over the chunk
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t y = __shfl_up(incl, off);
+            if (lane >= off) incl += y;
+        }
+        int k = -1;  // first instance of the chunk that crosses this lane's target
+        for (int q = 0; q < 64; ++q) {
+            const int64_t iq = __shfl(incl, q), nq = __shfl(nz, q);
+            if (k < 0 && nq > 0 && acc + iq > t) k = q;
+        }
+        const int ks = k < 0 ? 0 : k;
+        const int64_t ik = __shfl(incl, ks), nk = __shfl(nz, ks);
+        if (bsel < 0 && k >= 0) {
+            bsel = b0 + k;
+            before = acc + ik - nk;
+        }
+        acc += __shfl(incl, 63);
+    }
+    if (lane >= 1 && lane <= 7) {
+        int64_t res = N;
+        if (bsel >= 0) {
+            int64_t lo = inst_row[bsel], hi = inst_row[bsel + 1];
+            const int64_t want = t - before + rowptr[inst_row[bsel]];
             while (lo < hi) {
                 const int64_t mid = (lo + hi) / 2;
                 if (rowptr[mid] < want) lo = mid + 1;
                 else hi = mid;
             }
-            ranges[x] = lo;
-            return;
+            res = lo;
         }
-        acc += nz;
+        ranges[lane] = res;
     }
-    ranges[x] = N;
+    if (lane == 0) ranges[0] = 0;
+    if (lane == 8) ranges[8] = N;
 }
 
 __global__ void k_bcount(int nb, const int32_t *__restrict__ done, int32_t *__restrict__ out) {
