@@ -734,23 +734,56 @@ struct Solver {
         sigma_columns += nc;
     }
 
+    // Symmetric orthonormalization of T[:, 0:kept] in place: S T^T T S = Z
+    // diag(w) Z^T (S = diag(sc)), T <- T S Z_k w_k^(-1/2) over the eigenvalues
+    // w_k > drop, largest first; the unused columns of T are cleared.  Returns
+    // the number kept (0: none) and their smallest eigenvalue in wmin.
+    int sym_orth(int kept, const std::vector<double> &sc, double drop, double &wmin) {
+        double *Zd = scratch_b();  // K x K
+        std::vector<double> g = gram_host(Tm, kept, Tm, kept);
+        for (int a = 0; a < kept; ++a)
+            for (int b = a; b < kept; ++b) {
+                const double v = sc[a] * sc[b] * 0.5 * (g[(size_t)a * kept + b] + g[(size_t)b * kept + a]);
+                g[(size_t)a * kept + b] = g[(size_t)b * kept + a] = v;
+            }
+        std::vector<double> w, Z;
+        small_sym_eig(kept, g, w, Z);
+        std::vector<int> keep;
+        for (int j = kept - 1; j >= 0; --j)  // largest first
+            if (std::isfinite(w[j]) && w[j] > drop) keep.push_back(j);
+        const int nk = (int)keep.size();
+        if (nk == 0) return 0;
+        wmin = w[keep.back()];
+        // K x K transform: rows >= kept and columns >= nk are zero
+        std::vector<double> Zk((size_t)K * K, 0.0);
+        for (int a = 0; a < kept; ++a)
+            for (int q = 0; q < nk; ++q)
+                Zk[(size_t)a * K + q] = sc[a] * Z[(size_t)a * kept + keep[q]] / std::sqrt(w[keep[q]]);
+        upload_small(Zk, Zd);
+        tsmm(Tm, K, Zd, K, 1.0, 0.0, Tm);
+        return nk;
+    }
+
     // Orthonormalize the columns of T against V[:, 0:m] and within T; returns
     // the number of kept directions, left in T[:, 0:kept] (other columns
     // zeroed).  scale[q] (host, K entries) is 1/||T[:, q]|| for the columns to
-    // keep and 0 for those to discard; nullptr = the first n columns, scales
-    // from T^T T.  One projection pass against V, a second only when the first
-    // left less than half of some column's norm (decided on the device), so T
-    // is orthogonal to V to a few ulps; then symmetric orthonormalization of
-    // S T^T T S (S = diag(scale), unit columns): eigen-directions with
-    // eigenvalue <= ORTH_DROP, i.e. with less than a tenth of their norm
-    // outside span(V) and the other new directions, are dropped.  The
-    // transform T S Z w^(-1/2) therefore amplifies what is left of span(V)
-    // and the rounding of T^T T at most tenfold, and T needs no second round.
+    // keep and 0 for those to discard; nullptr = the initial block (the first
+    // n columns, scales from T^T T).  One projection pass against V, a second
+    // only when the first left less than half of some column's norm (decided
+    // on the device), so T is orthogonal to V to a few ulps; then symmetric
+    // orthonormalization of the unit-scaled block.  Corrections drop
+    // eigen-directions with eigenvalue <= ORTH_DROP (less than a tenth of
+    // their norm outside span(V) and the other new directions): the transform
+    // then amplifies rounding at most tenfold and needs no second round.  The
+    // initial block keeps everything above 1e-14 instead, since a warm-start
+    // guess can lie almost inside the span of the unit vectors that join it
+    // and its own direction must survive, and repeats the orthonormalization
+    // (eigenvalues > 1e-4) when the first kept one below 1e-2.
     int orthonormalize(int m, int n, const double *scale) {
-        double *C = scratch_a();   // m x K
-        double *Zd = scratch_b();  // K x K
+        double *C = scratch_a();  // m x K
+        const bool initial = scale == nullptr;
         std::vector<double> sc(K, 0.0);
-        if (scale) {
+        if (!initial) {
             for (int q = 0; q < K; ++q) sc[q] = scale[q];
         } else {
             std::vector<double> g = gram_host(Tm, n, Tm, n);
@@ -778,27 +811,9 @@ struct Solver {
             gram(V, m, Tm, kept, C, gate);
             tsmm(V, m, C, kept, -1.0, 1.0, Tm, gate);
         }
-        std::vector<double> g = gram_host(Tm, kept, Tm, kept);
-        for (int a = 0; a < kept; ++a)
-            for (int b = a; b < kept; ++b) {
-                const double v = sc[a] * sc[b] * 0.5 * (g[(size_t)a * kept + b] + g[(size_t)b * kept + a]);
-                g[(size_t)a * kept + b] = g[(size_t)b * kept + a] = v;
-            }
-        std::vector<double> w, Z;
-        small_sym_eig(kept, g, w, Z);
-        std::vector<int> keep;
-        for (int j = kept - 1; j >= 0; --j)  // largest first
-            if (std::isfinite(w[j]) && w[j] > ORTH_DROP) keep.push_back(j);
-        const int nk = (int)keep.size();
-        if (nk == 0) return 0;
-        // K x K transform: rows >= kept and columns >= nk are zero, so the
-        // unused columns of T are cleared as well
-        std::vector<double> Zk((size_t)K * K, 0.0);
-        for (int a = 0; a < kept; ++a)
-            for (int q = 0; q < nk; ++q)
-                Zk[(size_t)a * K + q] = sc[a] * Z[(size_t)a * kept + keep[q]] / std::sqrt(w[keep[q]]);
-        upload_small(Zk, Zd);
-        tsmm(Tm, K, Zd, K, 1.0, 0.0, Tm);
+        double wmin = 0.0;
+        int nk = sym_orth(kept, sc, initial ? 1e-14 : ORTH_DROP, wmin);
+        if (nk > 0 && initial && wmin < 1e-2) nk = sym_orth(nk, std::vector<double>(K, 1.0), 1e-4, wmin);
         return nk;
     }
 

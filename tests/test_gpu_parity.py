@@ -236,6 +236,25 @@ def test_warm_start_converges_immediately():
     assert st2["iterations"] <= 2
 
 
+def test_warm_start_from_a_reference_dominated_vector():
+    """A weakly correlated state (|c| of the lowest-diagonal determinant about
+    0.98): the guess lies almost inside the span of the unit vectors at the
+    lowest diagonal elements that join it in the initial block, and its own
+    direction must survive the orthonormalization."""
+    ints, a, b, cfg = W.config_inputs(1, ndet=5000)
+    d = np.diag(np.diag(ints.h))
+    ints.h = d + 0.02 * (ints.h - d)  # weak one- and two-electron coupling
+    ints.eri = ints.eri * 0.02
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    e, c, st = s.lowest_eigenpair(tol=1e-10)
+    cmax = float(c.abs().max())
+    e2, c2, st2 = s.lowest_eigenpair(guess=c, tol=1e-8)
+    log(f"  |c|max {cmax:.5f}; cold {st['iterations']} iterations, warm {st2['iterations']}")
+    assert cmax > 0.97
+    assert abs(e2 - e) < 1e-10
+    assert st2["iterations"] <= 2
+
+
 def test_not_converged_returns_best_estimate():
     ints, a, b, cfg = W.config_inputs(1, ndet=3000)
     s = solver_for(ints, a, b, cfg.na, cfg.nb)
