@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restric
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) out[e] = red[0];
@@ -236,7 +236,7 @@ __global__ void k_argmin_partial(int64_t nrows, const double *diag, const int32_
     si[threadIdx.x] = bi;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
+        if ((int)threadIdx.x < s) {
             double v = sv[threadIdx.x + s];
             int64_t j = si[threadIdx.x + s];
             if (v < sv[threadIdx.x] || (v == sv[threadIdx.x] && j < si[threadIdx.x])) {
@@ -263,7 +263,7 @@ __global__ void k_argmin_final(int nblk, const double *pv, const int64_t *pi, in
     si[threadIdx.x] = bi;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
+        if ((int)threadIdx.x < s) {
             double v = sv[threadIdx.x + s];
             int64_t j = si[threadIdx.x + s];
             if (v < sv[threadIdx.x] || (v == sv[threadIdx.x] && j < si[threadIdx.x])) {
@@ -291,7 +291,7 @@ __global__ void k_absmax_partial(int64_t nrows, const double *x, double *pv, int
     si[threadIdx.x] = bi;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
+        if ((int)threadIdx.x < s) {
             double v = sv[threadIdx.x + s];
             int64_t j = si[threadIdx.x + s];
             if (v > sv[threadIdx.x] || (v == sv[threadIdx.x] && j < si[threadIdx.x])) {
