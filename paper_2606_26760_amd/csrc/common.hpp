@@ -94,7 +94,7 @@ __host__ __device__ inline int lowbit(uint32_t x) {  // index of lowest set bit,
 }
 
 // Candidates tested per step of a group scan before the hits are emitted.
-constexpr int SCAN_W = 8;
+constexpr int SCAN_W = 16;
 
 // Davidson: a new direction is kept when the eigenvalue of its unit-scaled
 // block Gram exceeds this (more than a tenth of its norm lies outside the
