@@ -140,13 +140,31 @@ typedef struct hinqs_batch_stats {
 void hinqs_opts_default(hinqs_opts *opts);
 
 /*
+ * Device memory of a context.  Every buffer the library keeps (the sorted
+ * determinant tables, couplings, matrix elements, the Davidson basis, and the
+ * staging of calls that work in sorted order) comes from `alloc` and goes back
+ * through `free`, both called with the context's stream and the `user` pointer
+ * given to hinqs_create; a framework passes its own caching allocator here so
+ * the library's workspace shares its memory pool.  alloc returns NULL when it
+ * cannot provide `bytes` (the call then fails with HINQS_E_OOM and leaves the
+ * context usable); free receives only pointers alloc returned, with the same
+ * stream.  Buffers are released by hinqs_destroy, and when a larger one
+ * replaces them.
+ */
+typedef void *(*hinqs_alloc_fn)(size_t bytes, void *hip_stream, void *user);
+typedef void (*hinqs_free_fn)(void *ptr, void *hip_stream, void *user);
+
+/*
  * Create a context bound to HIP device `device` and stream `hip_stream`
  * (a hipStream_t; NULL = the null stream).  *out receives the handle.
- * Errors: INVALID_ARG, HIP.
+ * alloc_fn / free_fn: the device allocator (both NULL: hipMalloc / hipFree;
+ * exactly one NULL is INVALID_ARG); user is passed back to them unchanged.
+ * Errors: INVALID_ARG, OOM, HIP.
  */
-int hinqs_create(hinqs_ctx **out, int device, void *hip_stream);
+int hinqs_create(hinqs_ctx **out, int device, void *hip_stream, hinqs_alloc_fn alloc_fn,
+                 hinqs_free_fn free_fn, void *user);
 
-/* Release every device buffer of the context.  NULL is ignored. */
+/* Release every device buffer of the context (through its free_fn).  NULL is ignored. */
 void hinqs_destroy(hinqs_ctx *ctx);
 
 /* Message of the last failure on ctx ("" if none); valid until the next call. */

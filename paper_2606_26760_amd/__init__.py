@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 import threading
 
 import numpy as np
@@ -101,6 +102,10 @@ class BatchStats(ctypes.Structure):
 _lib = None
 _lock = threading.Lock()
 
+# hinqs_alloc_fn / hinqs_free_fn
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
 
 def load_library() -> ctypes.CDLL:
     """Load ``libhinqs.so``; raises if it has not been built."""
@@ -115,7 +120,7 @@ def load_library() -> ctypes.CDLL:
         P, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
         sig = {
             "hinqs_opts_default": (None, [P]),
-            "hinqs_create": (i32, [P, i32, P]),
+            "hinqs_create": (i32, [P, i32, P, ALLOC_FN, FREE_FN, P]),
             "hinqs_destroy": (None, [P]),
             "hinqs_last_error": (ctypes.c_char_p, [P]),
             "hinqs_set_integrals": (i32, [P, i32, P, P, dbl]),
@@ -184,10 +189,38 @@ def _host_u64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a).astype(np.uint64))
 
 
-class Hinqs:
-    """One solver context on one device and stream."""
+class TorchAllocator:
+    """Device memory from PyTorch's caching allocator, on the context's stream.
 
-    def __init__(self, device: int = 0, stream=None):
+    ``alloc`` returns 0 when the pool cannot serve the request (the library
+    then reports HINQS_E_OOM); ``free`` hands the block back to the pool, which
+    reuses it in the stream's order without a device synchronisation.
+    """
+
+    def __init__(self, device: int, stream_handle: int):
+        self.device = device
+        self.stream_handle = stream_handle
+
+    def alloc(self, nbytes: int) -> int:
+        try:
+            return int(_torch().cuda.caching_allocator_alloc(nbytes, self.device, self.stream_handle))
+        except Exception:  # torch.OutOfMemoryError and the like: report NULL
+            return 0
+
+    def free(self, ptr: int) -> None:
+        _torch().cuda.caching_allocator_delete(ptr)
+
+
+class Hinqs:
+    """One solver context on one device and stream.
+
+    ``allocator``: ``"torch"`` (default) routes every device buffer of the
+    library through PyTorch's caching allocator; ``"hip"`` leaves the library
+    on hipMalloc/hipFree; any object with ``alloc(nbytes) -> int`` (0 when out
+    of memory) and ``free(ptr)`` is used as given.
+    """
+
+    def __init__(self, device: int = 0, stream=None, allocator="torch"):
         torch = _torch()
         lib = load_library()
         if not torch.cuda.is_available():
@@ -197,8 +230,31 @@ class Hinqs:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         self._lib = lib
+        if allocator == "torch":
+            allocator = TorchAllocator(device, stream.cuda_stream)
+        self.allocator = None if allocator == "hip" else allocator
+        alloc_cb, free_cb = ALLOC_FN(), FREE_FN()  # NULL: hipMalloc / hipFree
+        if self.allocator is not None:
+            source = self.allocator
+
+            def _alloc(nbytes, _stream, _user):
+                try:
+                    return source.alloc(int(nbytes)) or None
+                except Exception:
+                    return None
+
+            def _free(ptr, _stream, _user):
+                try:
+                    source.free(int(ptr))
+                except Exception:
+                    pass
+
+            alloc_cb, free_cb = ALLOC_FN(_alloc), FREE_FN(_free)
+        # the callbacks must outlive every buffer of the context
+        self._callbacks = (alloc_cb, free_cb)
         h = ctypes.c_void_p()
-        rc = lib.hinqs_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        rc = lib.hinqs_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream), alloc_cb,
+                              free_cb, None)
         if rc != HINQS_OK:
             raise HinqsError(rc, "hinqs_create failed")
         self._h = h
@@ -210,6 +266,10 @@ class Hinqs:
             self._h = None
 
     def __del__(self):
+        # at interpreter shutdown the allocator callbacks can no longer run
+        # Python; the process is ending and its device memory goes with it
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

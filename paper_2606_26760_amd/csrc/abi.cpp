@@ -19,6 +19,7 @@ template <typename F>
 int guarded(hinqs_ctx *ctx, F &&f) {
     if (!ctx) return HINQS_E_INVALID_ARG;
     ctx->c.err.clear();
+    AllocScope scope(&ctx->c.alloc);
     try {
         HQ_CHECK(hipSetDevice(ctx->c.device));
         return f(ctx->c);
@@ -64,9 +65,11 @@ void hinqs_opts_default(hinqs_opts *o) {
     o->flags = 0;
 }
 
-int hinqs_create(hinqs_ctx **out, int device, void *hip_stream) {
+int hinqs_create(hinqs_ctx **out, int device, void *hip_stream, hinqs_alloc_fn alloc_fn,
+                 hinqs_free_fn free_fn, void *user) {
     if (!out) return HINQS_E_INVALID_ARG;
     *out = nullptr;
+    if ((alloc_fn == nullptr) != (free_fn == nullptr)) return HINQS_E_INVALID_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HINQS_E_INVALID_ARG;
     if (hipSetDevice(device) != hipSuccess) return HINQS_E_HIP;
@@ -74,6 +77,8 @@ int hinqs_create(hinqs_ctx **out, int device, void *hip_stream) {
     if (!ctx) return HINQS_E_OOM;
     ctx->c.device = device;
     ctx->c.stream = (hipStream_t)hip_stream;
+    ctx->c.alloc = Allocator{alloc_fn, free_fn, user, (hipStream_t)hip_stream};
+    AllocScope scope(&ctx->c.alloc);
     try {  // sigma row counters: zero here, and put back to zero by every launch
         ctx->c.sigma_ctr.ensure(SIGMA_CTR_WORDS);
     } catch (const Error &) {
@@ -92,7 +97,7 @@ void hinqs_destroy(hinqs_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->c.device);
     (void)hipStreamSynchronize(ctx->c.stream);
-    delete ctx;
+    delete ctx;   // every buffer returns its memory to the allocator it came from
 }
 
 const char *hinqs_last_error(const hinqs_ctx *ctx) { return ctx ? ctx->c.err.c_str() : "null context"; }
@@ -160,36 +165,35 @@ int hinqs_sigma(hinqs_ctx *ctx, int k, const void *X, void *S, int precision, in
         }
         // stage through sorted-order buffers (gather X, scatter S); pad k up to K
         const int64_t D = c.ndet;
-        DBuf<char> xs, ss, xp;
-        xs.ensure((size_t)D * K * esz);
-        ss.ensure((size_t)D * K * esz);
+        const size_t bytes = (size_t)D * K * esz;
+        char *xs = c.cs.get<char>(0, bytes);
+        char *ss = c.cs.get<char>(1, bytes);
         const void *src = X;
         if (K != k) {
             // pad to K columns: caller rows of k values -> rows of K values
-            xp.ensure((size_t)D * K * esz);
-            HQ_CHECK(hipMemsetAsync(xp.p, 0, (size_t)D * K * esz, s));
-            HQ_CHECK(hipMemcpy2DAsync(xp.p, (size_t)K * esz, X, (size_t)k * esz, (size_t)k * esz, D,
+            char *xp = c.cs.get<char>(2, bytes);
+            HQ_CHECK(hipMemsetAsync(xp, 0, bytes, s));
+            HQ_CHECK(hipMemcpy2DAsync(xp, (size_t)K * esz, X, (size_t)k * esz, (size_t)k * esz, D,
                                       hipMemcpyDeviceToDevice, s));
-            src = xp.p;
+            src = xp;
         }
-        if (sorted) HQ_CHECK(hipMemcpyAsync(xs.p, src, (size_t)D * K * esz, hipMemcpyDeviceToDevice, s));
-        else gather_rows(s, src, xs.p, c.perm.p, D, K * esz);
-        sigma_sorted(c, K, xs.p, K, ss.p, K, precision, s);
+        if (sorted) HQ_CHECK(hipMemcpyAsync(xs, src, bytes, hipMemcpyDeviceToDevice, s));
+        else gather_rows(s, src, xs, c.perm.p, D, K * esz);
+        sigma_sorted(c, K, xs, K, ss, K, precision, s);
         if (K == k) {
-            if (sorted) HQ_CHECK(hipMemcpyAsync(S, ss.p, (size_t)D * K * esz, hipMemcpyDeviceToDevice, s));
-            else scatter_rows(s, ss.p, S, c.perm.p, D, K * esz);
+            if (sorted) HQ_CHECK(hipMemcpyAsync(S, ss, bytes, hipMemcpyDeviceToDevice, s));
+            else scatter_rows(s, ss, S, c.perm.p, D, K * esz);
         } else {
             // unpad: scatter K-wide rows into a K-wide buffer, then copy k columns
             if (!sorted) {
-                scatter_rows(s, ss.p, xs.p, c.perm.p, D, K * esz);
-                HQ_CHECK(hipMemcpy2DAsync(S, (size_t)k * esz, xs.p, (size_t)K * esz, (size_t)k * esz, D,
+                scatter_rows(s, ss, xs, c.perm.p, D, K * esz);
+                HQ_CHECK(hipMemcpy2DAsync(S, (size_t)k * esz, xs, (size_t)K * esz, (size_t)k * esz, D,
                                           hipMemcpyDeviceToDevice, s));
             } else {
-                HQ_CHECK(hipMemcpy2DAsync(S, (size_t)k * esz, ss.p, (size_t)K * esz, (size_t)k * esz, D,
+                HQ_CHECK(hipMemcpy2DAsync(S, (size_t)k * esz, ss, (size_t)K * esz, (size_t)k * esz, D,
                                           hipMemcpyDeviceToDevice, s));
             }
         }
-        HQ_CHECK(hipStreamSynchronize(s));  // temporaries are released on return
         return HINQS_OK;
     });
 }
@@ -219,10 +223,9 @@ int hinqs_rdm12(hinqs_ctx *ctx, const double *coeffs, double *rdm1, double *rdm2
         if (flags & HINQS_SORTED_ORDER) {
             rdm12_sorted(c, coeffs, rdm1, rdm2);
         } else {
-            DBuf<double> cs;
-            cs.ensure(c.ndet);
-            gather_rows(c.stream, coeffs, cs.p, c.perm.p, c.ndet, 8);
-            rdm12_sorted(c, cs.p, rdm1, rdm2);
+            double *cs = c.cs.get<double>(0, c.ndet);
+            gather_rows(c.stream, coeffs, cs, c.perm.p, c.ndet, 8);
+            rdm12_sorted(c, cs, rdm1, rdm2);
         }
         return HINQS_OK;
     });
@@ -236,10 +239,9 @@ int hinqs_integral_grad(hinqs_ctx *ctx, const double *coeffs, double scale, doub
         if (flags & HINQS_SORTED_ORDER) {
             integral_grad_sorted(c, coeffs, scale, grad_h, grad_eri);
         } else {
-            DBuf<double> cs;
-            cs.ensure(c.ndet);
-            gather_rows(c.stream, coeffs, cs.p, c.perm.p, c.ndet, 8);
-            integral_grad_sorted(c, cs.p, scale, grad_h, grad_eri);
+            double *cs = c.cs.get<double>(0, c.ndet);
+            gather_rows(c.stream, coeffs, cs, c.perm.p, c.ndet, 8);
+            integral_grad_sorted(c, cs, scale, grad_h, grad_eri);
         }
         return HINQS_OK;
     });

@@ -34,6 +34,19 @@ struct Error : std::runtime_error {
 #define HQ_LAUNCH_CHECK() HQ_CHECK(hipGetLastError())
 
 // ---------------------------------------------------------- device buffer
+// Where device memory comes from: the allocator callbacks given to
+// hinqs_create (a framework's caching allocator), or hipMalloc when none were
+// given.  Each entry point installs its context's allocator for the duration
+// of the call; a buffer remembers the allocator it came from and returns its
+// memory there.
+struct Allocator {
+    hinqs_alloc_fn alloc = nullptr;
+    hinqs_free_fn free = nullptr;
+    void *user = nullptr;
+    hipStream_t stream = nullptr;
+};
+inline thread_local const Allocator *g_alloc = nullptr;
+
 // While set, buffers (re)allocated on this thread get twice the requested
 // capacity, so a context rebuilt for a sequence of growing problems (the
 // instances of a batch) reallocates rarely.
@@ -43,14 +56,19 @@ template <typename T>
 struct DBuf {
     T *p = nullptr;
     size_t n = 0;
+    Allocator src;   // allocator p came from (alloc == nullptr: hipMalloc)
     DBuf() = default;
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
     ~DBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (src.free) src.free(p, src.stream, src.user);
+            else (void)hipFree(p);
+        }
         p = nullptr;
         n = 0;
+        src = Allocator{};
     }
     // (Re)allocate to hold at least `count` elements; contents undefined.
     void ensure(size_t count) {
@@ -58,11 +76,18 @@ struct DBuf {
         release();
         if (g_dbuf_grow) count *= 2;
         size_t bytes = (count ? count : 1) * sizeof(T);
-        hipError_t e = hipMalloc((void **)&p, bytes);
-        if (e != hipSuccess) {
-            p = nullptr;
-            throw Error(HINQS_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
-                                         hipGetErrorString(e));
+        if (g_alloc && g_alloc->alloc) {
+            p = (T *)g_alloc->alloc(bytes, (void *)g_alloc->stream, g_alloc->user);
+            if (!p) throw Error(HINQS_E_OOM, "the context's allocator returned no memory for " +
+                                                 std::to_string(bytes) + " bytes");
+            src = *g_alloc;
+        } else {
+            hipError_t e = hipMalloc((void **)&p, bytes);
+            if (e != hipSuccess) {
+                p = nullptr;
+                throw Error(HINQS_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                             hipGetErrorString(e));
+            }
         }
         n = count ? count : 1;
     }
@@ -70,8 +95,16 @@ struct DBuf {
     void swap(DBuf &o) {
         std::swap(p, o.p);
         std::swap(n, o.n);
+        std::swap(src, o.src);
     }
     operator T *() const { return p; }
+};
+
+// Installs an allocator for the current thread until the end of the scope.
+struct AllocScope {
+    const Allocator *prev;
+    explicit AllocScope(const Allocator *a) : prev(g_alloc) { g_alloc = a; }
+    ~AllocScope() { g_alloc = prev; }
 };
 
 // --------------------------------------------------------- bit-string rules
@@ -236,6 +269,7 @@ struct BatchState;  // batched instances (batch.hip)
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    Allocator alloc;   // device memory of every buffer below
     std::string err;
 
     // integrals
@@ -299,6 +333,23 @@ struct Ctx {
         DBuf<double> eri_full;
         DBuf<char> sort;
     } bs;
+    // temporaries of calls that stage data (caller-order sigma, RDMs and
+    // gradients, top-k, expansion, PT2, product closure), kept between calls:
+    // once a size has been seen, repeating the call allocates nothing and has
+    // no buffer to release, so it need not wait for the stream
+    struct CallScratch {
+        DBuf<char> b[5];
+        DBuf<unsigned long long> flags;  // small counters and error flags
+        template <typename T>
+        T *get(int i, size_t count) {
+            b[i].ensure(count * sizeof(T));
+            return (T *)b[i].p;
+        }
+        unsigned long long *words(int n) {
+            flags.ensure(n);
+            return flags.p;
+        }
+    } cs;
     // Davidson workspace (basis, images, staging), kept between solves
     struct DavidsonWork {
         DBuf<double> Vb, Wb, T, Wn, small, partial, nrm, argv, xfin, signbuf;
@@ -360,6 +411,9 @@ SigmaCfg default_cfg(const Ctx &c, int k, int precision);
 // S = H X in sorted order with an explicit launch shape.
 void sigma_launch(const Ctx &c, int k, int precision, const SigmaCfg &cfg, const void *X, int ldx, void *S,
                   int lds, hipStream_t s);
+// FP32 off-diagonal product S = (H - diag(H)) X (X, S with leading dimension k); the caller adds the
+// diagonal term in FP64.
+void sigma_offdiag_fp32(const Ctx &c, int k, const float *X, float *S, hipStream_t s);
 // FP64 sigma over the rows that mk leaves live (X, S with leading dimension k).
 void sigma_masked_fp64(const Ctx &c, int k, const double *X, double *S, const SigmaMask &mk, hipStream_t s);
 

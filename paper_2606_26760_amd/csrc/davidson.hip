@@ -1,6 +1,6 @@
 // Block Davidson eigensolver for the lowest eigenpair of H_B (paper Sec. 2.2,
-// Step 3: "diagonalized with a Davidson eigensolver", warm-started from the
-// previous eigenvector).
+// Step 3: Davidson diagonalization of H_B, warm-started from the previous
+// eigenvector).
 //
 // Storage.  The basis V and its images W = H V live in HBM column-blocked:
 // block b holds columns [bK, bK+K) as a contiguous ndet x K row-major array
@@ -23,11 +23,11 @@
 // basis of the current Ritz vectors and those of the previous iteration,
 // which keeps the convergence of the unrestarted method far better than a
 // restart on the Ritz vectors alone.
-// MIXED precision: FP32 sigma products while the residual is above a switch
-// threshold (or until it stalls for three iterations below 1e-4 |theta|, near
-// the FP32 rounding floor; or for eight anywhere), then a restart on the Ritz
-// vectors, W recomputed with FP64 sigma, and FP64 iterations to the requested
-// tolerance.
+// MIXED precision: FP32 off-diagonal sigma products (diagonal term added in
+// FP64) while the residual is above a switch threshold (or until it stalls for
+// three iterations below 1e-4 |theta|, near the FP32 rounding floor; or for
+// eight anywhere), then a restart on the Ritz vectors, W recomputed with FP64
+// sigma, and FP64 iterations to the requested tolerance.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -329,9 +329,14 @@ __global__ void k_to_f32(int64_t n, const double *x, float *y) {
     if (t < n) y[t] = (float)x[t];
 }
 
-__global__ void k_to_f64(int64_t n, const float *x, double *y) {
+// W = (double)S32 + diag * X: the FP32 product covers the off-diagonal part only, and the
+// diagonal term (whose magnitude is the total energy, ~1e2 Ha) is applied in FP64 to the FP64
+// vector, so FP32 rounding no longer scales with |H_ii| and the FP32 phase can reach a far smaller
+// residual before the FP64 refinement.
+__global__ void k_fp32_finish(int64_t n, int K, const float *s32, const double *diag, const double *x,
+                              double *w) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) y[t] = (double)x[t];
+    if (t < n) w[t] = (double)s32[t] + diag[t / K] * x[t];
 }
 
 // ------------------------------------------------------------ host helpers
@@ -725,8 +730,9 @@ struct Solver {
             const int64_t n = D * K;
             hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n, 256)), dim3(256), 0, s, n, X, X32.p);
             HQ_LAUNCH_CHECK();
-            sigma_sorted(c, K, X32.p, K, S32.p, K, HINQS_FP32, s);
-            hipLaunchKernelGGL(k_to_f64, dim3(grid_for(n, 256)), dim3(256), 0, s, n, S32.p, Wn.p);
+            sigma_offdiag_fp32(c, K, X32.p, S32.p, s);
+            hipLaunchKernelGGL(k_fp32_finish, dim3(grid_for(n, 256)), dim3(256), 0, s, n, K, S32.p, c.diag.p, X,
+                               Wn.p);
             HQ_LAUNCH_CHECK();
         }
         HQ_CHECK(hipEventRecord(e1, s));

@@ -501,22 +501,18 @@ int64_t excitations_per_det(int norb, int na, int nb) {
 
 void top_k(Ctx &c, int64_t n, const double *v, int64_t k, bool largest, int32_t *idx) {
     hipStream_t s = c.stream;
-    DBuf<uint64_t> keys;
-    DBuf<int32_t> vals;
-    DBuf<unsigned> bad;
-    keys.ensure(n);
-    vals.ensure(n);
-    bad.ensure(1);
-    HQ_CHECK(hipMemsetAsync(bad.p, 0, sizeof(unsigned), s));
-    hipLaunchKernelGGL(k_order_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, v, n, largest, keys.p, vals.p,
-                       bad.p);
+    uint64_t *keys = c.cs.get<uint64_t>(0, n);
+    int32_t *vals = c.cs.get<int32_t>(1, n);
+    unsigned *bad = (unsigned *)c.cs.words(1);
+    HQ_CHECK(hipMemsetAsync(bad, 0, sizeof(unsigned), s));
+    hipLaunchKernelGGL(k_order_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, v, n, largest, keys, vals, bad);
     HQ_LAUNCH_CHECK();
-    radix_sort_u64(s, keys.p, vals.p, n, 64, c.work);
+    radix_sort_u64(s, keys, vals, n, 64, c.work);
     unsigned hbad = 0;
-    HQ_CHECK(hipMemcpyAsync(&hbad, bad.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipMemcpyAsync(&hbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     HQ_CHECK(hipStreamSynchronize(s));
     if (hbad) throw Error(HINQS_E_NONFINITE, "values contain NaN");
-    hipLaunchKernelGGL(k_take_top, dim3(grid_for(k, 256)), dim3(256), 0, s, vals.p, k, (const int32_t *)nullptr,
+    hipLaunchKernelGGL(k_take_top, dim3(grid_for(k, 256)), dim3(256), 0, s, vals, k, (const int32_t *)nullptr,
                        idx, (int32_t *)nullptr);
     HQ_LAUNCH_CHECK();
     HQ_CHECK(hipStreamSynchronize(s));
@@ -527,27 +523,26 @@ int64_t expand(Ctx &c, const double *coeffs, bool sorted, int64_t ntop, int64_t 
     hipStream_t s = c.stream;
     const int64_t n = c.ndet;
     if (ntop > n) ntop = n;
-    // the ntop largest |c| (stable: ties keep the lower index first)
-    DBuf<uint64_t> keys;
-    DBuf<int32_t> vals, pos;
-    DBuf<unsigned> bad;
-    keys.ensure(n);
-    vals.ensure(n);
-    pos.ensure(ntop);
-    bad.ensure(1);
-    HQ_CHECK(hipMemsetAsync(bad.p, 0, sizeof(unsigned), s));
-    hipLaunchKernelGGL(k_mag_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, coeffs, n, keys.p, vals.p, bad.p);
+    // the ntop largest |c| (stable: ties keep the lower index first).  Scratch
+    // slots 0 and 1 hold the sort keys and values, then (stream-ordered after
+    // the top ntop have been taken) the raw excitations and their sort values.
+    uint64_t *keys = c.cs.get<uint64_t>(0, n);
+    int32_t *vals = c.cs.get<int32_t>(1, n);
+    int32_t *pos = c.cs.get<int32_t>(2, ntop);
+    unsigned long long *words = c.cs.words(2);
+    unsigned *bad = (unsigned *)words;
+    unsigned long long *cnt = words + 1;
+    HQ_CHECK(hipMemsetAsync(bad, 0, sizeof(unsigned), s));
+    hipLaunchKernelGGL(k_mag_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, coeffs, n, keys, vals, bad);
     HQ_LAUNCH_CHECK();
-    radix_sort_u64(s, keys.p, vals.p, n, 63, c.work);
+    radix_sort_u64(s, keys, vals, n, 63, c.work);
     unsigned hbad = 0;
-    HQ_CHECK(hipMemcpyAsync(&hbad, bad.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipMemcpyAsync(&hbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     HQ_CHECK(hipStreamSynchronize(s));
     if (hbad) throw Error(HINQS_E_NONFINITE, "coefficients contain NaN/Inf");
-    hipLaunchKernelGGL(k_take_top, dim3(grid_for(ntop, 256)), dim3(256), 0, s, vals.p, ntop,
-                       sorted ? (const int32_t *)nullptr : (const int32_t *)c.inv.p, top, pos.p);
+    hipLaunchKernelGGL(k_take_top, dim3(grid_for(ntop, 256)), dim3(256), 0, s, vals, ntop,
+                       sorted ? (const int32_t *)nullptr : (const int32_t *)c.inv.p, top, pos);
     HQ_LAUNCH_CHECK();
-    keys.release();
-    vals.release();
 
     // every single and double of the chosen determinants, kept when coupled and outside B
     const int64_t nexc = excitations_per_det(c.norb, c.na, c.nb);
@@ -555,13 +550,9 @@ int64_t expand(Ctx &c, const double *coeffs, bool sorted, int64_t ntop, int64_t 
     if (cap >= ((int64_t)1 << 31))
         throw Error(HINQS_E_UNSUPPORTED, "expansion of " + std::to_string(ntop) +
                                              " determinants exceeds 2^31 excitations; expand fewer at once");
-    DBuf<uint64_t> raw;
-    DBuf<unsigned long long> cnt;
-    raw.ensure(cap);
-    cnt.ensure(1);
-    HQ_CHECK(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
-    ExpArgs ea{tables_of(c), c.norb, neri_packed(c.norb), c.na, c.nb, ntop, pos.p, c.d_eri.p, c.d_h.p, raw.p,
-               cnt.p};
+    uint64_t *raw = c.cs.get<uint64_t>(0, cap);
+    HQ_CHECK(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s));
+    ExpArgs ea{tables_of(c), c.norb, neri_packed(c.norb), c.na, c.nb, ntop, pos, c.d_eri.p, c.d_h.p, raw, cnt};
     const size_t lds = integral_lds(c);
     const int cus = device_cus(c);
     if (lds <= 150 * 1024) {
@@ -575,25 +566,24 @@ int64_t expand(Ctx &c, const double *coeffs, bool sorted, int64_t ntop, int64_t 
     }
     HQ_LAUNCH_CHECK();
     unsigned long long hcnt = 0;
-    HQ_CHECK(hipMemcpyAsync(&hcnt, cnt.p, sizeof(hcnt), hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipMemcpyAsync(&hcnt, cnt, sizeof(hcnt), hipMemcpyDeviceToHost, s));
     HQ_CHECK(hipStreamSynchronize(s));
     const int64_t nraw = (int64_t)hcnt;
     if (nraw == 0) return 0;
 
     // sort and drop repeats: ascending (alpha, beta)
-    DBuf<int32_t> rv, flag, fpos;
-    rv.ensure(nraw);
-    radix_sort_u64(s, raw.p, rv.p, nraw, 2 * c.norb, c.work);
-    flag.ensure(nraw);
-    fpos.ensure(nraw);
-    hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(nraw, 256)), dim3(256), 0, s, raw.p, nraw, flag.p);
+    int32_t *rv = c.cs.get<int32_t>(1, nraw);
+    radix_sort_u64(s, raw, rv, nraw, 2 * c.norb, c.work);
+    int32_t *flag = c.cs.get<int32_t>(3, nraw);
+    int32_t *fpos = c.cs.get<int32_t>(4, nraw);
+    hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(nraw, 256)), dim3(256), 0, s, raw, nraw, flag);
     HQ_LAUNCH_CHECK();
-    exclusive_scan_i32(s, flag.p, fpos.p, nraw, c.work);
+    exclusive_scan_i32(s, flag, fpos, nraw, c.work);
     int32_t last[2] = {0, 0};
-    HQ_CHECK(hipMemcpyAsync(&last[0], fpos.p + nraw - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HQ_CHECK(hipMemcpyAsync(&last[1], flag.p + nraw - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipMemcpyAsync(&last[0], fpos + nraw - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipMemcpyAsync(&last[1], flag + nraw - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (capacity > 0) {
-        hipLaunchKernelGGL(k_unique_write, dim3(grid_for(nraw, 256)), dim3(256), 0, s, raw.p, flag.p, fpos.p,
+        hipLaunchKernelGGL(k_unique_write, dim3(grid_for(nraw, 256)), dim3(256), 0, s, raw, flag, fpos,
                            nraw, c.norb, capacity, out_a, out_b);
         HQ_LAUNCH_CHECK();
     }
@@ -604,32 +594,29 @@ int64_t expand(Ctx &c, const double *coeffs, bool sorted, int64_t ntop, int64_t 
 void pt2(Ctx &c, const double *coeffs, bool sorted, double e0, int64_t ncand, const uint64_t *ca,
          const uint64_t *cb, double *numer, double *hxx, double *score) {
     hipStream_t s = c.stream;
-    DBuf<double> cs;
     const double *csp = coeffs;
     if (!sorted) {
-        cs.ensure(c.ndet);
-        gather_rows(s, coeffs, cs.p, c.perm.p, c.ndet, 8);
-        csp = cs.p;
+        double *cs = c.cs.get<double>(0, c.ndet);
+        gather_rows(s, coeffs, cs, c.perm.p, c.ndet, 8);
+        csp = cs;
     }
-    DBuf<unsigned> bad;
-    bad.ensure(1);
-    HQ_CHECK(hipMemsetAsync(bad.p, 0, sizeof(unsigned), s));
+    unsigned long long *words = c.cs.words(2);
+    unsigned *bad = (unsigned *)words;
+    unsigned long long *next = words + 1;
+    HQ_CHECK(hipMemsetAsync(bad, 0, sizeof(unsigned), s));
     Pt2Args pa{tables_of(c), c.norb, neri_packed(c.norb), c.na, c.nb, c.alink_max, c.alink_ptr.p, c.alink.p,
-               c.ecore, e0, ncand, ca, cb, csp, c.d_eri.p, c.d_h.p, numer, hxx, score, bad.p};
+               c.ecore, e0, ncand, ca, cb, csp, c.d_eri.p, c.d_h.p, numer, hxx, score, bad};
     // candidates in key order, and their groups in B
-    DBuf<uint64_t> keys;
-    DBuf<int32_t> order, ga_of, gb_of;
-    keys.ensure(ncand);
-    order.ensure(ncand);
-    ga_of.ensure(ncand);
-    gb_of.ensure(ncand);
-    hipLaunchKernelGGL(k_pt2_keys, dim3(grid_for(ncand, 256)), dim3(256), 0, s, ca, cb, ncand, c.norb, keys.p,
-                       order.p);
+    uint64_t *keys = c.cs.get<uint64_t>(1, ncand);
+    int32_t *order = c.cs.get<int32_t>(2, ncand);
+    int32_t *ga_of = c.cs.get<int32_t>(3, ncand);
+    int32_t *gb_of = c.cs.get<int32_t>(4, ncand);
+    hipLaunchKernelGGL(k_pt2_keys, dim3(grid_for(ncand, 256)), dim3(256), 0, s, ca, cb, ncand, c.norb, keys,
+                       order);
     HQ_LAUNCH_CHECK();
-    radix_sort_u64(s, keys.p, order.p, ncand, 2 * c.norb, c.work);
-    keys.release();
-    hipLaunchKernelGGL(k_pt2_groups, dim3(grid_for(ncand, 256)), dim3(256), 0, s, pa.B, ca, cb, order.p, ncand,
-                       c.norb, ga_of.p, gb_of.p);
+    radix_sort_u64(s, keys, order, ncand, 2 * c.norb, c.work);
+    hipLaunchKernelGGL(k_pt2_groups, dim3(grid_for(ncand, 256)), dim3(256), 0, s, pa.B, ca, cb, order, ncand,
+                       c.norb, ga_of, gb_of);
     HQ_LAUNCH_CHECK();
     const size_t lds = integral_lds(c);
     const int cus = device_cus(c);
@@ -638,9 +625,7 @@ void pt2(Ctx &c, const double *coeffs, bool sorted, double e0, int64_t ncand, co
     const int64_t runs = (ncand + PT2_RUN - 1) / PT2_RUN;
     const unsigned grid =
         (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * 2, (runs + PT_NT / 64 - 1) / (PT_NT / 64)));
-    DBuf<unsigned long long> next;
-    next.ensure(1);
-    HQ_CHECK(hipMemsetAsync(next.p, 0, sizeof(unsigned long long), s));
+    HQ_CHECK(hipMemsetAsync(next, 0, sizeof(unsigned long long), s));
     const int moves = c.na * (c.norb - c.na);
     auto launch = [&](auto lds_tag, auto slots_tag) {
         constexpr bool L = decltype(lds_tag)::value;
@@ -648,8 +633,7 @@ void pt2(Ctx &c, const double *coeffs, bool sorted, double e0, int64_t ncand, co
         if (L)
             HQ_CHECK(hipFuncSetAttribute((const void *)k_pt2<L, S>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)lds));
-        hipLaunchKernelGGL((k_pt2<L, S>), dim3(grid), dim3(PT_NT), L ? lds : 0, s, pa, order.p, ga_of.p, gb_of.p,
-                           next.p);
+        hipLaunchKernelGGL((k_pt2<L, S>), dim3(grid), dim3(PT_NT), L ? lds : 0, s, pa, order, ga_of, gb_of, next);
     };
     using T = std::true_type;
     using F = std::false_type;
@@ -667,7 +651,7 @@ void pt2(Ctx &c, const double *coeffs, bool sorted, double e0, int64_t ncand, co
     }
     HQ_LAUNCH_CHECK();
     unsigned hbad = 0;
-    HQ_CHECK(hipMemcpyAsync(&hbad, bad.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HQ_CHECK(hipMemcpyAsync(&hbad, bad, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     HQ_CHECK(hipStreamSynchronize(s));
     if (hbad)
         throw Error(HINQS_E_BAD_OCCUPATION,
@@ -730,15 +714,14 @@ int64_t product_closure(Ctx &c, int64_t cap, uint64_t *out_a, uint64_t *out_b) {
     hipStream_t s = c.stream;
     const int64_t total = (int64_t)c.nua * c.nub - c.ndet;
     if (cap <= 0 || total <= 0) return total;
-    DBuf<int64_t> miss, off;
-    miss.ensure(c.nua + 1);
-    off.ensure(c.nua + 1);
-    HQ_CHECK(hipMemsetAsync(miss.p + c.nua, 0, sizeof(int64_t), s));
-    hipLaunchKernelGGL(k_missing_counts, dim3(grid_for(c.nua, 256)), dim3(256), 0, s, c.ga.p, c.nua, c.nub, miss.p);
+    int64_t *miss = c.cs.get<int64_t>(0, c.nua + 1);
+    int64_t *off = c.cs.get<int64_t>(1, c.nua + 1);
+    HQ_CHECK(hipMemsetAsync(miss + c.nua, 0, sizeof(int64_t), s));
+    hipLaunchKernelGGL(k_missing_counts, dim3(grid_for(c.nua, 256)), dim3(256), 0, s, c.ga.p, c.nua, c.nub, miss);
     HQ_LAUNCH_CHECK();
-    exclusive_scan_i64(s, miss.p, off.p, c.nua + 1, c.work);
+    exclusive_scan_i64(s, miss, off, c.nua + 1, c.work);
     hipLaunchKernelGGL(k_missing_list, dim3(grid_for((int64_t)c.nua * 64, 256)), dim3(256), 0, s, c.ua.p, c.ub.p,
-                       c.sb.p, c.ga.p, c.nua, c.nub, off.p, cap, out_a, out_b);
+                       c.sb.p, c.ga.p, c.nua, c.nub, off, cap, out_a, out_b);
     HQ_LAUNCH_CHECK();
     HQ_CHECK(hipStreamSynchronize(s));
     return total;

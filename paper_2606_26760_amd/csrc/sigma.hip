@@ -256,11 +256,13 @@ __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma(XcdRows ranges, SigmaMask
             for (int c = 0; c < EPL; ++c) acc[c] += __shfl_xor(acc[c], off, TEAM);
         }
         if (g == 0) {
-            const T d = diag[row];
-            T xr[EPL];
-            load_vec<T, EPL>(Xq + row * ldx, xr);
+            if (diag) {   // null: off-diagonal part only (the caller adds the diagonal itself)
+                const T d = diag[row];
+                T xr[EPL];
+                load_vec<T, EPL>(Xq + row * ldx, xr);
 #pragma unroll
-            for (int c = 0; c < EPL; ++c) acc[c] += d * xr[c];
+                for (int c = 0; c < EPL; ++c) acc[c] += d * xr[c];
+            }
             store_vec<T, EPL>(S + row * lds + q * EPL, acc);
         }
         if (nrow >= r1) break;
@@ -378,7 +380,7 @@ __global__ __launch_bounds__(SIGMA_BLOCK) void k_sigma_xr(XcdRows ranges, SigmaM
             const int32_t jr = sl.ok[u] ? sl.j[u] : (int32_t)safe_row;
             load_vec<T, EPL>(Xq + (int64_t)jr * ldx, sl.x[u]);
         }
-        sl.dd = diag[sl.row];
+        sl.dd = diag ? diag[sl.row] : T(0);
         load_vec<T, EPL>(Xq + sl.row * ldx, sl.dx);
     };
     T acc[EPL];
@@ -549,6 +551,12 @@ void sigma_sorted(Ctx &c, int k, const void *X, int ldx, void *S, int lds, int p
         dispatch_k<float>(c, k, cfg, c.val32.p, c.diag32.p, (const float *)X, ldx, (float *)S, lds, s);
     else
         throw Error(HINQS_E_INVALID_ARG, "precision must be HINQS_FP64 or HINQS_FP32");
+}
+
+void sigma_offdiag_fp32(const Ctx &c, int k, const float *X, float *S, hipStream_t s) {
+    if (!c.have_elements) throw Error(HINQS_E_NOT_READY, "matrix elements are not built");
+    const SigmaCfg cfg = sigma_config(c, k, HINQS_FP32);
+    dispatch_k<float>(c, k, cfg, c.val32.p, (const float *)nullptr, X, k, S, k, s);
 }
 
 void sigma_masked_fp64(const Ctx &c, int k, const double *X, double *S, const SigmaMask &mk, hipStream_t s) {

@@ -1,6 +1,7 @@
 """CPU-side checks of the HIP library: it loads, exports every entry point the
 header declares, and its host-side sign rules agree with the oracle's
 operator application.  No GPU computation happens here."""
+import ctypes
 import os
 import re
 
@@ -74,3 +75,14 @@ def test_binding_refuses_without_gpu():
         pytest.skip("a GPU is visible")
     with pytest.raises(RuntimeError):
         hq.Hinqs()
+
+
+def test_create_rejects_half_an_allocator():
+    # alloc_fn without free_fn (or the reverse) is refused before any device call
+    lib = hq.load_library()
+    h = ctypes.c_void_p()
+    alloc = hq.ALLOC_FN(lambda n, s, u: None)
+    free = hq.FREE_FN(lambda p, s, u: None)
+    assert lib.hinqs_create(ctypes.byref(h), 0, None, alloc, hq.FREE_FN(), None) == -1
+    assert lib.hinqs_create(ctypes.byref(h), 0, None, hq.ALLOC_FN(), free, None) == -1
+    assert h.value is None
