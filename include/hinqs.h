@@ -216,9 +216,30 @@ int hinqs_set_determinants_device(hinqs_ctx *ctx, int64_t ndet, const uint64_t *
  *   S          device, same shape and type; must not overlap X
  *   precision  HINQS_FP64 or HINQS_FP32 (FP32 values, vectors and sums)
  *   flags      HINQS_SORTED_ORDER: X and S are in internal sorted order
- * Errors: NOT_READY, INVALID_ARG, UNSUPPORTED, HIP.
+ * Unless X and S are in sorted order, 16-byte aligned and k is 1, 2, 4, 8 or
+ * 16, the call stages them through sorted-order blocks of ndet x K values
+ * (K = k rounded up to those sizes) held by the context.
+ * Errors: NOT_READY, INVALID_ARG, UNSUPPORTED, OOM (staging), HIP.
  */
 int hinqs_sigma(hinqs_ctx *ctx, int k, const void *X, void *S, int precision, int flags);
+
+/*
+ * hinqs_sigma for callers that cannot allocate device memory: code under HIP
+ * graph capture, allocation-free serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, result and errors as hinqs_sigma; it calls no
+ * allocator, no memset and no synchronisation, and the caller still provides
+ * X and S.  The sigma row counters and, when staging is needed (see
+ * hinqs_sigma), the two ndet x K staging blocks live in one static device
+ * array of HINQS_NOALLOC_SCRATCH_BYTES per GPU, set up by the first
+ * hinqs_create on that GPU and held until the process ends.  A call needing
+ * more than the array (4096 + 2 * ndet * K * element size bytes when staged)
+ * fails with UNSUPPORTED.  Every call on one GPU shares that GPU's array and
+ * finds the previous call's contents there: calls that overlap on one GPU
+ * (other streams, contexts or threads) race and must be serialised by the
+ * caller.
+ */
+#define HINQS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int hinqs_sigma_noalloc(hinqs_ctx *ctx, int k, const void *X, void *S, int precision, int flags);
 
 /*
  * Lowest eigenpair of H_B by block Davidson (Step 3, warm-startable as the

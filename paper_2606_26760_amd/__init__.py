@@ -48,7 +48,8 @@ EXPORTED = ["hinqs_opts_default", "hinqs_create", "hinqs_destroy", "hinqs_last_e
             "hinqs_autotune", "hinqs_batch_clear", "hinqs_batch_add", "hinqs_batch_info",
             "hinqs_batch_lowest_eigenpair", "hinqs_expand", "hinqs_pt2", "hinqs_top_k",
             "hinqs_teacher_weights", "hinqs_distinct_strings", "hinqs_update_determinants",
-            "hinqs_grow_basis", "hinqs_get_determinants", "hinqs_product_closure"]
+            "hinqs_grow_basis", "hinqs_get_determinants", "hinqs_product_closure",
+            "hinqs_sigma_noalloc"]
 
 
 class HinqsError(RuntimeError):
@@ -127,6 +128,7 @@ def load_library() -> ctypes.CDLL:
             "hinqs_set_determinants": (i32, [P, i64, P, P, i32, i32]),
             "hinqs_set_determinants_device": (i32, [P, i64, P, P, i32, i32]),
             "hinqs_sigma": (i32, [P, i32, P, P, i32, i32]),
+            "hinqs_sigma_noalloc": (i32, [P, i32, P, P, i32, i32]),
             "hinqs_lowest_eigenpair": (i32, [P, P, P, P, P, P]),
             "hinqs_rdm12": (i32, [P, P, P, P, i32]),
             "hinqs_integral_grad": (i32, [P, P, dbl, P, P, i32]),
@@ -337,6 +339,21 @@ class Hinqs:
         self._check(self._lib.hinqs_sigma(self._h, X.shape[1], self._ptr(X), self._ptr(S), prec,
                                           SORTED_ORDER if sorted_order else 0))
         return S.squeeze(1) if squeeze else S
+
+    def sigma_noalloc(self, X, out, sorted_order: bool = False):
+        """``sigma`` through hinqs_sigma_noalloc: the library allocates nothing
+        (the caller provides ``out``); staging uses the static per-GPU array."""
+        torch = _torch()
+        squeeze = X.dim() == 1
+        prec = HINQS_FP64 if X.dtype == torch.float64 else HINQS_FP32
+        self._dev(X, X.dtype)
+        self._dev(out, X.dtype)
+        if X.shape != out.shape or X.shape[0] != self.ndet:
+            raise ValueError("X and out must both be ndet x k")
+        k = 1 if squeeze else X.shape[1]
+        self._check(self._lib.hinqs_sigma_noalloc(self._h, k, self._ptr(X), self._ptr(out), prec,
+                                                  SORTED_ORDER if sorted_order else 0))
+        return out
 
     def lowest_eigenpair(self, guess=None, *, block=8, max_space=None, max_iter=200, tol=1e-8,
                          mixed=False, precond_floor=1e-8, mixed_switch=1e-5, sorted_order=False,

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhinqs.so")
 SOURCES = ["scan.hip", "dets.hip", "connect.hip", "elements.hip", "sigma.hip", "autotune.hip", "davidson.hip", "batch.hip", "select.hip", "weights.hip", "update.hip",
-           "rdm.hip", "abi.cpp"]
+           "rdm.hip", "noalloc.hip", "abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 CFLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

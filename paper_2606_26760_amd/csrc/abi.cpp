@@ -41,6 +41,14 @@ void require_dets(const Ctx &c) {
     if (!c.have_elements) throw Error(HINQS_E_NOT_READY, "matrix elements are not built");
 }
 
+void check_sigma_args(const Ctx &c, int k, const void *X, const void *S, int precision) {
+    require_dets(c);
+    if (!X || !S) throw Error(HINQS_E_INVALID_ARG, "null vector pointer");
+    if (k < 1 || k > 16) throw Error(HINQS_E_UNSUPPORTED, "k must be in [1, 16]");
+    if (precision != HINQS_FP64 && precision != HINQS_FP32)
+        throw Error(HINQS_E_INVALID_ARG, "precision must be HINQS_FP64 or HINQS_FP32");
+}
+
 }  // namespace
 
 size_t Ctx::device_bytes() const {
@@ -88,6 +96,12 @@ int hinqs_create(hinqs_ctx **out, int device, void *hip_stream, hinqs_alloc_fn a
     if (hipMemset(ctx->c.sigma_ctr.p, 0, sizeof(unsigned long long) * SIGMA_CTR_WORDS) != hipSuccess) {
         delete ctx;
         return HINQS_E_HIP;
+    }
+    try {  // device address of the static scratch of hinqs_sigma_noalloc (once per device)
+        noalloc_setup(device);
+    } catch (const Error &e) {
+        delete ctx;
+        return e.code;
     }
     *out = ctx;
     return HINQS_OK;
@@ -149,11 +163,7 @@ int hinqs_set_determinants_device(hinqs_ctx *ctx, int64_t ndet, const uint64_t *
 
 int hinqs_sigma(hinqs_ctx *ctx, int k, const void *X, void *S, int precision, int flags) {
     return guarded(ctx, [&](Ctx &c) {
-        require_dets(c);
-        if (!X || !S) throw Error(HINQS_E_INVALID_ARG, "null vector pointer");
-        if (k < 1 || k > 16) throw Error(HINQS_E_UNSUPPORTED, "k must be in [1, 16]");
-        if (precision != HINQS_FP64 && precision != HINQS_FP32)
-            throw Error(HINQS_E_INVALID_ARG, "precision must be HINQS_FP64 or HINQS_FP32");
+        check_sigma_args(c, k, X, S, precision);
         const int esz = precision == HINQS_FP64 ? 8 : 4;
         const int K = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
         const bool sorted = (flags & HINQS_SORTED_ORDER) != 0;
@@ -194,6 +204,14 @@ int hinqs_sigma(hinqs_ctx *ctx, int k, const void *X, void *S, int precision, in
                                           hipMemcpyDeviceToDevice, s));
             }
         }
+        return HINQS_OK;
+    });
+}
+
+int hinqs_sigma_noalloc(hinqs_ctx *ctx, int k, const void *X, void *S, int precision, int flags) {
+    return guarded(ctx, [&](Ctx &c) {
+        check_sigma_args(c, k, X, S, precision);
+        sigma_noalloc(c, k, X, S, precision, (flags & HINQS_SORTED_ORDER) != 0);
         return HINQS_OK;
     });
 }

@@ -47,6 +47,10 @@ struct Allocator {
 };
 inline thread_local const Allocator *g_alloc = nullptr;
 
+// While set, any device allocation on this thread is an internal error (the
+// no-allocation entry point runs under it).
+inline thread_local bool g_no_alloc = false;
+
 // While set, buffers (re)allocated on this thread get twice the requested
 // capacity, so a context rebuilt for a sequence of growing problems (the
 // instances of a batch) reallocates rarely.
@@ -73,6 +77,7 @@ struct DBuf {
     // (Re)allocate to hold at least `count` elements; contents undefined.
     void ensure(size_t count) {
         if (count <= n && p) return;
+        if (g_no_alloc) throw Error(HINQS_E_HIP, "internal: device allocation in the no-allocation path");
         release();
         if (g_dbuf_grow) count *= 2;
         size_t bytes = (count ? count : 1) * sizeof(T);
@@ -399,8 +404,17 @@ void radix_sort_u64(hipStream_t s, uint64_t *keys, int32_t *vals, int64_t n, int
                     DBuf<char> &own);
 
 // Sigma (sigma.hip): S = H X in sorted order with leading dimensions.
+// ctr: the kernel's row counters (SIGMA_CTR_WORDS, zero on entry, left at
+// zero); nullptr = the context's own.
 void sigma_sorted(Ctx &c, int k, const void *X, int ldx, void *S, int lds, int precision,
-                  hipStream_t s);
+                  hipStream_t s, unsigned long long *ctr = nullptr);
+
+// No-allocation sigma (noalloc.hip).  noalloc_setup: once per device, with
+// that device current (hinqs_create calls it).  sigma_noalloc: the whole
+// product with counters and staging in the static array; arguments already
+// validated as for hinqs_sigma.
+void noalloc_setup(int device);
+void sigma_noalloc(Ctx &c, int k, const void *X, void *S, int precision, bool sorted);
 // Time the candidate launch shapes on c's couplings, keep the fastest in c
 // (and in a process-wide cache keyed by problem shape).  Returns it.
 SigmaCfg autotune_sigma(Ctx &c, int k, int precision);

@@ -448,7 +448,7 @@ constexpr int lanes_per_coupling() {
 
 template <typename T, int K, int TEAM, int UNR, bool MASK>
 void launch_sigma_u(const Ctx &c, const SigmaCfg &cfg, const SigmaMask &mk, const T *val, const T *diag,
-                    const T *X, int ldx, T *S, int lds, hipStream_t s) {
+                    const T *X, int ldx, T *S, int lds, hipStream_t s, unsigned long long *ctr) {
     static int cus = 0;
     if (!cus) {
         cus = 256;
@@ -468,24 +468,25 @@ void launch_sigma_u(const Ctx &c, const SigmaCfg &cfg, const SigmaMask &mk, cons
     else
         hipLaunchKernelGGL((k_sigma<T, K, TEAM, UNR, MASK>), dim3((unsigned)nblk), dim3(SIGMA_BLOCK), 0, s,
                            ranges, mk, xmap, c.rowptr.p, c.col.p, val, diag, X, ldx, S, lds,
-                           MASK ? (unsigned long long *)nullptr : c.sigma_ctr.p, std::max(1, cfg.run));
+                           MASK ? (unsigned long long *)nullptr : (ctr ? ctr : c.sigma_ctr.p),
+                           std::max(1, cfg.run));
     HQ_LAUNCH_CHECK();
 }
 
 template <typename T, int K, int TEAM, bool MASK>
 void launch_sigma(const Ctx &c, const SigmaCfg &cfg, const SigmaMask &mk, const T *val, const T *diag,
-                  const T *X, int ldx, T *S, int lds, hipStream_t s) {
-    if (cfg.unr <= 2) launch_sigma_u<T, K, TEAM, 2, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s);
-    else if (cfg.unr <= 4) launch_sigma_u<T, K, TEAM, 4, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s);
-    else launch_sigma_u<T, K, TEAM, 8, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s);
+                  const T *X, int ldx, T *S, int lds, hipStream_t s, unsigned long long *ctr) {
+    if (cfg.unr <= 2) launch_sigma_u<T, K, TEAM, 2, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s, ctr);
+    else if (cfg.unr <= 4) launch_sigma_u<T, K, TEAM, 4, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s, ctr);
+    else launch_sigma_u<T, K, TEAM, 8, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s, ctr);
 }
 
 template <typename T, int K, bool MASK>
 void dispatch_team(const Ctx &c, const SigmaCfg &cfg, const SigmaMask &mk, const T *val, const T *diag,
-                   const T *X, int ldx, T *S, int lds, hipStream_t s) {
+                   const T *X, int ldx, T *S, int lds, hipStream_t s, unsigned long long *ctr) {
     constexpr int LPN = lanes_per_coupling<T, K>();
     const int team = std::max(cfg.team, LPN);
-#define HQ_TEAM(n) launch_sigma<T, K, n, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s)
+#define HQ_TEAM(n) launch_sigma<T, K, n, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s, ctr)
     switch (team) {
         case 1: if constexpr (LPN <= 1) { HQ_TEAM(1); break; } [[fallthrough]];
         case 2: if constexpr (LPN <= 2) { HQ_TEAM(2); break; } [[fallthrough]];
@@ -500,13 +501,14 @@ void dispatch_team(const Ctx &c, const SigmaCfg &cfg, const SigmaMask &mk, const
 
 template <typename T, bool MASK = false>
 void dispatch_k(const Ctx &c, int k, const SigmaCfg &cfg, const T *val, const T *diag, const T *X, int ldx,
-                T *S, int lds, hipStream_t s, const SigmaMask &mk = SigmaMask{}) {
+                T *S, int lds, hipStream_t s, const SigmaMask &mk = SigmaMask{},
+                unsigned long long *ctr = nullptr) {
     switch (k) {
-        case 1: dispatch_team<T, 1, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s); break;
-        case 2: dispatch_team<T, 2, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s); break;
-        case 4: dispatch_team<T, 4, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s); break;
-        case 8: dispatch_team<T, 8, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s); break;
-        case 16: dispatch_team<T, 16, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s); break;
+        case 1: dispatch_team<T, 1, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s, ctr); break;
+        case 2: dispatch_team<T, 2, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s, ctr); break;
+        case 4: dispatch_team<T, 4, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s, ctr); break;
+        case 8: dispatch_team<T, 8, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s, ctr); break;
+        case 16: dispatch_team<T, 16, MASK>(c, cfg, mk, val, diag, X, ldx, S, lds, s, ctr); break;
         default: throw Error(HINQS_E_UNSUPPORTED, "sigma block size must be 1, 2, 4, 8 or 16");
     }
 }
@@ -542,13 +544,15 @@ SigmaCfg sigma_config(const Ctx &c, int k, int precision) {
 // X, S in sorted order; k in {1,2,4,8,16}; leading dimensions keep 16-byte
 // alignment of every row (ldx, lds multiples of 16 / sizeof(T) when k >= that).
 void sigma_sorted(Ctx &c, int k, const void *X, int ldx, void *S, int lds, int precision,
-                  hipStream_t s) {
+                  hipStream_t s, unsigned long long *ctr) {
     if (!c.have_elements) throw Error(HINQS_E_NOT_READY, "matrix elements are not built");
     const SigmaCfg cfg = sigma_config(c, k, precision);
     if (precision == HINQS_FP64)
-        dispatch_k<double>(c, k, cfg, c.val.p, c.diag.p, (const double *)X, ldx, (double *)S, lds, s);
+        dispatch_k<double>(c, k, cfg, c.val.p, c.diag.p, (const double *)X, ldx, (double *)S, lds, s,
+                           SigmaMask{}, ctr);
     else if (precision == HINQS_FP32)
-        dispatch_k<float>(c, k, cfg, c.val32.p, c.diag32.p, (const float *)X, ldx, (float *)S, lds, s);
+        dispatch_k<float>(c, k, cfg, c.val32.p, c.diag32.p, (const float *)X, ldx, (float *)S, lds, s,
+                          SigmaMask{}, ctr);
     else
         throw Error(HINQS_E_INVALID_ARG, "precision must be HINQS_FP64 or HINQS_FP32");
 }
