@@ -15,14 +15,20 @@ all; host inputs): build every instance, then one batched FP64 Davidson to
 1e-8 (one graph launch per iteration).  The same 64 instances solved one at a
 time are timed once outside the timed region for comparison.
 
-value = H.X elements applied by the sigma products of the step
-        ((nnz + ndet) * columns, summed over every block product of both
-        parts) / step time.
-The roofline object covers the FP64 sigma kernel: algorithmic bytes per launch
-(12 nnz + 16 k ndet + 16 ndet + 8) over its average launch time, taken from
-HIP events recorded around each launch on the library's stream; sigma_kernel
-adds the counter-measured traffic rate (profiles/sigma_traffic.json) and a
-measured device-to-device copy rate as the practical HBM ceiling.
+value = H.X elements per second of the FP64 block-sigma kernel on the
+        1e6-determinant set ((nnz + ndet) * k per launch over its average
+        launch time, from HIP events recorded around each launch on the
+        library's stream during the timed FP64 solves); the "step" object
+        gives the same elements summed over every block product of the step
+        (both solves and the batch) over the step's wall time.
+The roofline object covers that kernel: algorithmic bytes per launch
+(12 nnz + 16 k ndet + 16 ndet + 8) over the same launch time.  Its traffic
+is the memory-counter figure of profiles/sigma_traffic.json (FETCH_SIZE +
+WRITE_SIZE per launch, scaled by the factors a copy kernel of known size
+gives), used only while the sigma source is the one measured: it counts L2
+requests to the memory fabric, which the Infinity Cache serves in part, so
+its rate is not an HBM rate.  roofline_fp32 is the FP32 sigma kernel, timed
+with HIP events on the library's stream after the timed steps.
 cpu_baseline times the CPU oracle's matrix-free sigma on a bounded row sample.
 
 After the timed steps, the "select" object times one pass of the selection
@@ -66,21 +72,54 @@ def cpu_baseline(o, alpha, cfg, target_s=10.0):
     _, pairs = o.sigma_rows(X, rows, return_pairs=True)
     dt = time.perf_counter() - t0
     return {"value": pairs * cfg.k / dt, "unit": "elements/s", "cores": oracle.Oracle.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": f"matrix-free operator-application sigma, k={cfg.k}, {n2} random rows of the "
                       f"{len(alpha)}-determinant set ({pairs} stored elements), {dt:.1f} s"}
 
 
-def sigma_counter_run(hq, ints, alpha, beta, cfg, reps):
-    """Repeated FP64 block-sigma launches on the workload, then an elementwise
-    kernel that reads and writes 512 MiB each (the calibration reference for
-    FETCH_SIZE / WRITE_SIZE)."""
+def cpu_model():
+    """Host CPU model name (from /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def fp32_sigma_launch(hq, solver, D, k, reps=20):
+    """Average FP32 block-sigma launch time (ms) on the solver's set, from HIP
+    events on the library's stream (the current stream)."""
+    import torch
+    X = torch.randn(D, k, dtype=torch.float32, device="cuda")
+    S = torch.empty_like(X)
+    solver.sigma(X, out=S, sorted_order=True)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        solver.sigma(X, out=S, sorted_order=True)
+        b.record(stream)
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / reps
+
+
+def sigma_counter_run(hq, ints, alpha, beta, cfg, reps, precision="fp64"):
+    """Repeated block-sigma launches on the workload (FP64 or FP32), then two
+    calibration references for the memory counters, three launches each:
+      copy:   an elementwise kernel reading and writing 512 MiB (128-byte
+              streaming requests);
+      gather: index_select of 4 Mi random 64-byte rows of a 64 MiB table
+              (the access pattern of the sigma kernel's X rows), reading
+              256 MiB of rows plus 32 MiB of indices and writing 256 MiB."""
     import torch
     s = hq.Hinqs(0)
     s.set_integrals(ints.h, ints.eri, ints.e_core)
     s.set_determinants(alpha, beta, cfg.na, cfg.nb)
-    # the default launch shape, the one the step's FP64 solves use
-    X = torch.randn(len(alpha), cfg.k, dtype=torch.float64, device="cuda")
+    # the default launch shape, the one the step's solves use
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    X = torch.randn(len(alpha), cfg.k, dtype=dt, device="cuda")
     S = torch.empty_like(X)
     for _ in range(max(1, reps)):
         s.sigma(X, out=S, sorted_order=True)
@@ -88,9 +127,44 @@ def sigma_counter_run(hq, ints, alpha, beta, cfg, reps):
     dst = torch.empty_like(src)
     for _ in range(3):
         torch.mul(src, 1.0, out=dst)
+    del src, dst
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    table = torch.ones(1 << 20, 8, dtype=torch.float64, device="cuda")
+    idx = torch.randint(0, 1 << 20, (4 << 20,), device="cuda", generator=g)
+    out = torch.empty(4 << 20, 8, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        torch.index_select(table, 0, idx, out=out)
     torch.cuda.synchronize()
-    print(json.dumps({"mode": "sigma", "ndet": len(alpha), "nnz": s.info()["nnz"], "launches": reps,
-                      "shape": "default"}))
+    print(json.dumps({"mode": "sigma", "precision": precision, "ndet": len(alpha), "nnz": s.info()["nnz"],
+                      "launches": reps, "shape": "default"}))
+
+
+def solve_run(hq, ints, alpha, beta, cfg, reps):
+    """FP64 and mixed Davidson solves of the workload, `reps` each after one
+    untimed solve of each (for per-kernel traces of the solver alone)."""
+    import torch
+    s = hq.Hinqs(0)
+    s.set_integrals(ints.h, ints.eri, ints.e_core)
+    s.set_determinants(alpha, beta, cfg.na, cfg.nb)
+    out = {"mode": "solve", "ndet": len(alpha), "nnz": s.info()["nnz"]}
+    for mixed in (False, True):
+        s.lowest_eigenpair(tol=cfg.tol, block=cfg.k, mixed=mixed)
+        torch.cuda.synchronize()
+        ms, st = [], None
+        for _ in range(max(1, reps)):
+            t0 = time.perf_counter()
+            e, _, st = s.lowest_eigenpair(tol=cfg.tol, block=cfg.k, mixed=mixed)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+        key = "mixed" if mixed else "fp64"
+        out[key] = {"energy": e, "ms": min(ms), "iterations": st["iterations"],
+                    "iterations_fp32": st["iterations_fp32"], "ms_sigma": st["ms_sigma"],
+                    "sigma_blocks": st["sigma_blocks"]}
+        print(json.dumps({key: out[key]}), flush=True)
+    out["mixed_over_fp64"] = out["mixed"]["ms"] / out["fp64"]["ms"]
+    out["abs_dE"] = abs(out["mixed"]["energy"] - out["fp64"]["energy"])
+    print(json.dumps(out), flush=True)
 
 
 def batch_inputs(n=64):
@@ -209,7 +283,8 @@ def cpu_pt2_rate(o, c, e0, ya, yb, n=40000):
 
 def copy_peak_gbs(nbytes=2 << 30, reps=10):
     """Device-to-device copy rate (bytes read + written per second, GB/s) of
-    a 2 GiB buffer: the practical HBM ceiling next to the 8 TB/s spec."""
+    a 2 GiB buffer (larger than the Infinity Cache): the streaming rate this
+    HBM reaches with a plain copy, next to the 8 TB/s spec."""
     import torch
     src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
@@ -226,8 +301,9 @@ def copy_peak_gbs(nbytes=2 << 30, reps=10):
 
 
 def recorded_traffic():
-    """HBM bytes per FP64 sigma launch from the committed counter summary, or None
-    when the sigma kernel source has changed since the counters were taken."""
+    """Fabric bytes per FP64 sigma launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+    from the committed counter summary, or None when the sigma kernel source
+    has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "sigma_traffic.json")
     src = os.path.join(ROOT, "paper_2606_26760_amd", "csrc", "sigma.hip")
@@ -252,9 +328,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=25.0)
     ap.add_argument("--ntop", type=int, default=1000, help="determinants expanded by the selection pass")
     ap.add_argument("--keep", type=int, default=100000, help="candidates kept by score in the selection pass")
-    ap.add_argument("--mode", choices=["step", "sigma"], default="step",
+    ap.add_argument("--sigma-precision", choices=["fp64", "fp32"], default="fp64",
+                    help="precision of the launches of --mode sigma")
+    ap.add_argument("--mode", choices=["step", "sigma", "solve"], default="step",
                     help="sigma: only repeated FP64 sigma launches plus a copy kernel of known "
-                         "size (for hardware-counter runs)")
+                         "size (for hardware-counter runs); solve: only FP64 and mixed Davidson "
+                         "solves of the workload (for per-kernel traces of the solver)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU path is "
@@ -270,7 +349,10 @@ def main():
     ints, alpha, beta, cfg = W.config_inputs(2, ndet=args.ndet)
     D = len(alpha)
     if args.mode == "sigma":
-        sigma_counter_run(hq, ints, alpha, beta, cfg, args.steps)
+        sigma_counter_run(hq, ints, alpha, beta, cfg, args.steps, args.sigma_precision)
+        return
+    if args.mode == "solve":
+        solve_run(hq, ints, alpha, beta, cfg, args.steps)
         return
     dev = torch.device("cuda", 0)
     a_d = torch.from_numpy(alpha.view(np.int64).copy()).to(dev)
@@ -325,7 +407,7 @@ def main():
     elements = (nnz + D) * cols
     if insts is not None:
         elements += sum(r[3][1]["stats"]["sigma_elements"] for r in res)
-    value = elements / elapsed
+    step_value = elements / elapsed
     # FP64 sigma launches of the FP64 solves: one kernel per event pair
     ms_sig = sum(r[1][1]["ms_sigma"] for r in res)
     n_sig = sum(r[1][1]["sigma_blocks"] for r in res)
@@ -333,7 +415,10 @@ def main():
     k = cfg.k
     alg_bytes = 12 * nnz + 16 * k * D + 8 * (D + 1) + 8 * D
     achieved = alg_bytes / t_launch / 1e9
+    value = (nnz + D) * k / t_launch
     traffic = recorded_traffic()
+    ms32 = fp32_sigma_launch(hq, solver, D, k)
+    alg32 = 8 * nnz + 8 * k * D + 8 * (D + 1) + 4 * D
     med = lambda xs: float(np.median(xs))
     out = {
         "metric": METRIC,
@@ -357,15 +442,24 @@ def main():
                    "batch_instances": 0 if insts is None else len(insts)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_level": "L2-to-fabric requests (FETCH_SIZE + WRITE_SIZE, copy-calibrated); "
+                                      "Infinity Cache hits and HBM are not separable by these counters",
                      "kernel": "k_sigma (FP64 block sigma, k=8)",
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": t_launch * 1e3},
-        "sigma_kernel": {"elements_per_s": (nnz + D) * k / t_launch, "rows_per_s": D * k / t_launch,
+        "roofline_fp32": {"bound": "hbm", "achieved": alg32 / ms32 / 1e6, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": alg32 / ms32 / 1e6 / HBM_PEAK_GBS, "kernel": "k_sigma (FP32 block sigma, k=8)",
+                          "alg_bytes_per_launch": alg32, "avg_launch_ms": ms32,
+                          "elements_per_s": (nnz + D) * k / (ms32 * 1e-3)},
+        "sigma_kernel": {"elements_per_s": value, "rows_per_s": D * k / t_launch,
                          "launches": n_sig,
-                         "traffic_gbs": None if traffic is None else traffic / t_launch / 1e9,
-                         "traffic_frac": None if traffic is None else traffic / t_launch / 1e9 / HBM_PEAK_GBS,
-                         "copy_peak_gbs": copy_peak_gbs()},
+                         "fabric_traffic_gbs": None if traffic is None else traffic / t_launch / 1e9,
+                         "device_copy_gbs": copy_peak_gbs()},
+        "step": {"elements_per_s": step_value, "elements": elements,
+                 "what": "H.X elements of every block product of the step (both solves and the batch) "
+                         "over the step's wall time"},
         "solve_ms": {"fp64": med([r[0]["fp64"] for r in res]) * 1e3,
-                     "mixed": med([r[0]["mixed"] for r in res]) * 1e3},
+                     "mixed": med([r[0]["mixed"] for r in res]) * 1e3,
+                     "mixed_over_fp64": med([r[0]["mixed"] for r in res]) / med([r[0]["fp64"] for r in res])},
         "build_ms": med([r[0]["build"] for r in res]) * 1e3,
         "rdm_ms": med([r[0]["rdm"] for r in res]) * 1e3,
         "energy": {"fp64": res[-1][1][0], "mixed": res[-1][2][0],

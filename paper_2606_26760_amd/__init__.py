@@ -267,10 +267,11 @@ class Hinqs:
             self._lib.hinqs_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the allocator callbacks can no longer run
         # Python; the process is ending and its device memory goes with it
-        if sys.is_finalizing():
+        # (the function is bound at definition: module globals may be gone)
+        if _finalizing():
             return
         try:
             self.close()

@@ -87,6 +87,28 @@ def test_batch_matches_oracle_dense(instances):
             assert abs(float(c[off[i]:off[i + 1]] @ c_ref)) >= 1.0 - 1e-10
 
 
+def test_full_size_instance_vs_oracle_lanczos():
+    """Instance 33 of the batch at full size (norb 12, 7a + 7b, 19,900
+    determinants) solved inside a batch with two smaller full-size instances;
+    its eigenvalue against the oracle's Lanczos at 1e-10 Ha."""
+    insts = [W.batch_instance(i) for i in (33, 0, 12)]
+    assert len(insts[0][1]) > 19000
+    log(f"batch with a full-size instance of {len(insts[0][1])} determinants vs oracle Lanczos")
+    s = _batch(insts)
+    e, c, info = s.batch_lowest_eigenpair(tol=1e-9)
+    assert info["converged"]
+    off = info["offsets"]
+    c = c.cpu().numpy()
+    for i, (ints, a, b, spec) in enumerate(insts):
+        o = oracle_for(ints, a, b, spec["na"], spec["nb"])
+        e_ref, c_ref = o.lowest_eigenpair(dense_max=0 if i == 0 else 5000)
+        log(f"  instance {i}: n={len(a)} E={e[i]!r} ref={e_ref!r}")
+        assert abs(e[i] - e_ref) <= 1e-10, (i, e[i], e_ref)
+        w = o.spectrum(2)
+        if w[1] - w[0] > 1e-6:
+            assert abs(float(c[off[i]:off[i + 1]] @ c_ref)) >= 1.0 - 1e-9
+
+
 def test_graph_replays_equal_plain_launches(instances):
     """Each captured iteration graph is replayed many times; the result must be
     bit-identical to issuing the same kernels directly, and to a second call."""

@@ -78,8 +78,8 @@ def test_couplings_ragged_small_sets():
 
 def test_couplings_1m_sampled_rows():
     ints, a, b, cfg = W.config_inputs(2)
-    rows = np.random.default_rng(7).choice(len(a), 200, replace=False)
-    log("couplings cas16 1e6 dets, 200 sampled rows")
+    rows = np.random.default_rng(7).choice(len(a), 1000, replace=False)
+    log("couplings cas16 1e6 dets, 1000 sampled rows")
     _check_couplings(ints, a, b, cfg.na, cfg.nb, rows)
 
 
@@ -137,10 +137,53 @@ def test_sigma_1m_sampled_rows_fp64_and_fp32():
     log("sigma cas16 1e6 dets, sampled rows")
     s = solver_for(ints, a, b, cfg.na, cfg.nb)
     o = oracle_for(ints, a, b, cfg.na, cfg.nb)
-    rows = np.random.default_rng(8).choice(len(a), 150, replace=False)
+    rows = np.random.default_rng(8).choice(len(a), 1000, replace=False)
     X = W.random_block(len(a), 8, 23)
     _check_sigma(s, o, X, rows, 1e-12)
     _check_sigma(s, o, X, rows, 2e-6, dtype=torch.float32)
+
+
+def _subset_product(orbs, na, nb):
+    """Every determinant whose alpha (na) and beta (nb) electrons sit in the
+    orbitals `orbs`: a complete active space embedded in a larger orbital set."""
+    import itertools
+    strs = lambda n: [sum(1 << o for o in c) for c in itertools.combinations(orbs, n)]
+    sa, sb = strs(na), strs(nb)
+    a = np.array([x for x in sa for _ in sb], dtype=np.uint64)
+    b = np.array([y for _ in sa for y in sb], dtype=np.uint64)
+    return a, b
+
+
+@pytest.mark.parametrize("norb,na,nb,kind", [
+    (28, 4, 3, "cas"), (30, 5, 5, "cas"), (32, 6, 5, "cas"),
+    (28, 4, 3, "sampled"), (32, 2, 2, "sampled"), (32, 31, 1, "sampled")])
+def test_top_of_orbital_range(norb, na, nb, kind):
+    """norb 28-32: the 5-bit orbital fields of the coupling descriptor, the
+    strings' top bits and the global-memory integral path (the packed eri no
+    longer fits in LDS above norb ~ 17).  "cas": all determinants of the
+    lowest four and highest four orbitals (every coupling class among the top
+    orbital indices); "sampled": rank-weighted draws over all orbitals.
+    Couplings bit-exact on every row, FP64 sigma at the 1e-12 row bar, lowest
+    eigenvalue at 1e-10 Ha."""
+    ints = W.gen_integrals(norb, 8, -3.0, -0.5, 700 + norb + na)
+    if kind == "cas":
+        a, b = _subset_product(list(range(4)) + list(range(norb - 4, norb)), na, nb)
+    else:
+        n = {2: 400, 31: 64}.get(na, 3000)
+        a, b = W.sample_determinants(norb, na, nb, n, 0.45, 0.2, 800 + norb + na)
+    log(f"top of range norb={norb} na={na} nb={nb} {kind} n={len(a)}")
+    s, o = _check_couplings(ints, a, b, na, nb, np.arange(len(a)))
+    top = np.uint64(1) << np.uint64(norb - 1)
+    assert np.any((a & top) != 0) and np.any((b & top) != 0)  # the highest orbital is used
+    X = W.random_block(len(a), 3, 31 + norb)
+    _check_sigma(s, o, X, np.arange(len(a)), 1e-12)
+    e_ref, c_ref = o.lowest_eigenpair()
+    e, c, st = s.lowest_eigenpair(tol=1e-9, block=4)
+    log(f"  E={e!r} ref={e_ref!r} it={st['iterations']} nnz={s.info()['nnz']}")
+    assert abs(e - e_ref) <= 1e-10
+    w = o.spectrum(2)
+    if len(w) > 1 and w[1] - w[0] > 1e-6:
+        assert abs(float(np.dot(c.cpu().numpy(), c_ref))) >= 1 - 1e-9
 
 
 def test_sigma_sorted_order_matches_caller_order():
