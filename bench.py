@@ -472,6 +472,13 @@ def main():
     if insts is not None:
         be, binfo = res[-1][3]
         bst = binfo["stats"]
+        # the same batch with the untuned launch shape (2048-row chunks, 1024 Rayleigh-Ritz threads)
+        os.environ["HINQS_BATCH_CHUNK"], os.environ["HINQS_BATCH_RR_THREADS"] = "2048", "1024"
+        try:
+            _, _, dinfo = bsolver.batch_lowest_eigenpair(tol=cfg.tol, block=cfg.k, autotune=True)
+        finally:
+            del os.environ["HINQS_BATCH_CHUNK"], os.environ["HINQS_BATCH_RR_THREADS"]
+        dst = dinfo["stats"]
         sb, ss, se = sequential_batch(hq, insts, cfg.k, cfg.tol)
         ms_solve = med([r[0]["batch_solve"] for r in res]) * 1e3
         out["batch"] = {
@@ -482,6 +489,9 @@ def main():
             "iterations": bst["iterations"], "graphs": bst["graphs"],
             "ms_per_iteration": bst["ms_iterations"] / max(1, bst["iterations"]),
             "sigma_shape": [bst["sigma_team"], bst["sigma_unroll"], bst["sigma_occupancy"]],
+            "tuned_shape": {"chunk_rows": bst["chunk_rows"], "rr_threads": bst["rr_threads"]},
+            "default_shape_ms_per_iteration": dst["ms_iterations"] / max(1, dst["iterations"]),
+            "default_shape_iterations": dst["iterations"],
             "sequential_ms_build": sb * 1e3, "sequential_ms_solve": ss * 1e3,
             "solve_speedup_vs_sequential": ss * 1e3 / ms_solve,
             "max_abs_dE_vs_sequential": float(np.max(np.abs(np.asarray(se) - be))),

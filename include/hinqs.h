@@ -134,6 +134,9 @@ typedef struct hinqs_batch_stats {
     int64_t nnz;               /* stored couplings over all instances */
     int     sigma_team, sigma_unroll, sigma_occupancy;  /* sigma launch shape used */
     double  sigma_elements;    /* H x products applied: sum over instances of (nnz + ndet) * block per sigma */
+    int     chunk_rows;        /* rows per chunk of the tall-skinny kernels */
+    int     rr_threads;        /* threads of the per-instance Rayleigh-Ritz kernel */
+    double  ms_tune;           /* time spent timing launch shapes (HINQS_AUTOTUNE, first call per size class) */
 } hinqs_batch_stats;
 
 /* Fill *opts with the defaults listed above. */

@@ -94,7 +94,8 @@ class BatchStats(ctypes.Structure):
                 ("ms_iterations", ctypes.c_double), ("max_residual", ctypes.c_double),
                 ("ndet", ctypes.c_int64), ("nnz", ctypes.c_int64), ("sigma_team", ctypes.c_int),
                 ("sigma_unroll", ctypes.c_int), ("sigma_occupancy", ctypes.c_int),
-                ("sigma_elements", ctypes.c_double)]
+                ("sigma_elements", ctypes.c_double), ("chunk_rows", ctypes.c_int),
+                ("rr_threads", ctypes.c_int), ("ms_tune", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

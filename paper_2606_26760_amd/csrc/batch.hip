@@ -25,6 +25,8 @@
 // replayed.  Converged instances raise a flag that every kernel checks; the
 // host reads one counter per iteration to learn when all have finished.
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -51,6 +53,16 @@ struct BatchState {
     DBuf<int32_t> row_inst; // global row -> instance
     DBuf<int64_t> inst_row; // row offsets (ninst + 1), device copy
     bool dirty = true;      // inst_row and the XCD row ranges need a refresh
+    // launch shape of the batched iteration (chunk rows of the tall-skinny
+    // kernels, threads of the Rayleigh-Ritz kernel), per block-size index;
+    // tuned[k] says the shape was timed for the current instances
+    struct Shape {
+        int chunk = 2048;
+        int rr_threads = 1024;
+        double ms_per_it = 0.0;
+    };
+    Shape shape[5];
+    std::string tuned_key[5];
 };
 
 namespace {
@@ -343,13 +355,15 @@ __device__ inline double chunk_sum(const double *__restrict__ part, int stride, 
 }
 
 constexpr int RR_LD = MS + 1;
-// Threads of the Rayleigh-Ritz kernel: its Jacobi rounds are bound by LDS
-// traffic and latency, so a full 16-wave workgroup per instance beats fewer
-// waves despite the barriers (at m = 48: 1024 threads 0.55 ms, 256 threads
-// 0.82 ms, one wave 3.0 ms).
-constexpr int RR_NT = 1024;
-constexpr size_t RR_LDS_BYTES = sizeof(double) * (2 * MS * RR_LD + 2 * MS * KB + 2 * KB * KB + KB + RR_NT / 64 + MS) +
-                                sizeof(int) * (2 * MS + 2 * MS);
+// Threads of the Rayleigh-Ritz kernel (RR_NT in {256, 512, 1024}, chosen by
+// the batch tuner): its Jacobi rounds are bound by LDS traffic and latency,
+// so a full 16-wave workgroup per instance usually beats fewer waves despite
+// the barriers (at m = 48: 1024 threads 0.55 ms, 256 threads 0.82 ms, one
+// wave 3.0 ms).
+constexpr size_t rr_lds_bytes(int nt) {
+    return sizeof(double) * (2 * MS * RR_LD + 2 * MS * KB + 2 * KB * KB + KB + nt / 64 + MS) +
+           sizeof(int) * (2 * MS + 2 * MS);
+}
 
 // Rayleigh-Ritz of instance b at subspace size m: the last K columns of
 // G = V^T W arrive as chunk partials (gpart) and are folded into G; the valid
@@ -357,7 +371,7 @@ constexpr size_t RR_LDS_BYTES = sizeof(double) * (2 * MS * RR_LD + 2 * MS * KB +
 // restart (m == m_max): the basis is replaced by an orthonormal basis Q of
 // the current and the previous Ritz vectors (GD+k); Q (for the tall update),
 // Q^T G Q, Q^T Y and the validity of the new columns are written.
-template <int KK>
+template <int KK, int RR_NT>
 __global__ __launch_bounds__(RR_NT) void k_brr(BDev st, int m, int restart, const double *__restrict__ gpart) {
     const int b = blockIdx.x;
     if (st.done[b]) return;
@@ -931,8 +945,8 @@ struct Resources {  // released on every exit path
 };
 
 template <int KK>
-int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *energies, double *coeffs,
-                  int *status, int *iters_out, hinqs_batch_stats *stats,
+int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, const BatchState::Shape &shape,
+                  double *energies, double *coeffs, int *status, int *iters_out, hinqs_batch_stats *stats,
                   std::chrono::steady_clock::time_point t0) {
     const int nb = (int)B.meta.size();
     const int64_t N = B.g.ndet;
@@ -943,7 +957,10 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     const SigmaCfg scfg = sigma_config(B.g, KK, HINQS_FP64);
 
     // ---- chunk list: runs of at most CH rows of one instance
-    const int CH = std::max(64, env_or("HINQS_BATCH_CHUNK", 2048));
+    const int CH = std::max(64, env_or("HINQS_BATCH_CHUNK", shape.chunk));
+    const int RRT = env_or("HINQS_BATCH_RR_THREADS", shape.rr_threads);
+    if (RRT != 256 && RRT != 512 && RRT != 1024)
+        throw Error(HINQS_E_INVALID_ARG, "Rayleigh-Ritz threads must be 256, 512 or 1024");
     std::vector<Chunk> chunks;
     std::vector<int32_t> inst_chunk(nb + 1, 0);
     for (int b = 0; b < nb; ++b) {
@@ -1015,8 +1032,12 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     const auto t_buf = std::chrono::steady_clock::now();
     hipLaunchKernelGGL(k_bvalid_init, dim3(grid_for((int64_t)nb * MS, 256)), dim3(256), 0, s, nb, KK, st.valid);
     HQ_LAUNCH_CHECK();
-    HQ_CHECK(hipFuncSetAttribute((const void *)k_brr<KK>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)RR_LDS_BYTES));
+    HQ_CHECK(hipFuncSetAttribute((const void *)k_brr<KK, 256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)rr_lds_bytes(256)));
+    HQ_CHECK(hipFuncSetAttribute((const void *)k_brr<KK, 512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)rr_lds_bytes(512)));
+    HQ_CHECK(hipFuncSetAttribute((const void *)k_brr<KK, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)rr_lds_bytes(1024)));
 
     const Mat V{Vb.p, KK, (int64_t)bsz}, W{Wb.p, KK, (int64_t)bsz};
     SigmaMask mk;
@@ -1067,7 +1088,15 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
     auto phase = [&](int m) -> int {
         const int restart = (m == mmax) ? 1 : 0;
         const int mp = restart ? 2 * KK : m;
-        hipLaunchKernelGGL(k_brr<KK>, gin, dim3(RR_NT), RR_LDS_BYTES, s, st, m, restart, (const double *)gpart_u.p);
+        if (RRT == 1024)
+            hipLaunchKernelGGL((k_brr<KK, 1024>), gin, dim3(1024), rr_lds_bytes(1024), s, st, m, restart,
+                               (const double *)gpart_u.p);
+        else if (RRT == 512)
+            hipLaunchKernelGGL((k_brr<KK, 512>), gin, dim3(512), rr_lds_bytes(512), s, st, m, restart,
+                               (const double *)gpart_u.p);
+        else
+            hipLaunchKernelGGL((k_brr<KK, 256>), gin, dim3(256), rr_lds_bytes(256), s, st, m, restart,
+                               (const double *)gpart_u.p);
         HQ_LAUNCH_CHECK();
         if (restart) {
             tsmm(V, m, st.Q, MS * 2 * KB, 2 * KK, N2K{}, 1.0, 0.0, V, dn);
@@ -1201,8 +1230,68 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, double *
         stats->sigma_unroll = scfg.unr;
         stats->sigma_occupancy = scfg.occ;
         stats->sigma_elements = elements;
+        stats->chunk_rows = CH;
+        stats->rr_threads = RRT;
     }
     return nconv == nb ? HINQS_OK : HINQS_E_NOT_CONVERGED;
+}
+
+}  // namespace
+
+namespace {
+
+// Batch launch shapes tuned in this process, keyed by device architecture,
+// block size, subspace limit, instance count and problem-size class.
+std::mutex g_bshape_mutex;
+std::map<std::string, BatchState::Shape> g_bshape_cache;
+
+std::string batch_shape_key(const Ctx &c, const BatchState &B, int K, int mmax) {
+    hipDeviceProp_t prop;
+    std::string arch = "gpu";
+    if (hipGetDeviceProperties(&prop, c.device) == hipSuccess) arch = prop.gcnArchName;
+    const int64_t n = B.g.ndet, z = B.g.nnz;
+    const int dbucket = n > 0 ? (int)std::lround(2.0 * std::log2((double)n)) : 0;
+    const int nbucket = n > 0 ? (int)std::lround((double)z / (double)n / 16.0) : 0;
+    return arch + "|batch|k" + std::to_string(K) + "|m" + std::to_string(mmax) + "|i" +
+           std::to_string(B.meta.size()) + "|d" + std::to_string(dbucket) + "|n" + std::to_string(nbucket);
+}
+
+bool batch_shape_cached(const std::string &key, BatchState::Shape &out) {
+    std::lock_guard<std::mutex> lk(g_bshape_mutex);
+    auto it = g_bshape_cache.find(key);
+    if (it == g_bshape_cache.end()) return false;
+    out = it->second;
+    return true;
+}
+
+void batch_shape_store(const std::string &key, const BatchState::Shape &sh) {
+    std::lock_guard<std::mutex> lk(g_bshape_mutex);
+    g_bshape_cache[key] = sh;
+}
+
+// Times `iters` iterations of the batched solve for each candidate shape
+// (chunk rows 1024..8192, Rayleigh-Ritz threads 512 or 1024; every candidate
+// starts from the same initial block) and returns the fastest per iteration.
+template <typename F>
+BatchState::Shape tune_batch_shape(const BatchState &B, int iters, F &&time_it) {
+    static const int chunks[] = {1024, 2048, 4096, 8192};
+    static const int threads[] = {512, 1024};
+    BatchState::Shape best;
+    best.ms_per_it = 1e30;
+    for (int ch : chunks) {
+        if (ch > 2 * B.g.ndet / std::max<size_t>(1, B.meta.size()) && ch != chunks[0]) continue;
+        for (int nt : threads) {
+            BatchState::Shape sh;
+            sh.chunk = ch;
+            sh.rr_threads = nt;
+            sh.ms_per_it = time_it(sh, iters);
+            if (env_or("HINQS_VERBOSE", 0))
+                std::fprintf(stderr, "[hinqs] batch shape chunk %d rr_threads %d: %.3f ms per iteration\n", ch, nt,
+                             sh.ms_per_it);
+            if (sh.ms_per_it < best.ms_per_it) best = sh;
+        }
+    }
+    return best;
 }
 
 }  // namespace
@@ -1298,13 +1387,40 @@ int batch_solve(Ctx &c, const hinqs_opts &o, double *energies, double *coeffs, i
             throw Error(HINQS_E_UNSUPPORTED, "instance " + std::to_string(b) +
                                                  " has fewer determinants than the subspace size; solve it alone");
     batch_layout(c, B);
-    switch (K) {
-        case 1: return batch_solve_k<1>(c, B, o, mmax, energies, coeffs, status, iters_out, stats, t0);
-        case 2: return batch_solve_k<2>(c, B, o, mmax, energies, coeffs, status, iters_out, stats, t0);
-        case 4: return batch_solve_k<4>(c, B, o, mmax, energies, coeffs, status, iters_out, stats, t0);
-        case 8: return batch_solve_k<8>(c, B, o, mmax, energies, coeffs, status, iters_out, stats, t0);
-        default: return batch_solve_k<16>(c, B, o, mmax, energies, coeffs, status, iters_out, stats, t0);
+    auto run = [&](const BatchState::Shape &sh, const hinqs_opts &oo, double *e, double *x, int *st_,
+                   int *it_, hinqs_batch_stats *bs, std::chrono::steady_clock::time_point tt) {
+        switch (K) {
+            case 1: return batch_solve_k<1>(c, B, oo, mmax, sh, e, x, st_, it_, bs, tt);
+            case 2: return batch_solve_k<2>(c, B, oo, mmax, sh, e, x, st_, it_, bs, tt);
+            case 4: return batch_solve_k<4>(c, B, oo, mmax, sh, e, x, st_, it_, bs, tt);
+            case 8: return batch_solve_k<8>(c, B, oo, mmax, sh, e, x, st_, it_, bs, tt);
+            default: return batch_solve_k<16>(c, B, oo, mmax, sh, e, x, st_, it_, bs, tt);
+        }
+    };
+    const int ki = K <= 1 ? 0 : K <= 2 ? 1 : K <= 4 ? 2 : K <= 8 ? 3 : 4;
+    const std::string key = batch_shape_key(c, B, K, mmax);
+    double ms_tune = 0.0;
+    if ((o.flags & HINQS_AUTOTUNE) && B.tuned_key[ki] != key) {
+        const auto tt0 = std::chrono::steady_clock::now();
+        if (!batch_shape_cached(key, B.shape[ki])) {
+            B.shape[ki] = tune_batch_shape(B, mmax / K * 2, [&](const BatchState::Shape &sh, int iters) {
+                hinqs_opts oo = o;
+                oo.max_iter = iters;
+                std::vector<double> e(nb);
+                DBuf<double> x;
+                x.ensure((size_t)B.g.ndet);
+                hinqs_batch_stats bs{};
+                (void)run(sh, oo, e.data(), x.p, nullptr, nullptr, &bs, std::chrono::steady_clock::now());
+                return bs.iterations > 0 ? bs.ms_iterations / bs.iterations : 1e30;
+            });
+            batch_shape_store(key, B.shape[ki]);
+        }
+        B.tuned_key[ki] = key;
+        ms_tune = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tt0).count();
     }
+    const int rc = run(B.shape[ki], o, energies, coeffs, status, iters_out, stats, t0);
+    if (stats) stats->ms_tune = ms_tune;
+    return rc;
 }
 
 }  // namespace hinqs

@@ -585,6 +585,11 @@ struct Solver {
     // workspace kept in the context between solves
     DBuf<double> &Vb, &Wb, &T, &Wn, &small, &partial, &nrm;
     Mat V{}, W{}, Tm{}, Wnm{};
+    // Tm / Wnm: where the next new directions and their images are formed.
+    // When they start a column block of V (m a multiple of K, with a block
+    // left), that block of V and of W directly, so nothing is copied after
+    // the product; otherwise the separate T and Wn arrays.
+    bool direct = false;
     DBuf<float> &X32, &S32;
     DBuf<int32_t> &guess_idx;
     DBuf<double> &argv;
@@ -708,14 +713,34 @@ struct Solver {
         evs.clear();
     }
 
+    // Point Tm / Wnm at the place for new columns [m, m + K).
+    void bind_new(int m) {
+        const size_t bsz = (size_t)D * K;
+        direct = m % K == 0 && m / K < nblocks;
+        if (direct) {
+            Tm = Mat{V.p + (size_t)(m / K) * bsz, K, (int64_t)bsz};
+            Wnm = Mat{W.p + (size_t)(m / K) * bsz, K, (int64_t)bsz};
+        } else {
+            Tm = Mat{T.p, K, (int64_t)bsz};
+            Wnm = Mat{Wn.p, K, (int64_t)bsz};
+        }
+    }
+    // After Tm and Wnm hold kept new columns: move them to columns
+    // [m, m + kept) of V and W unless they were formed there.
+    void place_new(int kept, int m) {
+        if (direct && Tm.p == V.p + (size_t)(m / K) * D * K && m % K == 0) return;
+        put_columns(Tm.p, kept, V, m);
+        put_columns(Wnm.p, kept, W, m);
+    }
+
     void put_columns(const double *src, int nc, Mat dst, int c0) {
         const int64_t n = D * K;
         hipLaunchKernelGGL(k_put_columns, dim3(grid_for(n, 256)), dim3(256), 0, s, D, src, K, nc, dst, c0);
         HQ_LAUNCH_CHECK();
     }
 
-    // Wn = H X for a contiguous ndet x K block X (columns >= nc are zero).
-    void apply_h(const double *X, int nc, bool fp32) {
+    // out = H X for a contiguous ndet x K block X (columns >= nc are zero).
+    void apply_h(const double *X, int nc, bool fp32, double *out) {
         hipEvent_t e0, e1;
         HQ_CHECK(hipEventCreate(&e0));
         evs.push_back(e0);
@@ -723,7 +748,7 @@ struct Solver {
         evs.push_back(e1);
         HQ_CHECK(hipEventRecord(e0, s));
         if (!fp32) {
-            sigma_sorted(c, K, X, K, Wn.p, K, HINQS_FP64, s);
+            sigma_sorted(c, K, X, K, out, K, HINQS_FP64, s);
         } else {
             X32.ensure((size_t)D * K);
             S32.ensure((size_t)D * K);
@@ -732,7 +757,7 @@ struct Solver {
             HQ_LAUNCH_CHECK();
             sigma_offdiag_fp32(c, K, X32.p, S32.p, s);
             hipLaunchKernelGGL(k_fp32_finish, dim3(grid_for(n, 256)), dim3(256), 0, s, n, K, S32.p, c.diag.p, X,
-                               Wn.p);
+                               out);
             HQ_LAUNCH_CHECK();
         }
         HQ_CHECK(hipEventRecord(e1, s));
@@ -865,7 +890,7 @@ template <int KK>
 void launch_ritz(Solver &S, int m, const double *Yd, const double *thd, double floor_, int nroots,
                  unsigned grid) {
     hipLaunchKernelGGL(k_ritz<KK>, dim3(grid), dim3(256), 0, S.s, S.D, m, S.V, S.W, Yd, thd, S.c.diag.p,
-                       floor_, nroots, S.T.p, S.partial.p);
+                       floor_, nroots, S.Tm.p, S.partial.p);
     HQ_LAUNCH_CHECK();
 }
 
@@ -897,34 +922,34 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
     const bool verbose = vb && vb[0] && vb[0] != '0';
 
     // ---- initial block: warm start + lowest-diagonal unit vectors
+    S.bind_new(0);  // formed in place as the first column block of V
     S.guess_idx.ensure(K + 1);
     const int nunit = guess ? kroots - 1 : kroots;
     S.lowest_diag_indices(nunit, S.guess_idx.p);
     int n0 = 0;
     if (guess) {
         if (sorted) {
-            hipLaunchKernelGGL(k_copy_column, dim3(grid_for(D, 256)), dim3(256), 0, s, D, guess, S.T.p, K, 0);
+            hipLaunchKernelGGL(k_copy_column, dim3(grid_for(D, 256)), dim3(256), 0, s, D, guess, S.Tm.p, K, 0);
             HQ_LAUNCH_CHECK();
         } else {
             DBuf<double> tmp;
             tmp.ensure(D);
             gather_rows(s, guess, tmp.p, c.perm.p, D, 8);
-            hipLaunchKernelGGL(k_copy_column, dim3(grid_for(D, 256)), dim3(256), 0, s, D, tmp.p, S.T.p, K, 0);
+            hipLaunchKernelGGL(k_copy_column, dim3(grid_for(D, 256)), dim3(256), 0, s, D, tmp.p, S.Tm.p, K, 0);
             HQ_LAUNCH_CHECK();
             HQ_CHECK(hipStreamSynchronize(s));
         }
         n0 = 1;
     }
     if (nunit > 0) {
-        hipLaunchKernelGGL(k_unit_columns, dim3(grid_for(D, 256)), dim3(256), 0, s, D, S.T.p, K, n0, nunit,
+        hipLaunchKernelGGL(k_unit_columns, dim3(grid_for(D, 256)), dim3(256), 0, s, D, S.Tm.p, K, n0, nunit,
                            S.guess_idx.p);
         HQ_LAUNCH_CHECK();
     }
     int m = S.orthonormalize(0, n0 + nunit, nullptr);
     if (m == 0) throw Error(HINQS_E_INVALID_ARG, "initial guess is zero");
-    S.apply_h(S.T.p, m, fp32);
-    S.put_columns(S.T.p, m, S.V, 0);
-    S.put_columns(S.Wn.p, m, S.W, 0);
+    S.apply_h(S.Tm.p, m, fp32, S.Wnm.p);
+    S.place_new(m, 0);
 
     std::vector<double> G((size_t)96 * 96, 0.0);  // host copy, leading dimension 96
     // G[0:mrows, c0:c0+nc] = V[:, 0:mrows]^T B with B holding those nc columns
@@ -994,7 +1019,8 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
         }
         y0.assign(m, 0.0);
         for (int a = 0; a < m; ++a) y0[a] = Z[(size_t)a * m + 0];
-        // ---- residuals + preconditioned corrections (T)
+        // ---- residuals + preconditioned corrections (T, formed where V's new columns go)
+        S.bind_new(m);
         double *Yd = S.scratch_a();
         double *thd = S.scratch_a() + 96 * 16;
         S.upload_small(Y, Yd);
@@ -1049,8 +1075,7 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
             m = q;
             fp32 = false;
             // V's first block now holds the q basis vectors (q <= K)
-            S.apply_h(S.V.p, q, false);
-            S.put_columns(S.Wn.p, q, S.W, 0);
+            S.apply_h(S.V.p, q, false, S.W.p);  // V's and W's first blocks
             load_g_all(m);
             ++restarts;
             Yprev.clear();
@@ -1110,9 +1135,8 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
             if (it_fp32 > 0) --it_fp32;
             continue;
         }
-        S.apply_h(S.T.p, kept, fp32);
-        S.put_columns(S.T.p, kept, S.V, m);
-        S.put_columns(S.Wn.p, kept, S.W, m);
+        S.apply_h(S.Tm.p, kept, fp32, S.Wnm.p);
+        S.place_new(kept, m);
         load_g_cols(m, kept, m + kept, S.Wnm);
         Yprev.swap(Ycur);
         mprev = m;

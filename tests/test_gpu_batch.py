@@ -71,6 +71,44 @@ def test_batch_matches_sequential(instances, block, max_space):
         assert ci[np.argmax(np.abs(ci))] > 0
 
 
+@pytest.fixture(scope="module")
+def sequential_k8(instances):
+    return _sequential(instances, 8, 1e-9)
+
+
+@pytest.mark.parametrize("chunk,rr_threads", [(1024, 512), (1024, 1024), (2048, 512), (2048, 1024),
+                                              (4096, 512), (4096, 1024), (8192, 512), (8192, 1024),
+                                              (2048, 256)])
+def test_every_batch_shape(instances, sequential_k8, chunk, rr_threads, monkeypatch):
+    """Each launch shape the batch tuner can choose (chunk rows of the tall-skinny
+    kernels, Rayleigh-Ritz threads) gives the sequential solves' eigenpairs."""
+    monkeypatch.setenv("HINQS_BATCH_CHUNK", str(chunk))
+    monkeypatch.setenv("HINQS_BATCH_RR_THREADS", str(rr_threads))
+    log(f"batch shape chunk={chunk} rr_threads={rr_threads}")
+    s = _batch(instances)
+    e, c, info = s.batch_lowest_eigenpair(tol=1e-9)
+    st = info["stats"]
+    assert info["converged"] and st["chunk_rows"] == chunk and st["rr_threads"] == rr_threads
+    c = c.cpu().numpy()
+    off = info["offsets"]
+    for i, (es, cs, _) in enumerate(sequential_k8):
+        assert abs(e[i] - es) <= 1e-10, (i, e[i], es)
+        assert abs(float(c[off[i]:off[i + 1]] @ cs)) >= 1.0 - 1e-10, i
+
+
+def test_batch_autotune_picks_and_caches_a_shape(instances, sequential_k8):
+    s = _batch(instances)
+    e1, _, i1 = s.batch_lowest_eigenpair(tol=1e-9, autotune=True)
+    e2, _, i2 = s.batch_lowest_eigenpair(tol=1e-9, autotune=True)
+    st1, st2 = i1["stats"], i2["stats"]
+    log(f"tuned shape chunk={st1['chunk_rows']} rr_threads={st1['rr_threads']} in {st1['ms_tune']:.1f} ms")
+    assert st1["ms_tune"] > 0.0 and st2["ms_tune"] == 0.0   # the second call reuses the choice
+    assert st1["chunk_rows"] in (1024, 2048, 4096, 8192) and st1["rr_threads"] in (512, 1024)
+    assert (st2["chunk_rows"], st2["rr_threads"]) == (st1["chunk_rows"], st1["rr_threads"])
+    for i, (es, _, _) in enumerate(sequential_k8):
+        assert abs(e1[i] - es) <= 1e-10 and abs(e2[i] - es) <= 1e-10
+
+
 def test_batch_matches_oracle_dense(instances):
     small = [x for x in instances if len(x[1]) <= 4000]
     log(f"batch vs oracle dense, {len(small)} instances")
