@@ -76,6 +76,38 @@ def test_couplings_ragged_small_sets():
         _check_couplings(ints, a, b, na, nb, np.arange(len(a)))
 
 
+def test_couplings_lookup_path_forced(monkeypatch):
+    """The alpha+beta lookup (binary search of each beta string one move away)
+    in every group, however short: bit-exact on every row of the 20k set and
+    of ragged small sets."""
+    monkeypatch.setenv("HINQS_CONNECT_LOOKUP_MIN", "0")
+    ints, a, b, cfg = W.config_inputs(1)
+    log("couplings cas10 20000 dets, lookup path in every group")
+    _check_couplings(ints, a, b, cfg.na, cfg.nb, np.arange(len(a)))
+    for seed, (norb, na, nb, n) in enumerate([(5, 2, 2, 3), (7, 3, 1, 17), (8, 4, 4, 257), (6, 6, 1, 6)]):
+        ints = W.gen_integrals(norb, norb, -2, -0.5, 300 + seed)
+        a, b = W.sample_determinants(norb, na, nb, n, 0.5, 0.3, 400 + seed)
+        _check_couplings(ints, a, b, na, nb, np.arange(len(a)))
+
+
+@pytest.mark.parametrize("path", ["lookup", "scan"])
+def test_couplings_dense_product_space(path, monkeypatch):
+    """A product space with long alpha groups (norb 13: every one-electron alpha
+    string times every 6-electron beta string, 22,308 determinants, 1,716 rows
+    per group); couplings bit-exact and FP64 sigma at the row bar on 1,000
+    sampled rows, with the alpha+beta partners looked up by binary search and
+    with the scan."""
+    monkeypatch.setenv("HINQS_CONNECT_LOOKUP_MIN", "0" if path == "lookup" else str(1 << 30))
+    norb, na, nb = 13, 1, 6
+    ints = W.gen_integrals(norb, 8, -2.5, -0.5, 913)
+    a, b = _subset_product(list(range(norb)), na, nb)
+    log(f"couplings dense product space norb={norb} n={len(a)} ({path})")
+    rows = np.random.default_rng(77).choice(len(a), 1000, replace=False)
+    s, o = _check_couplings(ints, a, b, na, nb, rows)
+    X = W.random_block(len(a), 4, 78)
+    _check_sigma(s, o, X, rows, 1e-12)
+
+
 def test_couplings_1m_sampled_rows():
     ints, a, b, cfg = W.config_inputs(2)
     rows = np.random.default_rng(7).choice(len(a), 1000, replace=False)
