@@ -1064,18 +1064,28 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
                 do_switch = true;
         }
         if (do_switch) {
-            // basis := current Ritz vectors; images recomputed with FP64 products
+            // basis := current and previous Ritz vectors (as at a GD+k restart,
+            // so the FP64 phase keeps the last step's direction); images
+            // recomputed with FP64 products, one block product per K columns
+            const int nprev = (mprev > 0 && !Yprev.empty()) ? nroots_eff : 0;
+            const int qq = nroots_eff + nprev;
+            std::vector<double> M((size_t)m * qq, 0.0);
+            for (int a = 0; a < m; ++a) {
+                for (int r = 0; r < nroots_eff; ++r) M[(size_t)a * qq + r] = Y[(size_t)a * K + r];
+                if (a < mprev)
+                    for (int r = 0; r < nprev; ++r)
+                        M[(size_t)a * qq + nroots_eff + r] = Yprev[(size_t)a * nroots_eff + r];
+            }
             int q = 0;
-            std::vector<double> Yc((size_t)m * nroots_eff);
-            for (int a = 0; a < m; ++a)
-                for (int r = 0; r < nroots_eff; ++r) Yc[(size_t)a * nroots_eff + r] = Y[(size_t)a * K + r];
-            std::vector<double> Q = small_orth(m, nroots_eff, Yc, 1e-8, q);
+            std::vector<double> Q = small_orth(m, qq, M, 1e-8, q);
             S.upload_small(Q, S.scratch_b());
             S.tsmm(S.V, m, S.scratch_b(), q, 1.0, 0.0, S.V);
             m = q;
             fp32 = false;
-            // V's first block now holds the q basis vectors (q <= K)
-            S.apply_h(S.V.p, q, false, S.W.p);  // V's and W's first blocks
+            // V's first column blocks now hold the q <= 2K basis vectors
+            const size_t bsz = (size_t)D * K;
+            for (int b0 = 0; b0 < q; b0 += K)
+                S.apply_h(S.V.p + (size_t)(b0 / K) * bsz, std::min(K, q - b0), false, S.W.p + (size_t)(b0 / K) * bsz);
             load_g_all(m);
             ++restarts;
             Yprev.clear();
