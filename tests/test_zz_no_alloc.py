@@ -103,3 +103,38 @@ def test_noalloc_rejects_staging_beyond_the_array():
     # sorted order needs no staging, whatever the size
     S = _call(s, A, X, True)
     assert torch.equal(S, s.sigma(X, sorted_order=True))
+
+
+@pytest.mark.parametrize("k,sorted_order", [(3, False), (8, True)])
+def test_noalloc_sigma_replays_in_a_captured_graph(k, sorted_order):
+    """The entry point's purpose: issued under HIP graph capture (it allocates,
+    clears with memset and synchronizes nothing).  The graph is replayed
+    several times with new inputs written eagerly in between, and every replay
+    must equal the eager hinqs_sigma."""
+    ints, a, b, cfg = W.config_inputs(1)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        s = hq.Hinqs(stream=side)
+        s.set_integrals(ints.h, ints.eri, ints.e_core)
+        s.set_determinants(a, b, cfg.na, cfg.nb)
+        X = torch.empty(s.ndet, k, dtype=torch.float64, device="cuda")
+        out = torch.empty_like(X)
+        X.normal_()
+        s.sigma_noalloc(X, out, sorted_order=sorted_order)  # eager warm-up
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        s.sigma_noalloc(X, out, sorted_order=sorted_order)
+    torch.cuda.synchronize()
+    gen = torch.Generator(device="cuda")
+    for r in range(4):
+        gen.manual_seed(100 + r)
+        X.normal_(generator=gen)
+        out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        ref = s.sigma(X, sorted_order=sorted_order)
+        torch.cuda.synchronize()
+        log(f"  replay {r}: k={k} sorted={sorted_order}")
+        assert torch.equal(out, ref), r
