@@ -13,6 +13,8 @@
 //   Rayleigh-Ritz on G = V^T W         host Householder + implicit QL (cyclic
 //                                      Jacobi if QL does not converge), m <= 96
 //   T = (W y - theta V y) / (theta - H_ii)   fused Ritz/residual/preconditioner
+//                                      (V y, W y on FP64 MFMA, like every
+//                                      tall-skinny product of the solver)
 //   classical Gram-Schmidt of T against V (a second pass only when the first
 //   removed most of a column), then symmetric orthonormalization of T
 //   (eigendecomposition of T^T T; nearly dependent directions dropped)
@@ -36,7 +38,6 @@
 #include <numeric>
 
 #include "common.hpp"
-#include "dense.hpp"
 
 namespace hinqs {
 
@@ -122,35 +123,86 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restric
 }
 
 // Fused Ritz vector, residual, norm and diagonal preconditioner for the
-// first nroots of KB roots (ritz_row):
+// first nroots of KB roots:
 //   r_c = W y_c - theta_c V y_c,   T[:, c] = r_c / clamp(theta_c - H_ii)
-// partial[blk][c] = sum over the block's rows of r_c^2 and
-// partial[blk][KB + c] the same for T[:, c]^2.
-template <int KB>
+// (T[:, c] = 0 for c >= nroots).  V Y and W Y run on FP64 MFMA with the
+// operand layout of k_tsmm (16-row tiles, Y held in registers, m <= 4 STEPS);
+// the elementwise part works on the accumulators, whose element r of lane l is
+// row r0 + l/16 + 4r, column l%16.  partial[blk][c] = sum over the block's
+// rows of r_c^2 and partial[blk][KB + c] the same for T[:, c]^2.
+template <int KB, int STEPS>
 __global__ __launch_bounds__(256) void k_ritz(int64_t nrows, int m, Mat V, Mat W, const double *__restrict__ Y,
                                               const double *__restrict__ theta, const double *__restrict__ diag,
                                               double floor_, int nroots, double *__restrict__ T,
                                               double *__restrict__ partial) {
-    using L = RowLanes<KB>;
-    constexpr int RPB = 256 / L::LPN;
-    __shared__ double sY[96 * KB];
-    __shared__ double sTh[KB];
-    __shared__ double red[512];
-    const int nbk = (m + KB - 1) / KB;
-    for (int t = threadIdx.x; t < nbk * KB * KB; t += 256) sY[t] = t < m * KB ? Y[t] : 0.0;
-    if (threadIdx.x < KB) sTh[threadIdx.x] = theta[threadIdx.x];
-    __syncthreads();
-    const int g = threadIdx.x / L::LPN, q = threadIdx.x % L::LPN;
-    double rn2[L::EPL], tn2[L::EPL];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kk = lane >> 4;
+    double yv[STEPS];
 #pragma unroll
-    for (int e = 0; e < L::EPL; ++e) rn2[e] = tn2[e] = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * RPB + g; i < nrows; i += (int64_t)gridDim.x * RPB)
-        ritz_row<KB>(i, m, V, W, sY, sTh, diag[i], floor_, nroots, T, q, rn2, tn2);
-    double rs, ts;
-    ritz_block_sums<KB>(rn2, tn2, red, rs, ts);
-    if (threadIdx.x < KB) {
-        partial[(int64_t)blockIdx.x * 2 * KB + threadIdx.x] = rs;
-        partial[(int64_t)blockIdx.x * 2 * KB + KB + threadIdx.x] = ts;
+    for (int s = 0; s < STEPS; ++s) {
+        const int j = 4 * s + kk;
+        yv[s] = (j < m && col < KB) ? Y[j * KB + col] : 0.0;
+    }
+    const bool live = col < nroots;
+    const double th = col < KB ? theta[col] : 0.0;
+    const int nsteps = (m + 3) / 4;
+    const int64_t ntiles = (nrows + 15) / 16;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    double rn2 = 0.0, tn2 = 0.0;
+    for (int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; tile < ntiles; tile += nwaves) {
+        const int64_t r0 = tile * 16, ra = r0 + col;
+        const bool rok = ra < nrows;
+        dbl4 ax = dbl4{0.0, 0.0, 0.0, 0.0}, aw = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s0 = 0; s0 < STEPS; s0 += 4) {
+            if (s0 >= nsteps) break;
+            double xv[4], wv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = 4 * (s0 + u) + kk;
+                const bool ok = rok && j < m;
+                xv[u] = ok ? *V.at(ra, j) : 0.0;
+                wv[u] = ok ? *W.at(ra, j) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ax = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[u], yv[s0 + u], ax, 0, 0, 0);
+                aw = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[u], yv[s0 + u], aw, 0, 0, 0);
+            }
+        }
+        if (col < KB) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = r0 + kk + 4 * r;
+                if (row >= nrows) continue;
+                double t = 0.0;
+                if (live) {
+                    const double res = aw[r] - th * ax[r];
+                    double den = th - diag[row];
+                    if (fabs(den) < floor_) den = den < 0.0 ? -floor_ : floor_;
+                    t = res / den;
+                    rn2 += res * res;
+                    tn2 += t * t;
+                }
+                T[row * KB + col] = t;
+            }
+        }
+    }
+    // block sums per column: the lanes of column c are c, c + 16, c + 32, c + 48 in every wave
+    __shared__ double red[2][4][64];
+    red[0][wave][lane] = rn2;
+    red[1][wave][lane] = tn2;
+    __syncthreads();
+    if ((int)threadIdx.x < KB) {
+        const int c = threadIdx.x;
+        double rs = 0.0, ts = 0.0;
+        for (int w = 0; w < 4; ++w)
+            for (int q = 0; q < 4; ++q) {
+                rs += red[0][w][c + 16 * q];
+                ts += red[1][w][c + 16 * q];
+            }
+        partial[(int64_t)blockIdx.x * 2 * KB + c] = rs;
+        partial[(int64_t)blockIdx.x * 2 * KB + KB + c] = ts;
     }
 }
 
@@ -174,25 +226,62 @@ __global__ void k_proj_gate(const double *__restrict__ C, int m, int nc, const d
     }
 }
 
-// Out(i, c) = beta * Out(i, c) + alpha * sum_{j<m} A(i, j) B[j][c] (tsmm_row),
-// c < nc <= NC, m <= 96, A.kb == KB; B is m x nc row-major.  Out may alias A.
-template <int KB, int NC>
+// Out(i, c) = beta Out(i, c) + alpha sum_{j<m} A(i, j) B[j][c] for c < nc <= 16 NT, m <= 4 STEPS,
+// with FP64 MFMA (16x16x4): each wave takes 16-row tiles in turn; for k-step s lane l supplies
+// A(r0 + l%16, 4s + l/16), holds B[4s + l/16][16t + l%16] for every step in registers, and
+// receives rows r0 + l/16 + 4r of output column 16t + l%16.  A tile's rows are all read before
+// any is written, so Out may alias A.  B is m x nc row-major.
+template <int NT, int STEPS>
 __global__ __launch_bounds__(256) void k_tsmm(int64_t nrows, int m, Mat A, const double *__restrict__ B, int nc,
-                                              double alpha, double beta, Mat Out,
-                                              const int *__restrict__ gate) {
+                                              double alpha, double beta, Mat Out, const int *__restrict__ gate) {
     if (gate && *gate == 0) return;
-    using L = RowLanes<KB>;
-    constexpr int RPB = 256 / L::LPN;
-    __shared__ double sB[96 * NC];
-    const int nbk = (m + KB - 1) / KB;
-    for (int t = threadIdx.x; t < nbk * KB * NC; t += 256) {
-        const int j = t / NC, cc = t % NC;
-        sB[t] = (j < m && cc < nc) ? B[j * nc + cc] : 0.0;
+    const int lane = threadIdx.x & 63;
+    const int col = lane & 15, kk = lane >> 4;
+    double bv[STEPS][NT];
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int j = 4 * s + kk, c = 16 * t + col;
+            bv[s][t] = (j < m && c < nc) ? B[j * nc + c] : 0.0;
+        }
+    const int nsteps = (m + 3) / 4;
+    const int64_t ntiles = (nrows + 15) / 16;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; tile < ntiles; tile += nwaves) {
+        const int64_t r0 = tile * 16, ra = r0 + col;
+        const bool rok = ra < nrows;
+        dbl4 acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s0 = 0; s0 < STEPS; s0 += 4) {
+            if (s0 >= nsteps) break;
+            double av[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = 4 * (s0 + u) + kk;
+                av[u] = (rok && j < m) ? *A.at(ra, j) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[s0 + u][t], acc[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = 16 * t + col;
+            if (c >= nc) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = r0 + kk + 4 * r;
+                if (row >= nrows) continue;
+                double *o = Out.at(row, c);
+                *o = (beta == 0.0 ? 0.0 : beta * *o) + alpha * acc[t][r];
+            }
+        }
     }
-    __syncthreads();
-    const int g = threadIdx.x / L::LPN, q = threadIdx.x % L::LPN;
-    for (int64_t i = (int64_t)blockIdx.x * RPB + g; i < nrows; i += (int64_t)gridDim.x * RPB)
-        tsmm_row<KB, NC>(i, m, A, sB, nc, alpha, beta, Out, q);
 }
 
 // dst(i, c0 + c) = src[i * K + c] for c < nc.
@@ -622,7 +711,7 @@ struct Solver {
         Wnm = Mat{Wn.p, K, (int64_t)bsz};
         small.ensure(96 * 96 * 2 + 4096);
         nblk_gram = gram_blocks_for(D);
-        partial.ensure(std::max<size_t>((size_t)nblk_gram * 96 * 16, 2048 * 16) + 4096);
+        partial.ensure(std::max<size_t>((size_t)nblk_gram * 96 * 16, 2048 * 2 * 16) + 4096);  // gram / k_ritz partials
         nrm.ensure(64);
         HQ_CHECK(hipMemsetAsync(Vb.p, 0, sizeof(double) * bsz * nblocks, s));
         HQ_CHECK(hipMemsetAsync(Wb.p, 0, sizeof(double) * bsz * nblocks, s));
@@ -664,27 +753,15 @@ struct Solver {
         if (nc > 32) throw Error(HINQS_E_UNSUPPORTED, "tsmm width");
         if (m > 96) throw Error(HINQS_E_UNSUPPORTED, "tsmm depth");
         if (A.kb != K) throw Error(HINQS_E_UNSUPPORTED, "tsmm column block");
-        switch (K) {
-            case 1: tsmm_k<1>(A, m, Bs, nc, alpha, beta, Out, gate); break;
-            case 2: tsmm_k<2>(A, m, Bs, nc, alpha, beta, Out, gate); break;
-            case 4: tsmm_k<4>(A, m, Bs, nc, alpha, beta, Out, gate); break;
-            case 8: tsmm_k<8>(A, m, Bs, nc, alpha, beta, Out, gate); break;
-            default: tsmm_k<16>(A, m, Bs, nc, alpha, beta, Out, gate); break;
-        }
-    }
-    template <int KB>
-    void tsmm_k(Mat A, int m, const double *Bs, int nc, double alpha, double beta, Mat Out, const int *gate) {
-        constexpr int RPB = 256 / RowLanes<KB>::LPN;
-        const unsigned grid = (unsigned)std::min<int64_t>((D + RPB - 1) / RPB, 2048);
-        const int NC = nc <= 1 ? 1 : nc <= 2 ? 2 : nc <= 4 ? 4 : nc <= 8 ? 8 : nc <= 16 ? 16 : 32;
+        const int64_t ntiles = (D + 15) / 16;
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((ntiles + 3) / 4, 2048));
         dim3 g(grid), b(256);
-        switch (NC) {
-            case 1: hipLaunchKernelGGL((k_tsmm<KB, 1>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate); break;
-            case 2: hipLaunchKernelGGL((k_tsmm<KB, 2>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate); break;
-            case 4: hipLaunchKernelGGL((k_tsmm<KB, 4>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate); break;
-            case 8: hipLaunchKernelGGL((k_tsmm<KB, 8>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate); break;
-            case 16: hipLaunchKernelGGL((k_tsmm<KB, 16>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate); break;
-            default: hipLaunchKernelGGL((k_tsmm<KB, 32>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate); break;
+        if (nc <= 16) {
+            if (m <= 48) hipLaunchKernelGGL((k_tsmm<1, 12>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate);
+            else hipLaunchKernelGGL((k_tsmm<1, 24>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate);
+        } else {
+            if (m <= 48) hipLaunchKernelGGL((k_tsmm<2, 12>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate);
+            else hipLaunchKernelGGL((k_tsmm<2, 24>), g, b, 0, s, D, m, A, Bs, nc, alpha, beta, Out, gate);
         }
         HQ_LAUNCH_CHECK();
     }
@@ -889,8 +966,12 @@ struct Solver {
 template <int KK>
 void launch_ritz(Solver &S, int m, const double *Yd, const double *thd, double floor_, int nroots,
                  unsigned grid) {
-    hipLaunchKernelGGL(k_ritz<KK>, dim3(grid), dim3(256), 0, S.s, S.D, m, S.V, S.W, Yd, thd, S.c.diag.p,
-                       floor_, nroots, S.Tm.p, S.partial.p);
+    if (m <= 48)
+        hipLaunchKernelGGL((k_ritz<KK, 12>), dim3(grid), dim3(256), 0, S.s, S.D, m, S.V, S.W, Yd, thd, S.c.diag.p,
+                           floor_, nroots, S.Tm.p, S.partial.p);
+    else
+        hipLaunchKernelGGL((k_ritz<KK, 24>), dim3(grid), dim3(256), 0, S.s, S.D, m, S.V, S.W, Yd, thd, S.c.diag.p,
+                           floor_, nroots, S.Tm.p, S.partial.p);
     HQ_LAUNCH_CHECK();
 }
 
@@ -1025,7 +1106,7 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
         double *thd = S.scratch_a() + 96 * 16;
         S.upload_small(Y, Yd);
         S.upload_small(theta, thd);
-        const unsigned grid = (unsigned)std::min<int64_t>(grid_for(D, 256 / K), 2048);
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(((D + 15) / 16 + 3) / 4, 2048));
         switch (K) {
             case 1: launch_ritz<1>(S, m, Yd, thd, o.precond_floor, nroots_eff, grid); break;
             case 2: launch_ritz<2>(S, m, Yd, thd, o.precond_floor, nroots_eff, grid); break;
