@@ -105,6 +105,16 @@ struct DBuf {
     operator T *() const { return p; }
 };
 
+// Waits for the stream by polling it: the solver's loop waits for a few small
+// results each iteration, and a blocking wait adds the wake-up latency of the
+// sleeping host thread to every one of those round trips.
+inline void wait_stream(hipStream_t s) {
+    hipError_t e;
+    while ((e = hipStreamQuery(s)) == hipErrorNotReady) {
+    }
+    if (e != hipSuccess) throw Error(HINQS_E_HIP, std::string("stream wait: ") + hipGetErrorString(e));
+}
+
 // Installs an allocator for the current thread until the end of the scope.
 struct AllocScope {
     const Allocator *prev;
@@ -362,11 +372,13 @@ struct Ctx {
         DBuf<int32_t> guess_idx;
         DBuf<int64_t> argi;
         double *pinned = nullptr;  // host staging ring (hipHostMalloc)
+        double *pinned_dl = nullptr;  // host landing area of small device results
         DavidsonWork() = default;
         DavidsonWork(const DavidsonWork &) = delete;
         DavidsonWork &operator=(const DavidsonWork &) = delete;
         ~DavidsonWork() {
             if (pinned) (void)hipHostFree(pinned);
+            if (pinned_dl) (void)hipHostFree(pinned_dl);
         }
     } dw;
 

@@ -692,6 +692,7 @@ struct Solver {
     static constexpr int SLOTS = 16;
     static constexpr size_t SLOT_DOUBLES = 96 * 96;
     double *pinned = nullptr;
+    double *pinned_dl = nullptr;  // small downloads land here (pinned, so the copy is asynchronous)
     int upload_count = 0;
 
     Solver(Ctx &cc, int k, int m_max)
@@ -721,6 +722,9 @@ struct Solver {
             HQ_CHECK(hipHostMalloc((void **)&c.dw.pinned, sizeof(double) * SLOTS * SLOT_DOUBLES,
                                    hipHostMallocDefault));
         pinned = c.dw.pinned;
+        if (!c.dw.pinned_dl)
+            HQ_CHECK(hipHostMalloc((void **)&c.dw.pinned_dl, sizeof(double) * SLOT_DOUBLES, hipHostMallocDefault));
+        pinned_dl = c.dw.pinned_dl;
     }
     ~Solver() {
         (void)hipStreamSynchronize(s);  // the staging ring is free for the next solve
@@ -739,10 +743,16 @@ struct Solver {
 
     std::vector<double> gram_host(Mat A, int ma, Mat B, int nb) {
         gram(A, ma, B, nb, scratch_a());
-        std::vector<double> h((size_t)ma * nb);
-        HQ_CHECK(hipMemcpyAsync(h.data(), scratch_a(), sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
-        HQ_CHECK(hipStreamSynchronize(s));
-        return h;
+        return download(scratch_a(), (size_t)ma * nb);
+    }
+
+    // n doubles of device memory to the host (through the pinned landing area;
+    // the wait polls the stream)
+    std::vector<double> download(const double *src, size_t n) {
+        if (n > SLOT_DOUBLES) throw Error(HINQS_E_UNSUPPORTED, "small download too large");
+        HQ_CHECK(hipMemcpyAsync(pinned_dl, src, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        wait_stream(s);
+        return std::vector<double>(pinned_dl, pinned_dl + n);
     }
 
     // Out[:, 0:nc] = beta Out + alpha A[:, 0:m] Bs (m x nc row-major, device);
@@ -771,7 +781,7 @@ struct Solver {
     // uploads, and every SLOTS-th upload waits for the stream first.
     void upload_small(const std::vector<double> &h, double *dst) {
         if (h.size() > SLOT_DOUBLES) throw Error(HINQS_E_UNSUPPORTED, "small upload too large");
-        if (++upload_count % SLOTS == 0) HQ_CHECK(hipStreamSynchronize(s));
+        if (++upload_count % SLOTS == 0) wait_stream(s);
         double *slot = pinned + (size_t)(upload_count % SLOTS) * SLOT_DOUBLES;
         std::copy(h.begin(), h.end(), slot);
         HQ_CHECK(hipMemcpyAsync(dst, slot, sizeof(double) * h.size(), hipMemcpyHostToDevice, s));
@@ -1117,9 +1127,7 @@ int davidson(Ctx &c, const hinqs_opts &o, const double *guess, double *energy, d
         hipLaunchKernelGGL(k_reduce_partials, dim3(2 * K), dim3(256), 0, s, S.partial.p, (int)grid, 2 * K,
                            S.nrm.p, (const int *)nullptr);
         HQ_LAUNCH_CHECK();
-        std::vector<double> rt(2 * K);
-        HQ_CHECK(hipMemcpyAsync(rt.data(), S.nrm.p, sizeof(double) * 2 * K, hipMemcpyDeviceToHost, s));
-        HQ_CHECK(hipStreamSynchronize(s));
+        std::vector<double> rt = S.download(S.nrm.p, 2 * K);
         std::vector<double> rn(rt.begin(), rt.begin() + K), tn2(rt.begin() + K, rt.end());
         for (double &x : rn) x = std::sqrt(std::max(0.0, x));
         res0 = rn[0];
