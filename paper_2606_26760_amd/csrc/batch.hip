@@ -36,7 +36,6 @@
 #include <vector>
 
 #include "common.hpp"
-#include "dense.hpp"
 
 namespace hinqs {
 
@@ -281,55 +280,134 @@ __global__ __launch_bounds__(256) void k_bgram(const Chunk *__restrict__ chunks,
 }
 
 // Out(i, c) = beta Out(i, c) + alpha sum_{j<m} A(i, j) B_inst[j][c] for the
-// rows of each chunk (tsmm_row), with B_inst = Bs + inst * bstride (leading
-// dimension ldb) and A.kb == KB.  Out may alias A.
-template <int KB, int NC>
+// rows of each chunk, with B_inst = Bs + inst * bstride (leading dimension
+// ldb), c < nc <= 16 NT, m <= 4 STEPS.  FP64 MFMA (16x16x4) on 16-row tiles of
+// the chunk, the four waves taking every fourth tile: for k-step s lane l
+// supplies A(r0 + l%16, 4s + l/16), holds B_inst[4s + l/16][16t + l%16] in
+// registers and receives rows r0 + l/16 + 4r of column 16t + l%16.  A tile's
+// rows are all read before any is written, so Out may alias A.
+template <int NT, int STEPS>
 __global__ __launch_bounds__(256) void k_btsmm(const Chunk *__restrict__ chunks, const int32_t *__restrict__ done,
                                                int m, Mat A, const double *__restrict__ Bs, int bstride, int ldb,
                                                int nc, double alpha, double beta, Mat Out) {
     const Chunk ch = chunks[blockIdx.x];
     if (done[ch.inst]) return;
-    using L = RowLanes<KB>;
-    constexpr int RPB = 256 / L::LPN;
-    __shared__ double sB[MS * NC];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kk = lane >> 4;
     const double *B = Bs + (int64_t)ch.inst * bstride;
-    const int nbk = (m + KB - 1) / KB;
-    for (int t = threadIdx.x; t < nbk * KB * NC; t += 256) {
-        const int j = t / NC, cc = t % NC;
-        sB[t] = (j < m && cc < nc) ? B[j * ldb + cc] : 0.0;
-    }
-    __syncthreads();
-    const int g = threadIdx.x / L::LPN, q = threadIdx.x % L::LPN;
+    double bv[STEPS][NT];
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int j = 4 * s + kk, c = 16 * t + col;
+            bv[s][t] = (j < m && c < nc) ? B[j * ldb + c] : 0.0;
+        }
+    const int nsteps = (m + 3) / 4;
     const int64_t end = ch.r0 + ch.n;
-    for (int64_t i = ch.r0 + g; i < end; i += RPB) tsmm_row<KB, NC>(i, m, A, sB, nc, alpha, beta, Out, q);
+    for (int64_t r0 = ch.r0 + 16 * wave; r0 < end; r0 += 64) {
+        const int64_t ra = r0 + col;
+        const bool rok = ra < end;
+        dbl4 acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s0 = 0; s0 < STEPS; s0 += 4) {
+            if (s0 >= nsteps) break;
+            double av[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = 4 * (s0 + u) + kk;
+                av[u] = (rok && j < m) ? *A.at(ra, j) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[s0 + u][t], acc[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = 16 * t + col;
+            if (c >= nc) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = r0 + kk + 4 * r;
+                if (row >= end) continue;
+                double *o = Out.at(row, c);
+                *o = (beta == 0.0 ? 0.0 : beta * *o) + alpha * acc[t][r];
+            }
+        }
+    }
 }
 
-// Ritz vectors, residuals and preconditioned corrections of every root
-// (ritz_row), with per-chunk partial sums of r_c^2.
-template <int KK>
+// Ritz vectors, residuals and preconditioned corrections of every root of
+// each chunk's instance, with per-chunk partial sums of r_c^2:
+//   r_c = W y_c - theta_c V y_c,  T[:, c] = r_c / clamp(theta_c - H_ii),
+// V y and W y on FP64 MFMA with the tile layout of k_btsmm (m <= 4 STEPS).
+template <int KK, int STEPS>
 __global__ __launch_bounds__(256) void k_britz(const Chunk *__restrict__ chunks, BDev st, int m, Mat V, Mat W,
                                                const double *__restrict__ diag, double floor_,
                                                double *__restrict__ T, double *__restrict__ rpart) {
     const Chunk ch = chunks[blockIdx.x];
     if (st.done[ch.inst]) return;
-    using L = RowLanes<KK>;
-    constexpr int RPB = 256 / L::LPN;
-    __shared__ double sY[MS * KK];
-    __shared__ double sTh[KK];
-    __shared__ double red[512];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kk = lane >> 4;
     const double *Yb = st.Y + (int64_t)ch.inst * MS * KB;
-    for (int t = threadIdx.x; t < m * KK; t += 256) sY[t] = Yb[(t / KK) * KB + t % KK];
-    if (threadIdx.x < KK) sTh[threadIdx.x] = st.theta[ch.inst * KB + threadIdx.x];
-    __syncthreads();
-    const int g = threadIdx.x / L::LPN, q = threadIdx.x % L::LPN;
-    double rn2[L::EPL], tn2[L::EPL];
+    double yv[STEPS];
 #pragma unroll
-    for (int e = 0; e < L::EPL; ++e) rn2[e] = tn2[e] = 0.0;
+    for (int s = 0; s < STEPS; ++s) {
+        const int j = 4 * s + kk;
+        yv[s] = (j < m && col < KK) ? Yb[j * KB + col] : 0.0;
+    }
+    const double th = col < KK ? st.theta[ch.inst * KB + col] : 0.0;
+    const int nsteps = (m + 3) / 4;
     const int64_t end = ch.r0 + ch.n;
-    for (int64_t i = ch.r0 + g; i < end; i += RPB) ritz_row<KK>(i, m, V, W, sY, sTh, diag[i], floor_, KK, T, q, rn2, tn2);
-    double rs, ts;
-    ritz_block_sums<KK>(rn2, tn2, red, rs, ts);
-    if (threadIdx.x < KK) rpart[(int64_t)blockIdx.x * RSTRIDE + threadIdx.x] = rs;
+    double rn2 = 0.0;
+    for (int64_t r0 = ch.r0 + 16 * wave; r0 < end; r0 += 64) {
+        const int64_t ra = r0 + col;
+        const bool rok = ra < end;
+        dbl4 ax = dbl4{0.0, 0.0, 0.0, 0.0}, aw = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s0 = 0; s0 < STEPS; s0 += 4) {
+            if (s0 >= nsteps) break;
+            double xv[4], wv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = 4 * (s0 + u) + kk;
+                const bool ok = rok && j < m;
+                xv[u] = ok ? *V.at(ra, j) : 0.0;
+                wv[u] = ok ? *W.at(ra, j) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ax = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[u], yv[s0 + u], ax, 0, 0, 0);
+                aw = __builtin_amdgcn_mfma_f64_16x16x4f64(wv[u], yv[s0 + u], aw, 0, 0, 0);
+            }
+        }
+        if (col < KK) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = r0 + kk + 4 * r;
+                if (row >= end) continue;
+                const double res = aw[r] - th * ax[r];
+                double den = th - diag[row];
+                if (fabs(den) < floor_) den = den < 0.0 ? -floor_ : floor_;
+                rn2 += res * res;
+                T[row * KK + col] = res / den;
+            }
+        }
+    }
+    __shared__ double red[4][64];
+    red[wave][lane] = rn2;
+    __syncthreads();
+    if ((int)threadIdx.x < KK) {
+        const int c = threadIdx.x;
+        double rs = 0.0;
+        for (int w = 0; w < 4; ++w)
+            for (int q = 0; q < 4; ++q) rs += red[w][c + 16 * q];
+        rpart[(int64_t)blockIdx.x * RSTRIDE + c] = rs;
+    }
 }
 
 // ------------------------------------------------------- per-instance kernels
@@ -1062,8 +1140,8 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, const Ba
     auto tsmm = [&](Mat A, int m, const double *Bs, int bstride, int ldb, auto ncc, double alpha, double beta,
                     Mat Out, const int32_t *gate) {
         constexpr int NC = decltype(ncc)::value;
-        hipLaunchKernelGGL((k_btsmm<KK, NC>), gch, b256, 0, s, dch, gate, m, A, Bs, bstride, ldb, NC, alpha,
-                           beta, Out);
+        hipLaunchKernelGGL((k_btsmm<(NC + 15) / 16, MS / 4>), gch, b256, 0, s, dch, gate, m, A, Bs, bstride, ldb,
+                           NC, alpha, beta, Out);
         HQ_LAUNCH_CHECK();
     };
     using NK = std::integral_constant<int, KK>;
@@ -1103,8 +1181,8 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, const Ba
             tsmm(W, m, st.Q, MS * 2 * KB, 2 * KK, N2K{}, 1.0, 0.0, W, dn);
         }
         const Mat T = V.cols(mp);
-        hipLaunchKernelGGL(k_britz<KK>, gch, b256, 0, s, dch, st, mp, V, W, (const double *)g.diag.p, floor_, T.p,
-                           rpart.p);
+        hipLaunchKernelGGL((k_britz<KK, MS / 4>), gch, b256, 0, s, dch, st, mp, V, W, (const double *)g.diag.p,
+                           floor_, T.p, rpart.p);
         HQ_LAUNCH_CHECK();
         // projection against the basis, with T^T T from the first product; a
         // second pass only for instances whose first pass left some column

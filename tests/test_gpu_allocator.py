@@ -132,3 +132,33 @@ def test_caller_order_sigma_allocates_once():
     ref.set_determinants(a, b, na, nb)
     S_ref = ref.sigma(X)
     assert torch.allclose(S1, S_ref, rtol=0, atol=1e-12 * float(S_ref.abs().max()))
+
+
+def test_batch_buffers_through_the_allocator():
+    """The batch's concatenated arrays, per-instance build scratch and solve
+    buffers come from the allocator too; a NULL return while adding an
+    instance reports OOM, and the batch can be rebuilt and solved afterwards."""
+    insts = [W.batch_instance(i, 0.1) for i in (0, 9, 20)]
+    A = CountingAllocator()
+    s = hq.Hinqs(allocator=A)
+    for ints, a, b, spec in insts[:2]:
+        s.batch_add(ints.h, ints.eri, ints.e_core, a, b, spec["na"], spec["nb"])
+    A.fail = True
+    ints, a, b, spec = insts[2]
+    with pytest.raises(hq.HinqsError) as err:
+        s.batch_add(ints.h, ints.eri, ints.e_core, a, b, spec["na"], spec["nb"])
+    assert err.value.code == -9
+    A.fail = False
+    s.batch_clear()
+    for ints, a, b, spec in insts:
+        s.batch_add(ints.h, ints.eri, ints.e_core, a, b, spec["na"], spec["nb"])
+    e, c, info = s.batch_lowest_eigenpair(tol=1e-9)
+    assert info["converged"]
+    for i, (ints, a, b, spec) in enumerate(insts):
+        t = hq.Hinqs(allocator="hip")
+        t.set_integrals(ints.h, ints.eri, ints.e_core)
+        t.set_determinants(a, b, spec["na"], spec["nb"])
+        ei, _, _ = t.lowest_eigenpair(tol=1e-9)
+        assert abs(e[i] - ei) <= 1e-10
+    s.close()
+    assert not A.live
