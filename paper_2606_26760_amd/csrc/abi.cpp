@@ -174,36 +174,8 @@ int hinqs_sigma(hinqs_ctx *ctx, int k, const void *X, void *S, int precision, in
             return HINQS_OK;
         }
         // stage through sorted-order buffers (gather X, scatter S); pad k up to K
-        const int64_t D = c.ndet;
-        const size_t bytes = (size_t)D * K * esz;
-        char *xs = c.cs.get<char>(0, bytes);
-        char *ss = c.cs.get<char>(1, bytes);
-        const void *src = X;
-        if (K != k) {
-            // pad to K columns: caller rows of k values -> rows of K values
-            char *xp = c.cs.get<char>(2, bytes);
-            HQ_CHECK(hipMemsetAsync(xp, 0, bytes, s));
-            HQ_CHECK(hipMemcpy2DAsync(xp, (size_t)K * esz, X, (size_t)k * esz, (size_t)k * esz, D,
-                                      hipMemcpyDeviceToDevice, s));
-            src = xp;
-        }
-        if (sorted) HQ_CHECK(hipMemcpyAsync(xs, src, bytes, hipMemcpyDeviceToDevice, s));
-        else gather_rows(s, src, xs, c.perm.p, D, K * esz);
-        sigma_sorted(c, K, xs, K, ss, K, precision, s);
-        if (K == k) {
-            if (sorted) HQ_CHECK(hipMemcpyAsync(S, ss, bytes, hipMemcpyDeviceToDevice, s));
-            else scatter_rows(s, ss, S, c.perm.p, D, K * esz);
-        } else {
-            // unpad: scatter K-wide rows into a K-wide buffer, then copy k columns
-            if (!sorted) {
-                scatter_rows(s, ss, xs, c.perm.p, D, K * esz);
-                HQ_CHECK(hipMemcpy2DAsync(S, (size_t)k * esz, xs, (size_t)K * esz, (size_t)k * esz, D,
-                                          hipMemcpyDeviceToDevice, s));
-            } else {
-                HQ_CHECK(hipMemcpy2DAsync(S, (size_t)k * esz, ss, (size_t)K * esz, (size_t)k * esz, D,
-                                          hipMemcpyDeviceToDevice, s));
-            }
-        }
+        const size_t bytes = (size_t)c.ndet * K * esz;
+        sigma_staged(c, k, X, S, precision, sorted, c.cs.get<char>(0, bytes), c.cs.get<char>(1, bytes), nullptr);
         return HINQS_OK;
     });
 }

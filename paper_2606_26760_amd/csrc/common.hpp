@@ -427,6 +427,12 @@ void sigma_sorted(Ctx &c, int k, const void *X, int ldx, void *S, int lds, int p
 // validated as for hinqs_sigma.
 void noalloc_setup(int device);
 void sigma_noalloc(Ctx &c, int k, const void *X, void *S, int precision, bool sorted);
+// S = H X for X, S in caller order (sorted = false) or sorted order, any k in
+// [1, 16]: X gathered and padded to K columns into xs, the sorted product into
+// ss (both ndet x K of the precision's type), S scattered back.  ctr: as for
+// sigma_sorted.
+void sigma_staged(Ctx &c, int k, const void *X, void *S, int precision, bool sorted, void *xs, void *ss,
+                  unsigned long long *ctr);
 // Time the candidate launch shapes on c's couplings, keep the fastest in c
 // (and in a process-wide cache keyed by problem shape).  Returns it.
 SigmaCfg autotune_sigma(Ctx &c, int k, int precision);

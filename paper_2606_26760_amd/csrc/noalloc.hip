@@ -1,7 +1,9 @@
 // Sigma product S = H_B X without any device allocation (the repeated product
 // of the Davidson iteration, Sec. 2.2, Step 3), for callers that cannot
 // allocate: the kernel's row counters and the sorted-order staging of X and S
-// live in one static device array per GPU instead of context buffers.
+// live in one static device array per GPU instead of context buffers.  The
+// staging kernels (caller order and k padded to K in one pass each way) serve
+// hinqs_sigma too, with the context's buffers.
 //
 // Layout of the array: [0, 4096) row counters (SIGMA_CTR_WORDS words, cleared
 // by a fill kernel on every call; no memset, so the call can be captured in a
@@ -66,22 +68,26 @@ __global__ void k_stage_out(const T *__restrict__ ss, int K, const int32_t *__re
 }
 
 template <typename T>
-void staged(Ctx &c, int k, int K, const void *X, void *S, bool sorted, unsigned char *base, size_t blk) {
+void staged(Ctx &c, int k, int K, const void *X, void *S, bool sorted, T *xs, T *ss, unsigned long long *ctr) {
     hipStream_t s = c.stream;
     const int64_t D = c.ndet;
-    T *xs = (T *)(base + NOALLOC_CTR_BYTES);
-    T *ss = (T *)(base + NOALLOC_CTR_BYTES + blk);
     const int32_t *perm = sorted ? nullptr : c.perm.p;
     hipLaunchKernelGGL(k_stage_in<T>, dim3(grid_for(D * K, 256)), dim3(256), 0, s, (const T *)X, k, perm, D, K,
                        xs);
     HQ_LAUNCH_CHECK();
-    sigma_sorted(c, K, xs, K, ss, K, sizeof(T) == 8 ? HINQS_FP64 : HINQS_FP32, s,
-                 (unsigned long long *)base);
+    sigma_sorted(c, K, xs, K, ss, K, sizeof(T) == 8 ? HINQS_FP64 : HINQS_FP32, s, ctr);
     hipLaunchKernelGGL(k_stage_out<T>, dim3(grid_for(D * k, 256)), dim3(256), 0, s, ss, K, perm, D, k, (T *)S);
     HQ_LAUNCH_CHECK();
 }
 
 }  // namespace
+
+void sigma_staged(Ctx &c, int k, const void *X, void *S, int precision, bool sorted, void *xs, void *ss,
+                  unsigned long long *ctr) {
+    const int K = k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16;
+    if (precision == HINQS_FP64) staged<double>(c, k, K, X, S, sorted, (double *)xs, (double *)ss, ctr);
+    else staged<float>(c, k, K, X, S, sorted, (float *)xs, (float *)ss, ctr);
+}
 
 void noalloc_setup(int device) {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -119,13 +125,11 @@ void sigma_noalloc(Ctx &c, int k, const void *X, void *S, int precision, bool so
     hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(SIGMA_CTR_WORDS), 0, s, (unsigned long long *)base,
                        SIGMA_CTR_WORDS);
     HQ_LAUNCH_CHECK();
-    if (direct) {
+    if (direct)
         sigma_sorted(c, K, X, K, S, K, precision, s, (unsigned long long *)base);
-    } else if (precision == HINQS_FP64) {
-        staged<double>(c, k, K, X, S, sorted, base, blk);
-    } else {
-        staged<float>(c, k, K, X, S, sorted, base, blk);
-    }
+    else
+        sigma_staged(c, k, X, S, precision, sorted, base + NOALLOC_CTR_BYTES, base + NOALLOC_CTR_BYTES + blk,
+                     (unsigned long long *)base);
 }
 
 }  // namespace hinqs
