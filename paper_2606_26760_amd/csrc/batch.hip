@@ -1006,6 +1006,7 @@ void batch_layout(Ctx &c, BatchState &B) {
 struct Resources {  // released on every exit path
     hipStream_t bs = nullptr;
     hipEvent_t ev = nullptr;
+    int32_t *pinned = nullptr;  // landing word of the per-iteration finished-instance count
     std::vector<hipGraphExec_t> ex;
     bool capturing = false;
     ~Resources() {
@@ -1017,6 +1018,7 @@ struct Resources {  // released on every exit path
         for (auto e : ex)
             if (e) (void)hipGraphExecDestroy(e);
         if (bs) (void)hipStreamSynchronize(bs);
+        if (pinned) (void)hipHostFree(pinned);
         if (ev) (void)hipEventDestroy(ev);
         if (bs) (void)hipStreamDestroy(bs);
     }
@@ -1057,6 +1059,7 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, const Ba
     DBuf<Chunk> d_chunks;
     Resources R;
     HQ_CHECK(hipStreamCreateWithFlags(&R.bs, hipStreamNonBlocking));
+    HQ_CHECK(hipHostMalloc((void **)&R.pinned, sizeof(int32_t), hipHostMallocDefault));
     HQ_CHECK(hipEventCreateWithFlags(&R.ev, hipEventDisableTiming));
     HQ_CHECK(hipEventRecord(R.ev, c.stream));  // work queued on the caller's stream comes first
     HQ_CHECK(hipStreamWaitEvent(R.bs, R.ev, 0));
@@ -1247,8 +1250,10 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, const Ba
         }
         ++it;
         m_last = mp;
-        HQ_CHECK(hipMemcpyAsync(&ndone, d_ndone.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HQ_CHECK(hipStreamSynchronize(s));
+        // pinned landing word, polled wait: the next graph launch waits on this read
+        HQ_CHECK(hipMemcpyAsync(R.pinned, d_ndone.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        wait_stream(s);
+        ndone = *R.pinned;
         if (ndone >= nb) break;
         m = mp + KK;
     }
