@@ -238,7 +238,8 @@ def outer_iteration(hq, solver, solver_integrals, c, e0, ya, yb, cand_score, kee
     a_b, b_b = solver.determinants()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, _, bscore = solver.pt2(c, e0, a_b, b_b)
+    _, _, bscore = solver.pt2_members(c, e0)   # PT2 of the set's own members: one sigma product
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
     c_new, _, ms_upd = solver.grow_basis(ya, yb, cand_score, keep, basis_score=bscore, b_max=b_max, coeffs=c)
     torch.cuda.synchronize()

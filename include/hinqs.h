@@ -430,6 +430,19 @@ int hinqs_pt2(hinqs_ctx *ctx, const double *coeffs, double e0, int64_t ncand,
               double *score, int flags);
 
 /*
+ * hinqs_pt2 for the candidates x = the determinants of B themselves (their
+ * eviction ranking in Sec. 2.2, Step 2), from the coupling matrix: numer is
+ * the row of H_B c, diagonal included (one sigma product), hxx the diagonal,
+ * score = numer^2 / |e0 - hxx|.  Equal to hinqs_pt2 on B's own strings up to
+ * the order of the sums.
+ *   coeffs            device, ndet doubles (caller order unless HINQS_SORTED_ORDER)
+ *   numer, hxx, score device, ndet doubles each (same order), or NULL to skip
+ * Errors: NOT_READY, INVALID_ARG, NONFINITE, OOM, HIP.
+ */
+int hinqs_pt2_members(hinqs_ctx *ctx, const double *coeffs, double e0, double *numer, double *hxx,
+                      double *score, int flags);
+
+/*
  * Stable selection of the k smallest (or, with HINQS_LARGEST, the k
  * largest) of n doubles: idx (device, k int32) receives their indices in
  * that order, ties broken by the lower index; -0.0 equals +0.0.  This is the

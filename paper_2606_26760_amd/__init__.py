@@ -49,7 +49,7 @@ EXPORTED = ["hinqs_opts_default", "hinqs_create", "hinqs_destroy", "hinqs_last_e
             "hinqs_batch_lowest_eigenpair", "hinqs_expand", "hinqs_pt2", "hinqs_top_k",
             "hinqs_teacher_weights", "hinqs_distinct_strings", "hinqs_update_determinants",
             "hinqs_grow_basis", "hinqs_get_determinants", "hinqs_product_closure",
-            "hinqs_sigma_noalloc"]
+            "hinqs_sigma_noalloc", "hinqs_pt2_members"]
 
 
 class HinqsError(RuntimeError):
@@ -146,6 +146,7 @@ def load_library() -> ctypes.CDLL:
             "hinqs_batch_lowest_eigenpair": (i32, [P, P, P, P, P, P, P]),
             "hinqs_expand": (i32, [P, P, i64, i64, P, P, P, P, i32]),
             "hinqs_pt2": (i32, [P, P, dbl, i64, P, P, P, P, P, i32]),
+            "hinqs_pt2_members": (i32, [P, P, dbl, P, P, P, i32]),
             "hinqs_top_k": (i32, [P, i64, P, i64, i32, P]),
             "hinqs_teacher_weights": (i32, [P, P, P, P, P, i32]),
             "hinqs_distinct_strings": (i32, [P, P, P]),
@@ -555,6 +556,15 @@ class Hinqs:
         self._check(self._lib.hinqs_pt2(self._h, self._ptr(c), float(e0), n, self._ptr(ca), self._ptr(cb),
                                         *[self._ptr(t) for t in out], SORTED_ORDER if sorted_order else 0))
         return tuple(t[:n] for t in out)
+
+    def pt2_members(self, c, e0, sorted_order=False):
+        """pt2() of every determinant of B (numerator = row of H_B c), from one sigma product."""
+        torch = _torch()
+        self._dev(c, torch.float64)
+        out = [torch.empty(self.ndet, dtype=torch.float64, device=self.device) for _ in range(3)]
+        self._check(self._lib.hinqs_pt2_members(self._h, self._ptr(c), float(e0), *[self._ptr(t) for t in out],
+                                                SORTED_ORDER if sorted_order else 0))
+        return tuple(out)
 
     def top_k(self, values, k, largest=False):
         """Indices (int32 device tensor) of the k smallest (largest) values, ties by lower index."""

@@ -379,6 +379,17 @@ int hinqs_pt2(hinqs_ctx *ctx, const double *coeffs, double e0, int64_t ncand, co
     });
 }
 
+int hinqs_pt2_members(hinqs_ctx *ctx, const double *coeffs, double e0, double *numer, double *hxx, double *score,
+                      int flags) {
+    return guarded(ctx, [&](Ctx &c) {
+        require_dets(c);
+        if (!coeffs) throw Error(HINQS_E_INVALID_ARG, "null coefficients");
+        if (!std::isfinite(e0)) throw Error(HINQS_E_NONFINITE, "e0 is NaN/Inf");
+        pt2_members(c, coeffs, (flags & HINQS_SORTED_ORDER) != 0, e0, numer, hxx, score);
+        return HINQS_OK;
+    });
+}
+
 int hinqs_top_k(hinqs_ctx *ctx, int64_t n, const double *values, int64_t k, int flags, int32_t *idx) {
     return guarded(ctx, [&](Ctx &c) {
         if (!values || !idx) throw Error(HINQS_E_INVALID_ARG, "null pointer");

@@ -464,6 +464,11 @@ int64_t expand(Ctx &c, const double *coeffs, bool sorted, int64_t ntop, int64_t 
                uint64_t *out_b, int32_t *top);
 void pt2(Ctx &c, const double *coeffs, bool sorted, double e0, int64_t ncand, const uint64_t *ca,
          const uint64_t *cb, double *numer, double *hxx, double *score);
+// PT2 quantities (Eq. 3) of every member of B: numer = (H_B c)_x (one sigma
+// product, the diagonal included), hxx = H_xx, score = numer^2 / |e0 - hxx|;
+// outputs ndet each, caller order unless sorted.
+void pt2_members(Ctx &c, const double *coeffs, bool sorted, double e0, double *numer, double *hxx,
+                 double *score);
 
 // Determinants of (distinct alpha strings) x (distinct beta strings) that are
 // not in the set, ascending; the first cap are written; returns how many.

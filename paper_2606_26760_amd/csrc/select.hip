@@ -658,6 +658,41 @@ void pt2(Ctx &c, const double *coeffs, bool sorted, double e0, int64_t ncand, co
                     "a candidate has bits at or above norb or the wrong electron count (its outputs are NaN)");
 }
 
+namespace {
+
+// PT2 quantities of the members of B from (H_B c) in sorted order (diagonal
+// included); outputs in caller order through perm (null: sorted order).
+__global__ void k_pt2_members(int64_t n, const double *hc, const double *diag, double e0, const int32_t *perm,
+                              double *numer, double *hxx, double *score) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = perm ? (int64_t)perm[i] : i;
+    const double v = hc[i], d = diag[i];
+    if (numer) numer[o] = v;
+    if (hxx) hxx[o] = d;
+    if (score) score[o] = v * v / fabs(e0 - d);
+}
+
+}  // namespace
+
+void pt2_members(Ctx &c, const double *coeffs, bool sorted, double e0, double *numer, double *hxx,
+                 double *score) {
+    hipStream_t s = c.stream;
+    const int64_t n = c.ndet;
+    const double *cs = coeffs;
+    if (!sorted) {
+        double *g = c.cs.get<double>(0, n);
+        gather_rows(s, coeffs, g, c.perm.p, n, 8);
+        cs = g;
+    }
+    double *hc = c.cs.get<double>(1, n);
+    sigma_sorted(c, 1, cs, 1, hc, 1, HINQS_FP64, s);
+    hipLaunchKernelGGL(k_pt2_members, dim3(grid_for(n, 256)), dim3(256), 0, s, n, (const double *)hc,
+                       (const double *)c.diag.p, e0, sorted ? (const int32_t *)nullptr : (const int32_t *)c.perm.p,
+                       numer, hxx, score);
+    HQ_LAUNCH_CHECK();
+}
+
 }  // namespace hinqs
 
 // ------------------------------------------------------------ product space

@@ -157,6 +157,29 @@ def test_pt2_matches_oracle_cas10(cas10):
     assert np.count_nonzero(num) == len(num)
 
 
+def test_pt2_members_matches_oracle_and_pt2(cas10):
+    """PT2 of B's own members from one sigma product equals the oracle's PT2 of
+    those strings (numerator: the row of H_B c with the diagonal) at the PT2
+    bars, and the general kernel's results up to the order of the sums."""
+    ints, a, b, cfg, s, o = cas10
+    log("pt2 of the members of B (20k) via one sigma product")
+    c = _coeffs(len(a), 31)
+    e0 = float(o.pt2(c, 0.0, a[:300], b[:300])[1].min()) - 0.5
+    cd = torch.from_numpy(c).cuda()
+    num, hxx, score = (t.cpu().numpy() for t in s.pt2_members(cd, e0))
+    rn, rh, rs, absnum = o.pt2(c, e0, a, b, with_scale=True)
+    dn = 1e-12 * absnum + 1e-300
+    assert np.all(np.abs(num - rn) <= dn)
+    assert np.all(np.abs(hxx - rh) <= 1e-12 * np.abs(rh).max())
+    assert np.array_equal(score, num * num / np.abs(e0 - hxx))
+    gn, gh, gs = (t.cpu().numpy() for t in s.pt2(cd, e0, a, b))
+    assert np.all(np.abs(num - gn) <= 2 * dn) and np.array_equal(hxx, gh)
+    # sorted order: the same values permuted
+    perm = s.permutation().cpu().numpy().astype(np.int64)
+    n2 = s.pt2_members(torch.from_numpy(c[perm]).cuda(), e0, sorted_order=True)[0].cpu().numpy()
+    assert np.array_equal(n2, num[perm])
+
+
 def test_pt2_sorted_order_and_device_candidates(cas10):
     ints, a, b, cfg, s, o = cas10
     log("pt2 sorted order, device candidates")
