@@ -981,7 +981,7 @@ void grow_keep(DBuf<T> &b, size_t used, size_t need, hipStream_t s) {
     DBuf<T> nbuf;
     nbuf.ensure(std::max(need, 2 * b.n));
     copy_d2d(nbuf.p, b.p, (int64_t)used, s);
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
     b.swap(nbuf);
 }
 
@@ -999,7 +999,7 @@ void batch_layout(Ctx &c, BatchState &B) {
     B.inst_row.ensure(nb + 1);
     HQ_CHECK(hipMemcpyAsync(B.inst_row.p, B.row_off.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice,
                             c.stream));
-    HQ_CHECK(hipStreamSynchronize(c.stream));
+    wait_stream(c.stream);
     B.dirty = false;
 }
 
@@ -1109,7 +1109,7 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, const Ba
         st.energy = p; p += nb;
         st.resid = p;  p += nb;
     }
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
     const auto t_buf = std::chrono::steady_clock::now();
     hipLaunchKernelGGL(k_bvalid_init, dim3(grid_for((int64_t)nb * MS, 256)), dim3(256), 0, s, nb, KK, st.valid);
     HQ_LAUNCH_CHECK();
@@ -1214,7 +1214,7 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, const Ba
         return mp;
     };
 
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
     const auto t1 = std::chrono::steady_clock::now();
     const bool verbose = env_or("HINQS_VERBOSE", 0) != 0;
     if (verbose)
@@ -1278,7 +1278,7 @@ int batch_solve_k(Ctx &c, BatchState &B, const hinqs_opts &o, int mmax, const Ba
     HQ_CHECK(hipMemcpyAsync(r_h.data(), st.resid, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
     HQ_CHECK(hipMemcpyAsync(done_h.data(), st.done, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s));
     HQ_CHECK(hipMemcpyAsync(it_h.data(), st.iters, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, s));
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
     HQ_CHECK(hipEventRecord(R.ev, s));  // the caller's stream sees the outputs
     HQ_CHECK(hipStreamWaitEvent(c.stream, R.ev, 0));
     int nconv = 0;
@@ -1435,7 +1435,7 @@ int batch_add(Ctx &c, int norb, const double *h, const double *eri, double ecore
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(p.ndet, 256)), dim3(256), 0, s, p.ndet, B.row_inst.p + r0,
                        (int32_t)bi);
     HQ_LAUNCH_CHECK();
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
     B.g.ndet = r1;
     B.g.nnz = z1;
     B.meta.push_back({norb, na, nb, p.ndet, p.nnz});

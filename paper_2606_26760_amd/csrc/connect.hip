@@ -255,7 +255,7 @@ void export_connectivity(Ctx &c, int64_t *rowptr_c, int32_t *col_c, uint32_t *de
                            c.col.p, c.desc.p, c.perm.p, rowptr_c, col_c, desc_c);
         HQ_LAUNCH_CHECK();
     }
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
 }
 
 void compute_xcd_rows(Ctx &c) {
@@ -265,7 +265,7 @@ void compute_xcd_rows(Ctx &c) {
     hipLaunchKernelGGL(k_balance_bounds, dim3(1), dim3(64), 0, s, c.ndet, c.rowptr.p, bnd.p);
     HQ_LAUNCH_CHECK();
     HQ_CHECK(hipMemcpyAsync(c.xcd_rows, bnd.p, sizeof(c.xcd_rows), hipMemcpyDeviceToHost, s));
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
 }
 
 void build_connectivity(Ctx &c, bool xcd_rows) {
@@ -299,7 +299,7 @@ void build_connectivity(Ctx &c, bool xcd_rows) {
     exclusive_scan_i64(s, counts.p, c.rowptr.p, n + 1, c.work);
     int64_t nnz = 0;
     HQ_CHECK(hipMemcpyAsync(&nnz, c.rowptr.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
     if (nnz >= ((int64_t)1 << 40)) throw Error(HINQS_E_UNSUPPORTED, "too many couplings");
     c.nnz = nnz;
     c.col.ensure(nnz);

@@ -244,7 +244,7 @@ void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint6
     HQ_LAUNCH_CHECK();
     unsigned long long hbad[2];
     HQ_CHECK(hipMemcpyAsync(hbad, bad.p, sizeof(hbad), hipMemcpyDeviceToHost, s));
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
     if (hbad[1] & 1ull)
         throw Error(HINQS_E_BAD_OCCUPATION, "determinant " + std::to_string(hbad[0]) +
                                                 " (or another) has an occupied orbital >= norb");
@@ -277,7 +277,7 @@ void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint6
     HQ_LAUNCH_CHECK();
     int32_t hdup = 0;
     HQ_CHECK(hipMemcpyAsync(&hdup, dup.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
     if (hdup) throw Error(HINQS_E_DUPLICATE, "the determinant set contains a duplicate");
 
     // ---- alpha groups
@@ -285,7 +285,7 @@ void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint6
     int32_t last[2];
     HQ_CHECK(hipMemcpyAsync(&last[0], scan.p + ndet - 1, 4, hipMemcpyDeviceToHost, s));
     HQ_CHECK(hipMemcpyAsync(&last[1], flag.p + ndet - 1, 4, hipMemcpyDeviceToHost, s));
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
     c.nua = last[0] + last[1];
     c.ua.ensure(c.nua);
     c.ga.ensure(c.nua + 1);
@@ -309,7 +309,7 @@ void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint6
     exclusive_scan_i32(s, flag.p, scan.p, ndet, c.work);
     HQ_CHECK(hipMemcpyAsync(&last[0], scan.p + ndet - 1, 4, hipMemcpyDeviceToHost, s));
     HQ_CHECK(hipMemcpyAsync(&last[1], flag.p + ndet - 1, 4, hipMemcpyDeviceToHost, s));
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
     c.nub = last[0] + last[1];
     c.ub.ensure(c.nub);
     c.gb.ensure(c.nub + 1);
@@ -333,7 +333,7 @@ void build_determinants(Ctx &c, int64_t ndet, const uint64_t *alpha, const uint6
     hipLaunchKernelGGL(k_alpha_links, dim3(grid_for(c.nua, 128)), dim3(128), 0, s, c.ua.p, c.nua, norb,
                        maxl, c.alink_ptr.p, c.alink.p, c.alink_info.p);
     HQ_LAUNCH_CHECK();
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
     c.ms_sort = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     c.have_dets = true;
 }

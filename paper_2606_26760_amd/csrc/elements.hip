@@ -149,7 +149,7 @@ void build_integrals(Ctx &c, int norb, const double *h, const double *eri, doubl
     hipLaunchKernelGGL(k_pack_eri, dim3(grid_for(np, 256)), dim3(256), 0, s, full.p, norb, c.d_eri.p,
                        c.d_eri32.p);
     HQ_LAUNCH_CHECK();
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
     c.have_ints = true;
 }
 
@@ -192,7 +192,7 @@ void build_elements_after(Ctx &c, const int64_t *skip) {
         hipLaunchKernelGGL(k_diag<false>, dim3(grid_diag), dim3(256), 0, s, a);
         HQ_LAUNCH_CHECK();
     }
-    HQ_CHECK(hipStreamSynchronize(s));
+    wait_stream(s);
     c.have_elements = true;
     c.ms_elements =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
