@@ -146,6 +146,21 @@ def test_sigma_fp64_cas6(k):
     _check_sigma(s, o, X, np.arange(len(a)), 1e-12)
 
 
+def test_sigma_every_width_both_precisions():
+    """Every block width 1..16 in caller order, so each padded kernel width
+    (k -> K in {1, 2, 4, 8, 16}) and its staging are used, FP64 at the 1e-12
+    row bar and FP32 at 2e-6, on every row of a 3,000-determinant set."""
+    ints, a, b, cfg = W.config_inputs(1, ndet=3000)
+    log("sigma widths 1..16, fp64 and fp32, 3000 dets")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    o = oracle_for(ints, a, b, cfg.na, cfg.nb)
+    rows = np.arange(len(a))
+    for k in range(1, 17):
+        X = W.random_block(len(a), k, 300 + k)
+        _check_sigma(s, o, X, rows, 1e-12)
+        _check_sigma(s, o, X, rows, 2e-6, dtype=torch.float32)
+
+
 def test_sigma_fp64_cas10_all_rows():
     ints, a, b, cfg = W.config_inputs(1)
     log("sigma fp64 cas10 20000 dets k=8")
