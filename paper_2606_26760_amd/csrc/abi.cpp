@@ -93,7 +93,11 @@ int hinqs_create(hinqs_ctx **out, int device, void *hip_stream, hinqs_alloc_fn a
         delete ctx;
         return HINQS_E_OOM;
     }
-    if (hipMemset(ctx->c.sigma_ctr.p, 0, sizeof(unsigned long long) * SIGMA_CTR_WORDS) != hipSuccess) {
+    // on the context's stream: memory from a stream-ordered allocator may still
+    // be read by work queued there before it was handed out
+    if (hipMemsetAsync(ctx->c.sigma_ctr.p, 0, sizeof(unsigned long long) * SIGMA_CTR_WORDS, ctx->c.stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->c.stream) != hipSuccess) {
         delete ctx;
         return HINQS_E_HIP;
     }
