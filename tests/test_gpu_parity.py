@@ -233,6 +233,26 @@ def test_top_of_orbital_range(norb, na, nb, kind):
         assert abs(float(np.dot(c.cpu().numpy(), c_ref))) >= 1 - 1e-9
 
 
+def test_sigma_and_solve_are_bitwise_repeatable():
+    """The sigma kernel hands rows out through per-XCD counters, so which team
+    takes a row changes from launch to launch; every row is still summed by
+    one team in a fixed order, so repeated products and solves must agree to
+    the bit (1e6 set: FP64 and FP32 sigma; 20k set: the FP64 eigenpair)."""
+    ints, a, b, cfg = W.config_inputs(2)
+    log("bitwise repeatability: sigma at 1e6, k = 8")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    X = torch.from_numpy(W.random_block(len(a), 8, 51)).cuda()
+    assert torch.equal(s.sigma(X), s.sigma(X))
+    X32 = X.float()
+    assert torch.equal(s.sigma(X32), s.sigma(X32))
+    ints, a, b, cfg = W.config_inputs(1)
+    log("bitwise repeatability: FP64 eigenpair at 20k")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    e1, c1, _ = s.lowest_eigenpair(tol=1e-9)
+    e2, c2, _ = s.lowest_eigenpair(tol=1e-9)
+    assert e1 == e2 and torch.equal(c1, c2)
+
+
 def test_sigma_sorted_order_matches_caller_order():
     ints, a, b, cfg = W.config_inputs(1, ndet=4000)
     s = solver_for(ints, a, b, cfg.na, cfg.nb)
