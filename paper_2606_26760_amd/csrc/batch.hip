@@ -1435,7 +1435,7 @@ int batch_add(Ctx &c, int norb, const double *h, const double *eri, double ecore
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(p.ndet, 256)), dim3(256), 0, s, p.ndet, B.row_inst.p + r0,
                        (int32_t)bi);
     HQ_LAUNCH_CHECK();
-    wait_stream(s);
+    // no wait: the next instance's build reuses the scratch buffers in stream order
     B.g.ndet = r1;
     B.g.nnz = z1;
     B.meta.push_back({norb, na, nb, p.ndet, p.nnz});
