@@ -201,12 +201,13 @@ void rdm12_sorted(Ctx &c, const double *cs, double *rdm1, double *rdm2) {
     const int n = c.norb;
     const int64_t n4 = (int64_t)n * n * n * n;
     const int ntab = tab_size(n);
-    DBuf<double> g2c, tabc;
-    g2c.ensure((size_t)NCOPY * n4);
-    tabc.ensure((size_t)NCOPY * ntab);
-    HQ_CHECK(hipMemsetAsync(g2c.p, 0, sizeof(double) * NCOPY * n4, s));
-    HQ_CHECK(hipMemsetAsync(tabc.p, 0, sizeof(double) * NCOPY * ntab, s));
-    RdmArgs a{c.ndet, n, c.sa.p, c.sb.p, c.rowptr.p, c.col.p, c.desc.p, cs, g2c.p, tabc.p, ntab};
+    // accumulation copies in the context's call scratch (slots 2 and 3; slot
+    // 0 may hold the gathered coefficients), kept for the next call
+    double *g2c = c.cs.get<double>(2, (size_t)NCOPY * n4);
+    double *tabc = c.cs.get<double>(3, (size_t)NCOPY * ntab);
+    HQ_CHECK(hipMemsetAsync(g2c, 0, sizeof(double) * NCOPY * n4, s));
+    HQ_CHECK(hipMemsetAsync(tabc, 0, sizeof(double) * NCOPY * ntab, s));
+    RdmArgs a{c.ndet, n, c.sa.p, c.sb.p, c.rowptr.p, c.col.p, c.desc.p, cs, g2c, tabc, ntab};
     const size_t lds = sizeof(double) * (size_t)ntab;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
@@ -220,23 +221,20 @@ void rdm12_sorted(Ctx &c, const double *cs, double *rdm1, double *rdm2) {
         hipLaunchKernelGGL(k_rdm<false>, dim3(grid), dim3(256), 0, s, a);
     }
     HQ_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_rdm_assemble, dim3(grid_for(n4, 256)), dim3(256), 0, s, n, g2c.p, tabc.p, ntab,
+    hipLaunchKernelGGL(k_rdm_assemble, dim3(grid_for(n4, 256)), dim3(256), 0, s, n, g2c, tabc, ntab,
                        rdm1, rdm2);
     HQ_LAUNCH_CHECK();
-    HQ_CHECK(hipStreamSynchronize(s));
 }
 
 void integral_grad_sorted(Ctx &c, const double *cs, double scale, double *gh, double *geri) {
     hipStream_t s = c.stream;
     const int n = c.norb;
     const int64_t n4 = (int64_t)n * n * n * n;
-    DBuf<double> r1, r2;
-    r1.ensure((size_t)n * n);
-    r2.ensure((size_t)n4);
-    rdm12_sorted(c, cs, r1.p, r2.p);
-    hipLaunchKernelGGL(k_grad, dim3(grid_for(n4, 256)), dim3(256), 0, s, n, r1.p, r2.p, scale, gh, geri);
+    double *r1 = c.cs.get<double>(4, (size_t)n * n + (size_t)n4);  // rdm1, then rdm2
+    double *r2 = r1 + (size_t)n * n;
+    rdm12_sorted(c, cs, r1, r2);
+    hipLaunchKernelGGL(k_grad, dim3(grid_for(n4, 256)), dim3(256), 0, s, n, r1, r2, scale, gh, geri);
     HQ_LAUNCH_CHECK();
-    HQ_CHECK(hipStreamSynchronize(s));
 }
 
 }  // namespace hinqs

@@ -415,6 +415,33 @@ def test_rdm12_matches_oracle_seeded_vector():
         assert np.abs(d2.cpu().numpy() - r2).max() <= 1e-12 * scale * cfg.norb ** 2
 
 
+@pytest.mark.parametrize("case", ["norb16_sampled", "norb28_cas", "norb32_cas"])
+def test_rdm12_larger_orbital_counts(case):
+    """RDMs as full tensors against the oracle where the per-workgroup tables
+    still fit in LDS (norb 16) and where they go to global memory (norb 28
+    and 32, the top four and bottom four orbitals of an embedded active
+    space); a second call on the same context checks that the kept
+    accumulation scratch starts from zero again."""
+    if case == "norb16_sampled":
+        ints, a, b, cfg = W.config_inputs(2, ndet=3000)
+        norb, na, nb = cfg.norb, cfg.na, cfg.nb
+    else:
+        norb = 28 if case == "norb28_cas" else 32
+        na, nb = (4, 3) if norb == 28 else (3, 3)
+        ints = W.gen_integrals(norb, 8, -3.0, -0.5, 900 + norb)
+        a, b = _subset_product(list(range(4)) + list(range(norb - 4, norb)), na, nb)
+    log(f"rdm12 {case}: {len(a)} determinants")
+    s = solver_for(ints, a, b, na, nb)
+    o = oracle_for(ints, a, b, na, nb)
+    c = W.random_block(len(a), 1, 77)[:, 0]
+    r1, r2 = o.rdm12(c)
+    scale = float(np.sum(c * c))
+    for rep in range(2):
+        d1, d2 = s.rdm12(torch.from_numpy(c).cuda())
+        assert np.abs(d1.cpu().numpy() - r1).max() <= 1e-12 * scale * norb, rep
+        assert np.abs(d2.cpu().numpy() - r2).max() <= 1e-12 * scale * norb ** 2, rep
+
+
 def test_rdm12_identities_on_eigenvector_200k():
     ints, a, b, cfg = W.config_inputs(3)
     log("rdm12 identities cas12 200000 dets")
