@@ -293,10 +293,11 @@ def test_teacher_weights_full_size():
     _check_weights(s, a, b, _coeffs(len(a), 99))
 
 
-@pytest.mark.parametrize("norb,na,nb", [(18, 9, 8), (24, 12, 12)])
+@pytest.mark.parametrize("norb,na,nb", [(18, 9, 8), (24, 12, 12), (32, 16, 15), (32, 3, 2)])
 def test_expand_and_pt2_large_orbital_counts(norb, na, nb):
-    """More than 64 alpha single moves (81, 144) and, at norb 24, integrals
-    read from global memory instead of LDS."""
+    """More than 64 alpha single moves (81, 144, 256) and, from norb 24,
+    integrals read from global memory instead of LDS; norb 32 uses the top
+    bit of the strings and the largest orbital fields of the descriptors."""
     log(f"expand + pt2 at norb {norb} ({na}a {nb}b)")
     ints = W.gen_integrals(norb, norb, -2.0, -0.5, 900 + norb)
     a, b = W.sample_determinants(norb, na, nb, 2000, 0.3, 0.0, 910 + norb)
