@@ -239,6 +239,28 @@ def test_update_large_orbital_count_and_rule_errors():
     assert s.ndet == len(na_)
 
 
+@pytest.mark.parametrize("na,nb", [(16, 15), (3, 2)])
+def test_update_top_of_orbital_range(na, nb):
+    """norb 32: strings using the top bit, the largest orbital fields of the
+    descriptors and (16 alpha electrons) 256 alpha single moves; an update
+    with evictions and appended expansion determinants against an oracle
+    built from scratch on the new set."""
+    norb = 32
+    log(f"update at norb {norb} ({na}a {nb}b)")
+    ints = W.gen_integrals(norb, 8, -2.0, -0.5, 560 + na)
+    a, b = W.sample_determinants(norb, na, nb, 1200, 0.3, 0.0, 561 + na)
+    o = oracle_for(ints, a, b, na, nb)
+    c = _coeffs(len(a), 9)
+    ea, eb, _ = o.expand(c, 2)
+    rng = np.random.default_rng(na)
+    pick = rng.choice(len(ea), min(300, len(ea)), replace=False)
+    evict = rng.choice(len(a), 80, replace=False).astype(np.int32)
+    s = solver_for(ints, a, b, na, nb)
+    s.update_determinants(ea[pick], eb[pick], evict=evict)
+    na_, nb_, _ = _new_set(a, b, evict, ea[pick], eb[pick])
+    _check_set(s, oracle_for(ints, na_, nb_, na, nb), np.arange(len(na_)))
+
+
 def test_product_closure_and_its_energy():
     """The closure list equals the oracle's; appended with an update, the
     lowest eigenvalue on the product space matches the oracle's dense value
