@@ -204,3 +204,39 @@ def test_batch_not_converged_and_errors(instances):
     with pytest.raises(hq.HinqsError) as ex:
         s.batch_add(ints.h, ints.eri, ints.e_core, a[:5], b[:5], spec["na"] + 1, spec["nb"])
     assert ex.value.name == "BAD_OCCUPATION"
+
+
+def test_batch_small_instances_and_the_size_floor():
+    """Instances down to the subspace size (48 determinants at block 8; subsets
+    of the 300-determinant full space of norb 6, 3a + 2b, once with negative
+    and once with positive spectra) batched with a 1,381-determinant one:
+    each lowest eigenvalue against the oracle's dense diagonalization.  An
+    instance below that size is refused with UNSUPPORTED, and the context
+    then solves the valid batch."""
+    import dataclasses
+    ints = W.gen_integrals(6, 6, -2.0, -0.5, 41)
+    shifted = dataclasses.replace(ints, e_core=ints.e_core + 100.0)  # every eigenvalue positive
+    fa, fb = W.full_space(6, 3, 2)
+    rng = np.random.default_rng(42)
+    insts = []
+    for it in (ints, shifted):
+        for n in (48, 49, 60, 300):
+            idx = rng.permutation(len(fa))[:n]
+            insts.append((it, fa[idx], fb[idx], {"na": 3, "nb": 2}))
+    insts.append(W.batch_instance(29, 0.1))
+    tiny = (ints, fa[:47], fb[:47], {"na": 3, "nb": 2})
+    log("batch with small instances: " + ", ".join(str(len(x[1])) for x in insts))
+    s = _batch(insts + [tiny])
+    with pytest.raises(hq.HinqsError) as ex:
+        s.batch_lowest_eigenpair(block=8, tol=1e-9)
+    assert ex.value.name == "UNSUPPORTED" and "fewer determinants" in str(ex.value)
+    s.batch_clear()
+    for it, a, b, spec in insts:
+        s.batch_add(it.h, it.eri, it.e_core, a, b, spec["na"], spec["nb"])
+    e, c, info = s.batch_lowest_eigenpair(block=8, tol=1e-9)
+    assert all(int(x) == 0 for x in info["status"])
+    for i, (it, a, b, spec) in enumerate(insts):
+        o = oracle_for(it, a, b, spec["na"], spec["nb"])
+        e_ref = o.lowest_eigenpair()[0]
+        log(f"  instance {i}: n={len(a)} E={e[i]!r} ref={e_ref!r}")
+        assert abs(e[i] - e_ref) <= 1e-10
