@@ -298,10 +298,15 @@ def test_eigenpair_cas10_vs_lanczos():
     assert abs(np.dot(c.cpu().numpy(), c_ref)) >= 1 - 1e-9
 
 
-def test_eigenpair_small_sets_and_tiny_spaces():
+@pytest.mark.parametrize("e_shift", [0.0, 100.0])
+def test_eigenpair_small_sets_and_tiny_spaces(e_shift):
+    """Sets smaller than the block and the subspace; with e_shift = 100 every
+    eigenvalue is positive, so no padding direction may pose as eigenvalue 0."""
+    import dataclasses
     for seed, (norb, na, nb, n) in enumerate([(5, 2, 2, 1), (5, 2, 2, 5), (6, 3, 2, 37),
                                               (7, 3, 3, 150)]):
         ints = W.gen_integrals(norb, norb, -2, -0.5, 500 + seed)
+        ints = dataclasses.replace(ints, e_core=ints.e_core + e_shift)
         a, b = W.sample_determinants(norb, na, nb, n, 0.5, 0.3, 600 + seed)
         log(f"davidson tiny norb={norb} n={n}")
         s = solver_for(ints, a, b, na, nb)
