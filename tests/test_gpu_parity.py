@@ -405,6 +405,26 @@ def test_mixed_precision_matches_fp64_and_oracle():
     assert abs(torch.dot(cm, cr).item()) >= 1 - 1e-8
 
 
+@pytest.mark.parametrize("e_core", [-1000.0, 1000.0])
+def test_mixed_precision_with_a_large_constant(e_core):
+    """A large E_core (here +-1000 Ha, beyond any FP32 resolution of the
+    eigenvalue) sits on the diagonal, which the mixed path applies in FP64:
+    the mixed eigenvalue stays within 1e-8 Ha of the FP64 solve and the
+    oracle (10,000 determinants drawn like the 1e6 workload)."""
+    import dataclasses
+    ints, a, b, cfg = W.config_inputs(2, ndet=10_000)
+    ints = dataclasses.replace(ints, e_core=ints.e_core + e_core)
+    log(f"mixed with E_core {e_core:+.0f}, 10000 dets")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    e64, c64, _ = s.lowest_eigenpair(tol=1e-8)
+    em, cm, stm = s.lowest_eigenpair(tol=1e-8, mixed=True)
+    e_ref, _ = oracle_for(ints, a, b, cfg.na, cfg.nb).lowest_eigenpair()
+    log(f"  oracle {e_ref!r} fp64 {e64!r} mixed {em!r} ({stm['iterations_fp32']} of {stm['iterations']} FP32)")
+    assert abs(e64 - e_ref) <= 1e-10
+    assert abs(em - e_ref) <= 1e-8 and abs(em - e64) <= 1e-8
+    assert abs(torch.dot(c64, cm).item()) >= 1 - 1e-8
+
+
 # ------------------------------------------------------------- RDMs
 def test_rdm12_matches_oracle_seeded_vector():
     for idx, n in [(0, None), (3, 400)]:
