@@ -320,6 +320,51 @@ def test_eigenpair_small_sets_and_tiny_spaces(e_shift):
                 assert abs(np.dot(c.cpu().numpy(), c_ref)) >= 1 - 1e-10
 
 
+def _two_copies():
+    """H_B = H_A (+) H_A exactly: the full 2a+2b space of orbitals 0..3 and the
+    same space moved to orbitals 4..7 (the two halves differ by four electrons,
+    so nothing couples them), with the integrals of orbitals 4..7 a copy of
+    those of 0..3.  Every eigenvalue is exactly twofold degenerate."""
+    base = W.gen_integrals(4, 4, -2.0, -0.5, 97)
+    h = np.zeros((8, 8))
+    eri = np.zeros((8,) * 4)
+    for o in (0, 4):
+        h[o:o + 4, o:o + 4] = base.h
+        eri[o:o + 4, o:o + 4, o:o + 4, o:o + 4] = base.eri
+    ints = W.Integrals(8, h, eri, 0.0)
+    fa, fb = W.full_space(4, 2, 2)
+    a = np.concatenate([fa, fa << np.uint64(4)])
+    b = np.concatenate([fb, fb << np.uint64(4)])
+    return ints, a, b
+
+
+@pytest.mark.parametrize("block,mixed", [(8, False), (1, False), (4, True)])
+def test_exactly_degenerate_ground_state(block, mixed):
+    ints, a, b = _two_copies()
+    log(f"degenerate ground state, {len(a)} dets, block {block}, mixed {mixed}")
+    s = solver_for(ints, a, b, 2, 2)
+    o = oracle_for(ints, a, b, 2, 2)
+    w = np.linalg.eigvalsh(o.dense())
+    assert abs(w[1] - w[0]) <= 1e-12 * abs(w[0])  # the construction is exact
+    e, c, st = s.lowest_eigenpair(tol=1e-9, block=block, mixed=mixed)
+    assert abs(e - w[0]) <= (1e-8 if mixed else 1e-10)
+    # the vector lies in the degenerate eigenspace: its residual is small
+    H = o.dense()
+    x = c.cpu().numpy()
+    assert np.linalg.norm(H @ x - e * x) <= 1e-7
+
+
+def test_batch_exactly_degenerate_instances():
+    ints, a, b = _two_copies()
+    w0 = np.linalg.eigvalsh(oracle_for(ints, a, b, 2, 2).dense())[0]
+    s = hq.Hinqs()
+    for _ in range(3):
+        s.batch_add(ints.h, ints.eri, ints.e_core, a, b, 2, 2)
+    e, c, info = s.batch_lowest_eigenpair(block=8, tol=1e-9)
+    assert all(int(x) == 0 for x in info["status"])
+    assert np.all(np.abs(np.asarray(e) - w0) <= 1e-10)
+
+
 def test_second_projection_pass_both_ways():
     """The second pass against the basis runs only when a new direction kept
     less than half its norm in the first; both outcomes reach the oracle."""
