@@ -312,3 +312,30 @@ def test_expand_and_pt2_large_orbital_counts(norb, na, nb):
     cb = np.concatenate([rb[pick], b[inb]])
     e0 = float(o.pt2(c, 0.0, a[:50], b[:50])[1].min()) - 0.5
     _check_pt2(s, o, c, e0, ca, cb)
+
+
+def test_expand_every_determinant_and_ntop_clamp():
+    """ntop = ndet (every determinant of a 300-determinant set expanded)
+    against the oracle, then the same call through the C ABI with ntop above
+    ndet: the library clamps it and returns the same list."""
+    import ctypes
+    ints, a, b, cfg = W.config_inputs(1, ndet=300)
+    log("expand all 300 determinants; ntop above ndet through the C ABI")
+    s = solver_for(ints, a, b, cfg.na, cfg.nb)
+    o = oracle_for(ints, a, b, cfg.na, cfg.nb)
+    c = _coeffs(len(a), 5)
+    ra, rb = _check_expand(s, o, c, len(a))
+    cd = torch.from_numpy(c).cuda()
+    ntop = len(a) + 100
+    cap = len(ra) + 1000
+    out_a = torch.empty(cap, dtype=torch.int64, device="cuda")
+    out_b = torch.empty(cap, dtype=torch.int64, device="cuda")
+    top = torch.full((ntop,), -1, dtype=torch.int32, device="cuda")
+    n = ctypes.c_int64(0)
+    rc = s._lib.hinqs_expand(s._h, s._ptr(cd), ntop, cap, s._ptr(out_a), s._ptr(out_b), ctypes.byref(n),
+                             s._ptr(top), 0)
+    torch.cuda.synchronize()
+    assert rc == 0 and n.value == len(ra)
+    assert np.array_equal(_strings(out_a[:n.value]), ra) and np.array_equal(_strings(out_b[:n.value]), rb)
+    t = top.cpu().numpy()
+    assert np.array_equal(np.sort(t[:len(a)]), np.arange(len(a))) and np.all(t[len(a):] == -1)
