@@ -620,3 +620,29 @@ def test_eigenpair_every_block_size(block, max_space, mixed):
     if w[1] - w[0] > 1e-6:
         assert abs(np.dot(c.cpu().numpy(), c_ref)) >= 1 - 1e-9
     assert st["restarts"] >= 1 or st["iterations"] * block < max_space
+
+
+def test_side_stream_and_interleaved_contexts():
+    """A context on a stream of its own solves to the same bits as one on the
+    default stream, and two contexts whose calls interleave on one GPU (each
+    with its own row counters) give the products each gives alone."""
+    ints, a, b, cfg = W.config_inputs(1, ndet=8000)
+    log("side stream and interleaved contexts, 8000 dets")
+    s0 = solver_for(ints, a, b, cfg.na, cfg.nb)
+    e0, c0, _ = s0.lowest_eigenpair(tol=1e-9)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        s1 = hq.Hinqs(stream=side)
+        s1.set_integrals(ints.h, ints.eri, ints.e_core)
+        s1.set_determinants(a, b, cfg.na, cfg.nb)
+        e1, c1, _ = s1.lowest_eigenpair(tol=1e-9)
+    side.synchronize()
+    assert e0 == e1 and torch.equal(c0, c1)
+    ints2, a2, b2, cfg2 = W.config_inputs(0)
+    s2 = solver_for(ints2, a2, b2, cfg2.na, cfg2.nb)
+    X0 = torch.from_numpy(W.random_block(len(a), 8, 61)).cuda()
+    X2 = torch.from_numpy(W.random_block(len(a2), 8, 62)).cuda()
+    ref0, ref2 = s0.sigma(X0), s2.sigma(X2)
+    for _ in range(3):
+        assert torch.equal(s0.sigma(X0), ref0)
+        assert torch.equal(s2.sigma(X2), ref2)
