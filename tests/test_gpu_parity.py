@@ -646,3 +646,35 @@ def test_side_stream_and_interleaved_contexts():
     for _ in range(3):
         assert torch.equal(s0.sigma(X0), ref0)
         assert torch.equal(s2.sigma(X2), ref2)
+
+
+def test_device_resident_determinants_match_host_input():
+    """hinqs_set_determinants_device (strings already in HBM, as the outer loop
+    hands them over) builds the same set as the host-array entry point:
+    couplings, diagonal and sigma bitwise equal; its validation reports the
+    same errors."""
+    ints, a, b, cfg = W.config_inputs(1, ndet=6000)
+    log("device-resident determinant input, 6000 dets")
+    sh = solver_for(ints, a, b, cfg.na, cfg.nb)
+    sd = hq.Hinqs()
+    sd.set_integrals(ints.h, ints.eri, ints.e_core)
+    da = torch.from_numpy(a.view(np.int64)).cuda()
+    db = torch.from_numpy(b.view(np.int64)).cuda()
+    sd.set_determinants(da, db, cfg.na, cfg.nb)
+    for x, y in zip(sd.connectivity(), sh.connectivity()):
+        assert torch.equal(x, y)
+    assert torch.equal(sd.diag(), sh.diag())
+    X = torch.from_numpy(W.random_block(len(a), 8, 71)).cuda()
+    assert torch.equal(sd.sigma(X), sh.sigma(X))
+    bad_a = da.clone()
+    bad_a[5] = bad_a[4]
+    bad_b = db.clone()
+    bad_b[5] = bad_b[4]
+    with pytest.raises(hq.HinqsError) as ei:
+        sd.set_determinants(bad_a, bad_b, cfg.na, cfg.nb)
+    assert ei.value.name == "DUPLICATE"
+    bad_a = da.clone()
+    bad_a[3] = bad_a[3] | (1 << 20)
+    with pytest.raises(hq.HinqsError) as ei:
+        sd.set_determinants(bad_a, db, cfg.na, cfg.nb)
+    assert ei.value.name == "BAD_OCCUPATION"
